@@ -1,0 +1,136 @@
+"""Parallel propose / evaluate / accept sweeps over colour classes of pixels.
+
+Sec. 3.4 parallelises the optimiser by mutating many pixels at once, keeping
+the mutated sets disjoint, evaluating the unmodified cost for each candidate
+and accepting improving moves as the sequential optimiser would; roughly a
+quarter of the pixels move concurrently.  Readings used here:
+  * mutation: the pixel's offset is redrawn from a counter-based Philox
+    stream at counter (p, sweep, problem, S_PROP), and its hit counts are
+    recomputed;
+  * disjoint sets: colour classes kappa = (y mod K) K + (x mod K), visited in
+    increasing kappa; K = 2 gives four classes (a quarter of the pixels each);
+  * snapshot semantics: every pixel of a class is evaluated against the
+    state at the start of its phase, then all accepted moves are committed;
+  * accept iff the energy change is strictly negative (no temperature).
+    Sec. 2 says the loss of Eq. (1) is reduced, yet lowering that sum makes
+    neighbouring error vectors alike, which moves error energy to low
+    frequencies, against the blue-noise goal of Sec. 3.3 and Fig. 1c.  The
+    default follows the text (descend); ``objective = -1`` accepts moves that
+    raise the sum instead (ascend), the only sign under which swapping pixels
+    lowers the blurred error.
+
+Decisions use the exact integer form of the energy change (energy module).
+
+Test infrastructure: this file is part of the CPU oracle.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import energy, estimator, integrands, philox
+
+
+@dataclass
+class Problem:
+    n: int
+    g: tuple
+    width: int
+    height: int
+    radius: int
+    sigma: float
+    colour_k: int
+    seed: int
+    problem_id: int
+    table: dict                       # Heaviside table (synthgen format)
+    objective: int = 1                # +1: accept dE < 0 (descend); -1: accept dE > 0
+
+    def __post_init__(self):
+        validate(self)
+        self.areas = integrands.heaviside_areas(self.table)
+
+
+def validate(p) -> None:
+    """Configuration checks (the library applies the same rules)."""
+    m = int(p.n).bit_length() - 1
+    if p.n < 1 or (1 << m) != p.n or m > 15:
+        raise ValueError("N must be a power of two in [1, 2**15]")
+    if any(int(v) % 2 == 0 for v in p.g) and p.n > 1:
+        raise ValueError("generator components must be odd (coprime to N)")
+    if p.colour_k < 1 or p.width % p.colour_k or p.height % p.colour_k:
+        raise ValueError("K must divide the tile width and height")
+    if p.radius < 1 or p.radius >= min(p.width, p.height):
+        raise ValueError("window radius must satisfy 1 <= r < min(W, H)")
+    if getattr(p, "objective", 1) not in (1, -1):
+        raise ValueError("objective must be +1 (descend) or -1 (ascend)")
+    if len(p.table["nx"]) < 1:
+        raise ValueError("at least one integrand is required")
+
+
+@dataclass
+class State:
+    u: np.ndarray            # int64 [H, W, 2]  (Q0.16 offsets)
+    c: np.ndarray            # int64 [H, W, T]  (hit counts)
+    sweep: int = 0
+    accepts: list = field(default_factory=list)   # per phase
+
+
+def initial_state(prob: Problem, u0: np.ndarray) -> State:
+    u = np.asarray(u0, dtype=np.int64).reshape(prob.height, prob.width, 2).copy()
+    c = estimator.hit_counts(prob.n, prob.g, u.reshape(-1, 2), prob.table)
+    return State(u=u, c=c.reshape(prob.height, prob.width, -1))
+
+
+def philox_offsets(prob: Problem) -> np.ndarray:
+    """Initial offsets from the counter stream S_INIT at counters (p, 0, problem, S_INIT)."""
+    w = philox.draw(np.arange(prob.width * prob.height), 0, prob.problem_id, philox.S_INIT, prob.seed)
+    return philox.q16_pair(w).reshape(prob.height, prob.width, 2)
+
+
+def class_pixels(width: int, height: int, k: int, kappa: int):
+    """(ys, xs) of colour class kappa in raster order."""
+    ys, xs = np.divmod(np.arange(width * height, dtype=np.int64), width)
+    sel = (ys % k) * k + (xs % k) == kappa
+    return ys[sel], xs[sel]
+
+
+def proposals(prob: Problem, ys, xs, sweep: int) -> np.ndarray:
+    """Candidate offsets of pixels (ys, xs) at a sweep: uint16 [M, 2]."""
+    p = np.asarray(ys, dtype=np.int64) * prob.width + np.asarray(xs, dtype=np.int64)
+    return philox.q16_pair(philox.draw(p, sweep, prob.problem_id, philox.S_PROP, prob.seed))
+
+
+def phase(prob: Problem, st: State, kappa: int) -> dict:
+    """One colour phase at sweep st.sweep; commits accepted moves into st."""
+    ys, xs = class_pixels(prob.width, prob.height, prob.colour_k, kappa)
+    u_new = proposals(prob, ys, xs, st.sweep).astype(np.int64)
+    c_new = estimator.hit_counts(prob.n, prob.g, u_new, prob.table)
+    xd = energy.delta_class_sums(st.c, ys, xs, c_new, prob.radius)
+    acc = energy.weighted_class_sum(xd, prob.radius, prob.sigma)
+    accept = (acc < 0.0) if prob.objective == 1 else (acc > 0.0)
+    st.u[ys[accept], xs[accept]] = u_new[accept]
+    st.c[ys[accept], xs[accept]] = c_new[accept]
+    return {"ys": ys, "xs": xs, "u_new": u_new, "c_new": c_new, "xd": xd,
+            "delta": acc * (2.0 / (prob.n * prob.n)), "accept": accept}
+
+
+def sweep(prob: Problem, st: State) -> None:
+    """All K^2 phases of one sweep, then advance the sweep index."""
+    for kappa in range(prob.colour_k ** 2):
+        st.accepts.append(int(phase(prob, st, kappa)["accept"].sum()))
+    st.sweep += 1
+
+
+def run(prob: Problem, st: State, k: int) -> State:
+    for _ in range(k):
+        sweep(prob, st)
+    return st
+
+
+def errors(prob: Problem, st: State) -> np.ndarray:
+    return estimator.errors_from_counts(st.c, prob.n, prob.areas)
+
+
+def energy_of(prob: Problem, st: State) -> float:
+    return energy.energy_exact(st.c, prob.n, prob.radius, prob.sigma)
