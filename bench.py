@@ -1,0 +1,170 @@
+"""Benchmark: pixel-updates/s of the lattice-offset optimiser sweep.
+
+One step = one sweep of the whole hot path (for every colour class:
+proposals + recount, energy change, commit) over a 256x256 tile with
+N = 256 samples per pixel, T = 1024 Heaviside integrands and a 9x9 window.
+Inputs are synthetic (seeded) and resident in HBM before the timed region.
+
+Prints one JSON line.  Per-kernel durations come from HIP events recorded on
+the problem's stream around every launch of the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synthgen  # noqa: E402
+
+METRIC = "pixel-updates/sec at 256² tile, T=1024, N=256; HBM GB/s vs peak; BF16 vs FP32"
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit vector lane-operations per second
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def cpu_baseline(w: dict, inp: dict, sweeps: int = 16, row_pixels: int = 128) -> dict:
+    """The oracle timed on a band of class-0 pixels (one class row) of the same
+    workload: proposals, recount, energy change and commit, repeated over
+    ``sweeps`` sweeps.  The window state of the band is computed first (not
+    timed)."""
+    from oracle import energy, estimator, sweep as osw
+
+    W, H, T, r = w["width"], w["height"], w["t_heaviside"], w["radius"]
+    ref = osw.Problem(n=w["n"], g=w["g"], width=W, height=H, radius=r, sigma=w["sigma"],
+                      colour_k=w["colour_k"], seed=w["seed"], problem_id=0, table=inp["heaviside"])
+    u0 = inp["offsets"].reshape(-1, 2).astype(np.int64)
+    c = np.zeros((H, W, T), dtype=np.int16)
+    rows = [(y + H) % H for y in range(-r, r + 1)]
+    for y in rows:
+        c[y] = estimator.hit_counts(w["n"], w["g"], u0[y * W:(y + 1) * W], inp["heaviside"])
+    xs = np.arange(0, W, w["colour_k"])[:row_pixels]
+    ys = np.zeros_like(xs)
+    t0 = time.perf_counter()
+    for s in range(sweeps):
+        u_new = osw.proposals(ref, ys, xs, s).astype(np.int64)
+        c_new = estimator.hit_counts(w["n"], w["g"], u_new, inp["heaviside"])
+        d = energy.weighted_class_sum(energy.delta_class_sums(c, ys, xs, c_new, r), r, w["sigma"])
+        acc = d < 0.0
+        c[ys[acc], xs[acc]] = c_new[acc]
+    dt = time.perf_counter() - t0
+    return {"value": sweeps * len(xs) / dt, "unit": "pixel-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} sweeps x {len(xs)} class-0 pixels of one row (recount N*T predicates "
+                      f"+ exact energy change + commit), numpy FP64/int64 oracle, single thread",
+            "seconds": dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="tile256_n256_t1024")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the optimiser's batched "
+                                   "and multi-tile sharding is not built for several GPUs", "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+    from paper_2105_12620_amd import bnlat
+
+    torch.cuda.set_device(0)
+    w = dict(synthgen.WORKLOADS[args.workload])
+    inp = synthgen.problem_inputs(w)
+    stream = torch.cuda.Stream()
+    prob = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]), stream=stream.cuda_stream)
+    prob.init_offsets(inp["offsets"])
+    prob.compute_errors()
+    K2 = w["colour_k"] ** 2
+    P, T, N, M = w["width"] * w["height"], w["t_heaviside"], w["n"], prob.M
+
+    def staged_sweep(events):
+        for kappa in range(K2):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if events is not None else None
+            if e: e[0].record(stream)
+            prob.phase_propose(kappa)
+            if e: e[1].record(stream)
+            prob.phase_evaluate(kappa)
+            if e: e[2].record(stream)
+            prob.phase_commit(kappa)
+            if e:
+                e[3].record(stream)
+                events.append(e)
+        prob.phase_advance()
+
+    for _ in range(args.warmup):
+        staged_sweep(None)
+    torch.cuda.synchronize()
+
+    # timed region: K sweeps, every launch bracketed by events on the problem stream
+    events = []
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        staged_sweep(events)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    k_ms = {"count": [], "delta": [], "commit": []}
+    for e in events:
+        k_ms["count"].append(e[0].elapsed_time(e[1]))
+        k_ms["delta"].append(e[1].elapsed_time(e[2]))
+        k_ms["commit"].append(e[2].elapsed_time(e[3]))
+    avg = {k: float(np.mean(v)) for k, v in k_ms.items()}
+
+    # graph-replayed sweeps (bn_sweep) over the same number of steps
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    prob.sweep(1)
+    torch.cuda.synchronize()
+    g0.record(stream)
+    prob.sweep(args.steps)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = g0.elapsed_time(g1)
+
+    # algorithmic work per launch
+    count_ops = 2.0 * M * N * T                       # v_dot2 + compare per (sample, integrand)
+    count_tops = count_ops / (avg["count"] * 1e-3) / 1e12
+    win = (2 * w["radius"] + 1) ** 2 - 1
+    # energy change: read the moved pixel's old and new rows and its window
+    # once per phase (the tile, 2 B per count), write M decisions
+    delta_bytes = 2.0 * T * (P + M) + 9.0 * M
+    commit_bytes = 0.0
+    value = P * args.steps / (total_ms * 1e-3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "pixel-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "tile": f"{w['width']}x{w['height']}", "n": N, "t": T,
+                   "window": f"{2 * w['radius'] + 1}x{2 * w['radius'] + 1}", "colour_classes": K2,
+                   "precision": "fp32", "mutation": "redraw"},
+        "roofline": {"bound": "alu", "kernel": "k_count_points (proposal recount)",
+                     "achieved": count_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": count_tops / VALU_PEAK_TOPS, "traffic": None,
+                     "work_per_launch": f"{M} pixels x {N} samples x {T} integrands x 2 lane-ops"},
+        "kernels_ms": avg,
+        "delta_hbm_gbs": delta_bytes / (avg["delta"] * 1e-3) / 1e9,
+        "delta_hbm_frac": delta_bytes / (avg["delta"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "graph_value": P * args.steps / (graph_ms * 1e-3),
+        "window_offsets": win,
+    }
+    prob.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, inp)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

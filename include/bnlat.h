@@ -1,0 +1,218 @@
+/*
+ * bnlat.h -- C ABI of the MI355X (gfx950) screen-space lattice-offset optimiser.
+ *
+ * The method (Belcour & Heitz, "Lessons Learned and Improvements when
+ * Building Screen-Space Samplers with Blue-Noise Error Distribution",
+ * SIGGRAPH 2021 Talks):
+ *   - Sec. 2: a screen-space sampler is a main sequence plus a tile of
+ *     per-pixel scrambling parameters u_p; the tile is optimised so that the
+ *     pixels' Monte Carlo errors on random test integrands minimise the
+ *     Gaussian-windowed energy of Eq. (1);
+ *   - Sec. 3.2: main sequence = 2D rank-1 lattice s^k = mod(Phi(k) g / N, 1),
+ *     scrambled per pixel by the toroidal shift mod(s^k + u_p, 1) (Fig. 1a);
+ *   - Sec. 3.3: a sampler is judged by the RMSE of its error tile after
+ *     Gaussian blurs of several sizes (Fig. 1c);
+ *   - Sec. 3.4: the optimiser mutates disjoint pixel sets in parallel.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: bn_status; BN_OK (0) on success, a negative code on
+ *     failure.  On failure bn_last_error() holds a message (thread local) and
+ *     the problem keeps its previous state unless stated otherwise.
+ *   - Fixed point: offsets and sample coordinates are Q0.16 (uint16 v means
+ *     v / 65536); the modulo-one wrap is uint16 wrap-around.  N = 2^m must
+ *     divide 65536.
+ *   - Memory: the library allocates and owns every device buffer of a
+ *     problem (created in bn_create_problem, freed in bn_destroy_problem).
+ *     Every pointer argument named host_* or out is caller-owned host
+ *     memory of the size stated; the library never keeps it.
+ *   - Streams: all device work of a problem is ordered on its HIP stream
+ *     (given at creation, or created by the library).  Entry points that
+ *     return data to host memory synchronise that stream first.
+ *   - Thread safety: a problem (or batch) may be used by one host thread at a
+ *     time; distinct problems may be used concurrently.
+ *   - The library has no CPU fallback: without a usable gfx950 device every
+ *     entry point that needs one returns BN_EHIP.
+ */
+#ifndef BNLAT_H
+#define BNLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bn_problem_s* bn_problem;
+typedef struct bn_batch_s* bn_batch;
+
+typedef enum {
+  BN_OK = 0,
+  BN_EINVAL = -1,       /* invalid argument or configuration                  */
+  BN_ENOMEM = -2,       /* device or host allocation failed                   */
+  BN_EHIP = -3,         /* HIP runtime error (no device, launch failure, ...) */
+  BN_ESTATE = -4,       /* call out of order (e.g. sweep before errors)       */
+  BN_EUNSUPPORTED = -5, /* valid request this build does not implement        */
+  BN_ENUMERIC = -6      /* non-finite or out-of-range numeric result          */
+} bn_status;
+
+/* Arithmetic of the energy-change evaluation (the neighbourhood Gram part).
+ * BN_FP32: integer hit counts and FP32 error vectors on the vector ALUs.
+ * BN_BF16: centred hit counts (c - N/2) in BF16 on the matrix cores with
+ *          FP32 accumulation (exact when N <= 256 and T (N/2)^2 <= 2^24);
+ *          accepted moves are re-checked with the exact integer form.      */
+typedef enum { BN_FP32 = 0, BN_BF16 = 1 } bn_precision;
+
+/* Mutation.  BN_REDRAW: the pixel's offset is redrawn from the Philox
+ * stream and its hit counts recomputed (Sec. 3.4 run with random offset
+ * proposals).  BN_SWAP (pixel-pair swaps, Sec. 2 and Sec. 3.4) is reserved. */
+typedef enum { BN_REDRAW = 0, BN_SWAP = 1 } bn_move;
+
+/* Problem description (Eq. (1) window, Sec. 3.2 lattice, Sec. 3.4 classes). */
+typedef struct {
+  uint32_t n;            /* samples per pixel N = 2^m, 1 <= N <= 32768           */
+  uint32_t g[2];         /* lattice generator; each component odd (coprime to N) */
+  uint32_t width;        /* toroidal tile width W  (multiple of colour_k)        */
+  uint32_t height;       /* toroidal tile height H (multiple of colour_k)        */
+  uint32_t t_heaviside;  /* number T of Heaviside test integrands, >= 1          */
+  uint32_t t_gauss;      /* number of Gaussian integrands (must be 0 here)       */
+  double sigma;          /* energy weight w_o = exp(-|o|^2 / sigma^2), > 0       */
+  uint32_t radius;       /* window offsets o in [-r, r]^2 \ {0}; 1 <= r < min(W,H), r <= 8 */
+  uint32_t colour_k;     /* colour modulus K: K*K classes (y mod K) K + (x mod K) */
+  int32_t objective;     /* +1: accept dE < 0 (descend Eq. (1)); -1: accept dE > 0 */
+  uint64_t seed;         /* Philox key (low, high 32 bits)                       */
+  uint32_t problem_id;   /* third Philox counter word; batch member index        */
+  bn_precision precision;
+  bn_move move;
+} bn_config;
+
+/* One Heaviside test integrand (Sec. 2): f(x) = 1 iff n . (x - c/65536) > 0
+ * (edge excluded); n is an int16 normal of length about 2^14, c a Q0.16
+ * point on the edge.  8 bytes, no padding. */
+typedef struct {
+  int16_t nx, ny;
+  uint16_t cx, cy;
+} bn_heaviside;
+
+typedef struct {
+  uint64_t proposals;    /* pixel proposals evaluated                          */
+  uint64_t accepts;      /* proposals committed                                */
+  uint64_t bf16_vetoes;  /* BF16 accepts rejected by the exact re-check        */
+  uint64_t sweep_index;  /* sweep index after the call                         */
+} bn_sweep_stats;
+
+/* ---------------------------------------------------------------- lifecycle */
+
+/* Create a problem.  cfg is validated before any device work (rules above).
+ * heavisides: host array [cfg->t_heaviside], or NULL to draw them from the
+ *   Philox stream (counter (t, 0, problem_id, 0xB): angle 2 pi w0 2^-32,
+ *   normal = round-half-even(2^14 (cos, sin)), edge point (w1>>16, w2>>16)).
+ * stream: hipStream_t to order all work on, or NULL to let the library create
+ *   (and later destroy) a non-blocking stream.
+ * The exact integral of each Heaviside (area of the unit square on the hit
+ * side) is computed on the host in FP64.  *out receives the handle. */
+bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides,
+                            void* stream, bn_problem* out);
+bn_status bn_destroy_problem(bn_problem p);
+
+/* Set the offset tile U = {u_p} (Sec. 2).  host_u: uint16 [H][W][2] (x then y), or
+ * NULL for Philox offsets (counter (p, 0, problem_id, 0xA), p = y W + x,
+ * u = (w0 >> 16, w1 >> 16)).  Invalidates hit counts and errors. */
+bn_status bn_init_offsets(bn_problem p, const uint16_t* host_u);
+
+/* Hit counts c[p][t] = #{k : f_t(s_p^k) = 1} and error vectors
+ * e[p][t] = c/N - A_t (FP32) of every pixel (Sec. 2, estimator of the test
+ * integrand map).  Requires offsets. */
+bn_status bn_compute_errors(bn_problem p);
+
+/* Run k sweeps of the parallel optimiser (Sec. 3.4).  One sweep visits the
+ * K*K colour classes in increasing order; for every pixel of a class it
+ * draws a proposal (counter (p, sweep, problem_id, 0xC)), recounts its hits,
+ * evaluates the energy change of Eq. (1) against the state at the start of
+ * the phase and commits the accepted moves; then the sweep index advances.
+ * stats (nullable) receives totals over the k sweeps (synchronises).
+ * Returns BN_ESTATE before bn_compute_errors. */
+bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats);
+
+/* Energy of Eq. (1) over the window, both orderings of each pair:
+ * E = sum_p sum_o w_o |e_p - e_{p+o}|^2, evaluated exactly in integers per
+ * distance class and combined in FP64.  Synchronises. */
+bn_status bn_energy(bn_problem p, double* out);
+
+/* Blur criterion of Sec. 3.3 / Fig. 1c: for each sigmas[i] > 0,
+ * out[i] = sqrt(mean_{p,t} ((k_sigma * e_t)(p))^2) with k_sigma the
+ * normalised Gaussian of standard deviation sigma periodised on the torus,
+ * applied separably.  n <= 64.  Synchronises. */
+bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, double* out);
+
+/* Copy the offset tile to host_u: uint16 [H][W][2].  Synchronises. */
+bn_status bn_get_offsets(bn_problem p, uint16_t* host_u);
+
+/* ------------------------------------------------------- inspection / parity */
+
+/* host: uint16 [H*W][T] hit counts.  Requires bn_compute_errors. */
+bn_status bn_get_counts(bn_problem p, uint16_t* host);
+/* host: float [H*W][T] error vectors.  Requires bn_compute_errors. */
+bn_status bn_get_errors(bn_problem p, float* host);
+/* Integrand table as used (heavisides [T], nullable) and the FP64 exact
+ * integrals (areas [T], nullable). */
+bn_status bn_get_integrands(bn_problem p, bn_heaviside* heavisides, double* areas);
+/* The N scrambled samples of one pixel in van der Corput order k = 0..N-1,
+ * computed on the device: host uint16 [N][2].  Synchronises. */
+bn_status bn_get_points(bn_problem p, uint32_t pixel, uint16_t* host);
+/* Energy change of moving pixels[j] (raster index y W + x, distinct) to
+ * offset proposals[j] (uint16 [m][2]) against the current state, each
+ * evaluated alone; no state change.  out_de: double [m]; out_counts
+ * (nullable): uint16 [m][T] recounted hits.  m <= H*W.  Synchronises. */
+bn_status bn_delta_energy(bn_problem p, const uint32_t* pixels, const uint16_t* proposals,
+                          uint32_t m, double* out_de, uint16_t* out_counts);
+bn_status bn_get_sweep_index(bn_problem p, uint64_t* out);
+bn_status bn_set_sweep_index(bn_problem p, uint64_t sweep);
+
+/* The three steps of one colour phase kappa < K*K at the current sweep
+ * index, as bn_sweep runs them: propose + recount, evaluate, commit.
+ * bn_phase_advance moves the sweep index on by one (device and host).
+ * bn_get_phase copies the last phase's per-pixel results (class order is
+ * raster order of the class pixels); every pointer is nullable:
+ * u_new uint16 [M][2], c_new uint16 [M][T], delta double [M], accept uint8 [M],
+ * with M = H*W / (K*K). */
+bn_status bn_phase_propose(bn_problem p, uint32_t kappa);
+bn_status bn_phase_evaluate(bn_problem p, uint32_t kappa);
+bn_status bn_phase_commit(bn_problem p, uint32_t kappa);
+bn_status bn_phase_advance(bn_problem p);
+bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* delta,
+                       uint8_t* accept);
+
+/* ----------------------------------------------------------------- batching */
+
+/* Independent problems (e.g. the dimension pairs of a padded sampler,
+ * Sec. 3.1) swept together: each colour step of every member runs in one
+ * launch per kernel, and k sweeps are replayed from one captured HIP graph.
+ * All members must share one stream.  tune_cache (nullable) names a file
+ * holding the launch choices of the tuner.  Members stay owned by the caller
+ * and must outlive the batch. */
+bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tune_cache,
+                          bn_batch* out);
+bn_status bn_batch_sweep(bn_batch b, uint32_t k);
+bn_status bn_destroy_batch(bn_batch b);
+
+/* ------------------------------------------------ host-only (no device work) */
+
+bn_status bn_validate_config(const bn_config* cfg);
+/* Distinct squared distances d of the window offsets in increasing order and
+ * their weights exp(-d / sigma^2) (FP64): class_d uint32 [*n_classes],
+ * class_w double [*n_classes]; pass NULL arrays to query the count. */
+bn_status bn_window_classes(const bn_config* cfg, uint32_t* n_classes, uint32_t* class_d,
+                            double* class_w);
+/* Exact area (FP64) of the unit square on the hit side of one Heaviside. */
+bn_status bn_heaviside_area(const bn_heaviside* h, double* out);
+/* The Philox-drawn Heavisides bn_create_problem uses when given NULL. */
+bn_status bn_draw_heavisides(uint64_t seed, uint32_t problem_id, uint32_t t, bn_heaviside* out);
+
+const char* bn_status_string(bn_status s);
+const char* bn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BNLAT_H */

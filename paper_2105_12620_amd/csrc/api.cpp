@@ -1,0 +1,752 @@
+// C-ABI of the lattice-offset optimiser: validation, host tables, device
+// buffers, stream-ordered launches and graph-captured sweeps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bnlat.h"
+#include "bnlat_dev.h"
+
+using namespace bnlat;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bn_status fail(bn_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(BN_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+uint32_t round_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
+
+bool is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
+
+// ------------------------------------------------------------------ Philox
+// Host Philox4x32-10 (Salmon et al., SC 2011) for drawing integrands.
+void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = (uint32_t)p1;
+    c[2] = n2;
+    c[3] = (uint32_t)p0;
+  }
+}
+
+// ------------------------------------------------------ Heaviside integrals
+// Area of {x in [0,1]^2 : a x + b y >= k}: walk the square's boundary, keep
+// the corners on the hit side and the points where the edge crosses the
+// line, then take the polygon's shoelace area.
+double half_plane_area(double a, double b, double k) {
+  static const double cx[4] = {0.0, 1.0, 1.0, 0.0};
+  static const double cy[4] = {0.0, 0.0, 1.0, 1.0};
+  double px[8], py[8];
+  int m = 0;
+  for (int i = 0; i < 4; ++i) {
+    const int j = (i + 1) & 3;
+    const double fi = a * cx[i] + b * cy[i] - k;
+    const double fj = a * cx[j] + b * cy[j] - k;
+    if (fi >= 0.0) {
+      px[m] = cx[i];
+      py[m] = cy[i];
+      ++m;
+    }
+    if ((fi >= 0.0) != (fj >= 0.0)) {
+      const double s = fi / (fi - fj);
+      px[m] = cx[i] + s * (cx[j] - cx[i]);
+      py[m] = cy[i] + s * (cy[j] - cy[i]);
+      ++m;
+    }
+  }
+  if (m < 3) return 0.0;
+  double twice = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const int j = (i + 1) % m;
+    twice += px[i] * py[j] - px[j] * py[i];
+  }
+  return std::fabs(twice) * 0.5;
+}
+
+bn_status heaviside_area_checked(const bn_heaviside& h, double* out) {
+  if (h.nx == 0 && h.ny == 0) return fail(BN_EINVAL, "Heaviside normal is (0, 0)");
+  if (h.nx < -16384 || h.nx > 16384 || h.ny < -16384 || h.ny > 16384)
+    return fail(BN_EINVAL, "Heaviside normal components must lie in [-16384, 16384]");
+  const double k = ((double)h.nx * h.cx + (double)h.ny * h.cy) / 65536.0;
+  *out = half_plane_area((double)h.nx, (double)h.ny, k);
+  return BN_OK;
+}
+
+// ---------------------------------------------------------------- windows
+void window_classes(uint32_t r, double sigma, std::vector<uint32_t>& d, std::vector<double>& w) {
+  d.clear();
+  w.clear();
+  for (uint32_t dd = 1; dd <= 2 * r * r; ++dd) {
+    bool found = false;
+    for (int y = -(int)r; y <= (int)r && !found; ++y)
+      for (int x = -(int)r; x <= (int)r && !found; ++x)
+        if ((uint32_t)(x * x + y * y) == dd) found = true;
+    if (found) {
+      d.push_back(dd);
+      w.push_back(std::exp(-(double)dd / (sigma * sigma)));
+    }
+  }
+}
+
+// Periodised, normalised Gaussian of standard deviation s on a ring of n
+// pixels; returns the taps above a negligible relative level.
+void blur_taps(uint32_t n, double s, std::vector<float>& k, std::vector<int32_t>& d) {
+  std::vector<double> kd(n, 0.0);
+  const int reps = (int)std::ceil(6.0 * s / n) + 1;
+  double total = 0.0, kmax = 0.0;
+  for (uint32_t i = 0; i < n; ++i) {
+    for (int m = -reps; m <= reps; ++m) {
+      const double z = (double)i + (double)m * n;
+      kd[i] += std::exp(-(z * z) / (2.0 * s * s));
+    }
+    total += kd[i];
+  }
+  for (uint32_t i = 0; i < n; ++i) kmax = std::max(kmax, kd[i]);
+  k.clear();
+  d.clear();
+  for (uint32_t i = 0; i < n; ++i)
+    if (kd[i] > 1e-12 * kmax) {
+      k.push_back((float)(kd[i] / total));
+      d.push_back((int32_t)i);
+    }
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- the handle
+struct bn_problem_s {
+  bn_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevView v{};
+  std::vector<bn_heaviside> heav;
+  std::vector<double> area64;
+  std::vector<uint32_t> cls_d;
+  std::vector<double> cls_w;
+  std::vector<void*> allocs;
+  uint32_t list_cap = 0;
+  uint16_t* list_cnt = nullptr;
+  uint32_t* list_u = nullptr;
+  uint32_t* list_pix = nullptr;
+  double* list_delta = nullptr;
+  uint8_t* list_accept = nullptr;
+  unsigned long long* ysum = nullptr;
+  uint64_t sweep = 0;
+  bool have_offsets = false;
+  bool have_counts = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool graph_failed = false;
+
+  template <class T>
+  bn_status alloc(T** ptr, size_t count) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BN_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+    }
+    allocs.push_back(p);
+    *ptr = (T*)p;
+    return BN_OK;
+  }
+  ~bn_problem_s() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : allocs) (void)hipFree(p);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+struct bn_batch_s {
+  std::vector<bn_problem> members;
+};
+
+namespace {
+
+bn_status validate(const bn_config* c) {
+  if (!c) return fail(BN_EINVAL, "config is NULL");
+  if (!is_pow2(c->n) || c->n > 32768) return fail(BN_EINVAL, "N=%u must be a power of two in [1, 32768]", c->n);
+  if (c->n > 1 && (!(c->g[0] & 1) || !(c->g[1] & 1)))
+    return fail(BN_EINVAL, "generator components must be odd (coprime to N)");
+  if (c->colour_k < 1 || c->width % c->colour_k || c->height % c->colour_k)
+    return fail(BN_EINVAL, "colour_k=%u must divide width and height", c->colour_k);
+  if (c->width < 2 || c->height < 2) return fail(BN_EINVAL, "tile must be at least 2x2");
+  if (c->radius < 1 || c->radius >= std::min(c->width, c->height))
+    return fail(BN_EINVAL, "radius must satisfy 1 <= r < min(W, H)");
+  if (c->radius > MAX_RADIUS) return fail(BN_EINVAL, "radius must be <= %u", MAX_RADIUS);
+  if (c->t_heaviside + c->t_gauss < 1) return fail(BN_EINVAL, "at least one integrand is required");
+  if (!(c->sigma > 0.0) || !std::isfinite(c->sigma)) return fail(BN_EINVAL, "sigma must be finite and > 0");
+  if (c->objective != 1 && c->objective != -1) return fail(BN_EINVAL, "objective must be +1 or -1");
+  if (c->precision != BN_FP32 && c->precision != BN_BF16) return fail(BN_EINVAL, "unknown precision");
+  if (c->move != BN_REDRAW && c->move != BN_SWAP) return fail(BN_EINVAL, "unknown move");
+  if ((uint64_t)c->width * c->height > (1u << 26)) return fail(BN_EINVAL, "tile larger than 2^26 pixels");
+  if (c->t_heaviside > (1u << 16)) return fail(BN_EINVAL, "more than 65536 integrands");
+  return BN_OK;
+}
+
+bn_status supported(const bn_config* c) {
+  if (c->n > MAX_N) return fail(BN_EUNSUPPORTED, "N > %u is not supported by this build", MAX_N);
+  if (c->radius > 6) return fail(BN_EUNSUPPORTED, "radius > 6 is not supported by this build");
+  if (c->t_gauss) return fail(BN_EUNSUPPORTED, "Gaussian integrands are not supported by this build");
+  if (c->precision != BN_FP32) return fail(BN_EUNSUPPORTED, "BF16 precision is not supported by this build");
+  if (c->move != BN_REDRAW) return fail(BN_EUNSUPPORTED, "swap moves are not supported by this build");
+  return BN_OK;
+}
+
+bn_status check_device() {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    return fail(BN_EHIP, "no HIP device available");
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(BN_EHIP, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+  return BN_OK;
+}
+
+bn_status sync(bn_problem p) {
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return BN_OK;
+}
+
+bn_status ensure_list(bn_problem p, uint32_t m) {
+  if (m <= p->list_cap) return BN_OK;
+  bn_status s;
+  if ((s = p->alloc(&p->list_cnt, (size_t)m * p->v.tp)) != BN_OK) return s;
+  if ((s = p->alloc(&p->list_u, m)) != BN_OK) return s;
+  if ((s = p->alloc(&p->list_pix, m)) != BN_OK) return s;
+  if ((s = p->alloc(&p->list_delta, m)) != BN_OK) return s;
+  if ((s = p->alloc(&p->list_accept, m)) != BN_OK) return s;
+  p->list_cap = m;
+  return BN_OK;
+}
+
+bn_status record_sweep(bn_problem p) {
+  for (uint32_t kappa = 0; kappa < p->cfg.colour_k * p->cfg.colour_k; ++kappa) {
+    HIPCHK(launch_count(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
+    HIPCHK(launch_delta(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
+    HIPCHK(launch_commit(p->v, kappa, p->stream));
+  }
+  HIPCHK(launch_advance(p->v, p->stream));
+  return BN_OK;
+}
+
+bn_status build_graph(bn_problem p) {
+  if (p->graph_exec || p->graph_failed) return BN_OK;
+  if (p->stream == nullptr) {
+    p->graph_failed = true;
+    return BN_OK;
+  }
+  HIPCHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+  bn_status s = record_sweep(p);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->stream, &g);
+  if (s != BN_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p->graph_failed = true;
+    return BN_OK;
+  }
+  e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g);
+    p->graph_exec = nullptr;
+    p->graph_failed = true;
+    return BN_OK;
+  }
+  p->graph = g;
+  return BN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bn_status_string(bn_status s) {
+  switch (s) {
+    case BN_OK: return "ok";
+    case BN_EINVAL: return "invalid argument";
+    case BN_ENOMEM: return "out of memory";
+    case BN_EHIP: return "HIP runtime error";
+    case BN_ESTATE: return "call out of order";
+    case BN_EUNSUPPORTED: return "unsupported";
+    case BN_ENUMERIC: return "numeric error";
+  }
+  return "unknown status";
+}
+
+const char* bn_last_error(void) { return g_last_error.c_str(); }
+
+bn_status bn_validate_config(const bn_config* cfg) { return validate(cfg); }
+
+bn_status bn_window_classes(const bn_config* cfg, uint32_t* n_classes, uint32_t* class_d, double* class_w) {
+  bn_status s = validate(cfg);
+  if (s != BN_OK) return s;
+  if (!n_classes) return fail(BN_EINVAL, "n_classes is NULL");
+  std::vector<uint32_t> d;
+  std::vector<double> w;
+  window_classes(cfg->radius, cfg->sigma, d, w);
+  if ((class_d || class_w) && *n_classes < d.size())
+    return fail(BN_EINVAL, "arrays hold %u entries, %zu needed", *n_classes, d.size());
+  *n_classes = (uint32_t)d.size();
+  for (size_t i = 0; i < d.size(); ++i) {
+    if (class_d) class_d[i] = d[i];
+    if (class_w) class_w[i] = w[i];
+  }
+  return BN_OK;
+}
+
+bn_status bn_heaviside_area(const bn_heaviside* h, double* out) {
+  if (!h || !out) return fail(BN_EINVAL, "NULL argument");
+  return heaviside_area_checked(*h, out);
+}
+
+bn_status bn_draw_heavisides(uint64_t seed, uint32_t problem_id, uint32_t t, bn_heaviside* out) {
+  if (!out && t) return fail(BN_EINVAL, "out is NULL");
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (uint32_t i = 0; i < t; ++i) {
+    uint32_t c[4] = {i, 0u, problem_id, S_INTEG};
+    philox10(c, k0, k1);
+    const double theta = 2.0 * M_PI * (double)c[0] * 0x1p-32;
+    out[i].nx = (int16_t)std::nearbyint(16384.0 * std::cos(theta));
+    out[i].ny = (int16_t)std::nearbyint(16384.0 * std::sin(theta));
+    out[i].cx = (uint16_t)(c[1] >> 16);
+    out[i].cy = (uint16_t)(c[2] >> 16);
+  }
+  return BN_OK;
+}
+
+bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides, void* stream,
+                            bn_problem* out) {
+  bn_status s = validate(cfg);
+  if (s != BN_OK) return s;
+  if (!out) return fail(BN_EINVAL, "out is NULL");
+  if ((s = supported(cfg)) != BN_OK) return s;
+  *out = nullptr;
+
+  // Host tables first: every input is checked before the device is touched.
+  std::vector<bn_heaviside> heav(cfg->t_heaviside);
+  if (heavisides)
+    std::copy(heavisides, heavisides + cfg->t_heaviside, heav.begin());
+  else if ((s = bn_draw_heavisides(cfg->seed, cfg->problem_id, cfg->t_heaviside, heav.data())) != BN_OK)
+    return s;
+  std::vector<double> area(cfg->t_heaviside);
+  for (uint32_t t = 0; t < cfg->t_heaviside; ++t)
+    if ((s = heaviside_area_checked(heav[t], &area[t])) != BN_OK)
+      return fail(s, "integrand %u: %s", t, g_last_error.c_str());
+
+  if ((s = check_device()) != BN_OK) return s;
+
+  bn_problem p = new bn_problem_s();
+  p->cfg = *cfg;
+  p->heav = heav;
+  p->area64 = area;
+  window_classes(cfg->radius, cfg->sigma, p->cls_d, p->cls_w);
+  if (stream) {
+    p->stream = (hipStream_t)stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(BN_EHIP, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
+    }
+    p->own_stream = true;
+  }
+
+  DevView& v = p->v;
+  v.n = cfg->n;
+  v.log2n = 0;
+  while ((1u << v.log2n) < cfg->n) ++v.log2n;
+  v.w = cfg->width;
+  v.h = cfg->height;
+  v.t = cfg->t_heaviside;
+  v.tp = round_up(v.t, T_ALIGN);
+  v.k = cfg->colour_k;
+  v.cw = cfg->width / cfg->colour_k;
+  v.ch = cfg->height / cfg->colour_k;
+  v.pc = v.cw * v.ch;
+  v.problem = cfg->problem_id;
+  v.seed_lo = (uint32_t)cfg->seed;
+  v.seed_hi = (uint32_t)(cfg->seed >> 32);
+  v.objective = cfg->objective;
+  v.radius = cfg->radius;
+  v.ncls = (uint32_t)p->cls_d.size();
+  const size_t P = (size_t)v.w * v.h;
+
+  std::vector<uint32_t> lat(v.n);
+  const uint32_t step = 65536u / v.n;
+  for (uint32_t i = 0; i < v.n; ++i) {
+    const uint32_t jx = (uint32_t)(((uint64_t)i * cfg->g[0]) % v.n);
+    const uint32_t jy = (uint32_t)(((uint64_t)i * cfg->g[1]) % v.n);
+    lat[i] = ((jx * step) & 0xFFFFu) | (((jy * step) & 0xFFFFu) << 16);
+  }
+  std::vector<int2> ihp(v.tp, make_int2(0, 0));
+  std::vector<float> areaf(v.tp, 0.0f);
+  for (uint32_t t = 0; t < v.t; ++t) {
+    const bn_heaviside& h = heav[t];
+    ihp[t].x = (int)(((uint32_t)(uint16_t)h.nx) | ((uint32_t)(uint16_t)h.ny << 16));
+    ihp[t].y = (int)h.nx * ((int)h.cx - 32768) + (int)h.ny * ((int)h.cy - 32768);
+    areaf[t] = (float)area[t];
+  }
+
+  uint32_t* lat_d;
+  int2* ihp_d;
+  float* area_d;
+  double* wd_d;
+  if ((s = p->alloc(&lat_d, v.n)) != BN_OK || (s = p->alloc(&ihp_d, v.tp)) != BN_OK ||
+      (s = p->alloc(&area_d, v.tp)) != BN_OK || (s = p->alloc(&wd_d, v.ncls)) != BN_OK ||
+      (s = p->alloc(&v.U, P)) != BN_OK || (s = p->alloc(&v.cnt, P * v.tp)) != BN_OK ||
+      (s = p->alloc(&v.err, P * v.tp)) != BN_OK || (s = p->alloc(&v.u_new, v.pc)) != BN_OK ||
+      (s = p->alloc(&v.c_new, (size_t)v.pc * v.tp)) != BN_OK || (s = p->alloc(&v.delta, v.pc)) != BN_OK ||
+      (s = p->alloc(&v.accept, v.pc)) != BN_OK || (s = p->alloc(&v.ctr, 2)) != BN_OK ||
+      (s = p->alloc(&p->ysum, v.ncls)) != BN_OK) {
+    delete p;
+    return s;
+  }
+  v.lat = lat_d;
+  v.ihp = ihp_d;
+  v.area = area_d;
+  v.wd = wd_d;
+  v.pix_list = nullptr;
+  const unsigned long long zero[2] = {0ull, 0ull};
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpyAsync(lat_d, lat.data(), v.n * 4, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(ihp_d, ihp.data(), v.tp * 8, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(area_d, areaf.data(), v.tp * 4, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(wd_d, p->cls_w.data(), v.ncls * 8, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(v.ctr, zero, sizeof zero, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(BN_EHIP, "uploading tables: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return BN_OK;
+}
+
+bn_status bn_destroy_problem(bn_problem p) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  delete p;
+  return BN_OK;
+}
+
+bn_status bn_init_offsets(bn_problem p, const uint16_t* host_u) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  const size_t P = (size_t)p->v.w * p->v.h;
+  if (host_u) {
+    HIPCHK(hipMemcpyAsync(p->v.U, host_u, P * 4, hipMemcpyHostToDevice, p->stream));
+    bn_status s = sync(p);  // the caller may reuse host_u as soon as we return
+    if (s != BN_OK) return s;
+  } else {
+    HIPCHK(launch_init_offsets(p->v, p->stream));
+  }
+  p->have_offsets = true;
+  p->have_counts = false;
+  return BN_OK;
+}
+
+bn_status bn_compute_errors(bn_problem p) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  if (!p->have_offsets) return fail(BN_ESTATE, "offsets are not initialised");
+  HIPCHK(launch_count(p->v, MODE_ALL, 0, p->v.w * p->v.h, p->stream));
+  p->have_counts = true;
+  return BN_OK;
+}
+
+bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run before bn_sweep");
+  unsigned long long before[2] = {0, 0}, after[2] = {0, 0};
+  if (stats) {
+    HIPCHK(hipMemcpyAsync(before, p->v.ctr, sizeof before, hipMemcpyDeviceToHost, p->stream));
+    bn_status s = sync(p);
+    if (s != BN_OK) return s;
+  }
+  bn_status s = build_graph(p);
+  if (s != BN_OK) return s;
+  for (uint32_t i = 0; i < k; ++i) {
+    if (p->graph_exec) {
+      HIPCHK(hipGraphLaunch(p->graph_exec, p->stream));
+    } else if ((s = record_sweep(p)) != BN_OK) {
+      return s;
+    }
+  }
+  p->sweep += k;
+  if (stats) {
+    HIPCHK(hipMemcpyAsync(after, p->v.ctr, sizeof after, hipMemcpyDeviceToHost, p->stream));
+    if ((s = sync(p)) != BN_OK) return s;
+    stats->proposals = (uint64_t)k * p->v.w * p->v.h;
+    stats->accepts = after[1] - before[1];
+    stats->bf16_vetoes = 0;
+    stats->sweep_index = after[0];
+  }
+  return BN_OK;
+}
+
+bn_status bn_energy(bn_problem p, double* out) {
+  if (!p || !out) return fail(BN_EINVAL, "NULL argument");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  HIPCHK(hipMemsetAsync(p->ysum, 0, p->v.ncls * sizeof(unsigned long long), p->stream));
+  HIPCHK(launch_energy(p->v, p->ysum, p->stream));
+  std::vector<unsigned long long> y(p->v.ncls);
+  HIPCHK(hipMemcpyAsync(y.data(), p->ysum, y.size() * 8, hipMemcpyDeviceToHost, p->stream));
+  bn_status s = sync(p);
+  if (s != BN_OK) return s;
+  // The kernel sums half of the window; the mirrored half has the same total.
+  double acc = 0.0;
+  for (uint32_t c = 0; c < p->v.ncls; ++c) acc = acc + p->cls_w[c] * (double)(long long)(2 * y[c]);
+  *out = acc / ((double)p->v.n * (double)p->v.n);
+  if (!std::isfinite(*out)) return fail(BN_ENUMERIC, "energy is not finite");
+  return BN_OK;
+}
+
+bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, double* out) {
+  if (!p || (n && (!sigmas || !out))) return fail(BN_EINVAL, "NULL argument");
+  if (n > 64) return fail(BN_EINVAL, "at most 64 blur sizes");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  for (uint32_t i = 0; i < n; ++i)
+    if (!(sigmas[i] > 0.0) || !std::isfinite(sigmas[i])) return fail(BN_EINVAL, "blur sizes must be > 0");
+  const size_t P = (size_t)p->v.w * p->v.h;
+  const uint32_t nparts = blur_partials(p->v);
+  float *tmp = nullptr, *kx = nullptr, *ky = nullptr;
+  int32_t *dx = nullptr, *dy = nullptr;
+  double* part = nullptr;
+  // Scratch for the blur lives for the duration of the call only.
+  auto release = [&]() {
+    for (void* q : {(void*)tmp, (void*)kx, (void*)ky, (void*)dx, (void*)dy, (void*)part})
+      if (q) (void)hipFree(q);
+  };
+  hipError_t e = hipMalloc((void**)&tmp, P * p->v.tp * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&kx, p->v.w * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&ky, p->v.h * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&dx, p->v.w * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&dy, p->v.h * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&part, (size_t)nparts * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(BN_ENOMEM, "quality metric scratch: %s", hipGetErrorString(e));
+  }
+  std::vector<double> hp(nparts);
+  for (uint32_t i = 0; i < n; ++i) {
+    std::vector<float> hkx, hky;
+    std::vector<int32_t> hdx, hdy;
+    blur_taps(p->v.w, sigmas[i], hkx, hdx);
+    blur_taps(p->v.h, sigmas[i], hky, hdy);
+    uint32_t np = 0;
+    e = hipMemcpyAsync(kx, hkx.data(), hkx.size() * 4, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dx, hdx.data(), hdx.size() * 4, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ky, hky.data(), hky.size() * 4, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dy, hdy.data(), hdy.size() * 4, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+      e = launch_blur(p->v, kx, (uint32_t)hkx.size(), dx, ky, (uint32_t)hky.size(), dy, tmp, part, &np,
+                      p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, (size_t)np * 8, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+      release();
+      return fail(BN_EHIP, "quality metric: %s", hipGetErrorString(e));
+    }
+    double acc = 0.0;
+    for (uint32_t b = 0; b < np; ++b) acc += hp[b];
+    out[i] = std::sqrt(acc / ((double)P * p->v.t));
+  }
+  release();
+  return BN_OK;
+}
+
+bn_status bn_get_offsets(bn_problem p, uint16_t* host_u) {
+  if (!p || !host_u) return fail(BN_EINVAL, "NULL argument");
+  if (!p->have_offsets) return fail(BN_ESTATE, "offsets are not initialised");
+  HIPCHK(hipMemcpyAsync(host_u, p->v.U, (size_t)p->v.w * p->v.h * 4, hipMemcpyDeviceToHost, p->stream));
+  return sync(p);
+}
+
+bn_status bn_get_counts(bn_problem p, uint16_t* host) {
+  if (!p || !host) return fail(BN_EINVAL, "NULL argument");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  HIPCHK(hipMemcpy2DAsync(host, p->v.t * 2, p->v.cnt, p->v.tp * 2, p->v.t * 2, (size_t)p->v.w * p->v.h,
+                          hipMemcpyDeviceToHost, p->stream));
+  return sync(p);
+}
+
+bn_status bn_get_errors(bn_problem p, float* host) {
+  if (!p || !host) return fail(BN_EINVAL, "NULL argument");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  HIPCHK(hipMemcpy2DAsync(host, p->v.t * 4, p->v.err, p->v.tp * 4, p->v.t * 4, (size_t)p->v.w * p->v.h,
+                          hipMemcpyDeviceToHost, p->stream));
+  return sync(p);
+}
+
+bn_status bn_get_integrands(bn_problem p, bn_heaviside* heavisides, double* areas) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  if (heavisides) std::copy(p->heav.begin(), p->heav.end(), heavisides);
+  if (areas) std::copy(p->area64.begin(), p->area64.end(), areas);
+  return BN_OK;
+}
+
+bn_status bn_get_points(bn_problem p, uint32_t pixel, uint16_t* host) {
+  if (!p || !host) return fail(BN_EINVAL, "NULL argument");
+  if (!p->have_offsets) return fail(BN_ESTATE, "offsets are not initialised");
+  if (pixel >= p->v.w * p->v.h) return fail(BN_EINVAL, "pixel %u out of range", pixel);
+  // The list count buffer (m rows of Tp uint16) doubles as room for N uint32.
+  bn_status s = ensure_list(p, std::max<uint32_t>(1, (2 * p->v.n + p->v.tp - 1) / p->v.tp));
+  if (s != BN_OK) return s;
+  uint32_t* buf = (uint32_t*)p->list_cnt;
+  HIPCHK(launch_points(p->v, pixel, buf, p->stream));
+  HIPCHK(hipMemcpyAsync(host, buf, (size_t)p->v.n * 4, hipMemcpyDeviceToHost, p->stream));
+  return sync(p);
+}
+
+bn_status bn_delta_energy(bn_problem p, const uint32_t* pixels, const uint16_t* proposals, uint32_t m,
+                          double* out_de, uint16_t* out_counts) {
+  if (!p || (m && (!pixels || !proposals || !out_de))) return fail(BN_EINVAL, "NULL argument");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  const uint32_t P = p->v.w * p->v.h;
+  if (m > P) return fail(BN_EINVAL, "m=%u exceeds the pixel count", m);
+  for (uint32_t i = 0; i < m; ++i)
+    if (pixels[i] >= P) return fail(BN_EINVAL, "pixel %u out of range", pixels[i]);
+  if (m == 0) return BN_OK;
+  bn_status s = ensure_list(p, m);
+  if (s != BN_OK) return s;
+  DevView lv = p->v;
+  lv.c_new = p->list_cnt;
+  lv.u_new = p->list_u;
+  lv.pix_list = p->list_pix;
+  lv.delta = p->list_delta;
+  lv.accept = p->list_accept;
+  HIPCHK(hipMemcpyAsync(p->list_pix, pixels, (size_t)m * 4, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->list_u, proposals, (size_t)m * 4, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(launch_count(lv, MODE_LIST, 0, m, p->stream));
+  HIPCHK(launch_delta(lv, MODE_LIST, 0, m, p->stream));
+  HIPCHK(hipMemcpyAsync(out_de, p->list_delta, (size_t)m * 8, hipMemcpyDeviceToHost, p->stream));
+  if (out_counts)
+    HIPCHK(hipMemcpy2DAsync(out_counts, p->v.t * 2, p->list_cnt, p->v.tp * 2, p->v.t * 2, m,
+                            hipMemcpyDeviceToHost, p->stream));
+  return sync(p);
+}
+
+bn_status bn_get_sweep_index(bn_problem p, uint64_t* out) {
+  if (!p || !out) return fail(BN_EINVAL, "NULL argument");
+  unsigned long long v = 0;
+  HIPCHK(hipMemcpyAsync(&v, p->v.ctr, 8, hipMemcpyDeviceToHost, p->stream));
+  bn_status s = sync(p);
+  if (s != BN_OK) return s;
+  p->sweep = v;
+  *out = v;
+  return BN_OK;
+}
+
+bn_status bn_set_sweep_index(bn_problem p, uint64_t sweep) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  const unsigned long long v = sweep;
+  HIPCHK(hipMemcpyAsync(p->v.ctr, &v, 8, hipMemcpyHostToDevice, p->stream));
+  bn_status s = sync(p);
+  if (s != BN_OK) return s;
+  p->sweep = sweep;
+  return BN_OK;
+}
+
+bn_status bn_phase_propose(bn_problem p, uint32_t kappa) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
+  HIPCHK(launch_count(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
+  return BN_OK;
+}
+
+bn_status bn_phase_evaluate(bn_problem p, uint32_t kappa) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
+  HIPCHK(launch_delta(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
+  return BN_OK;
+}
+
+bn_status bn_phase_commit(bn_problem p, uint32_t kappa) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
+  HIPCHK(launch_commit(p->v, kappa, p->stream));
+  return BN_OK;
+}
+
+bn_status bn_phase_advance(bn_problem p) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  HIPCHK(launch_advance(p->v, p->stream));
+  p->sweep += 1;
+  return BN_OK;
+}
+
+bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* delta, uint8_t* accept) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  const uint32_t M = p->v.pc;
+  if (u_new) HIPCHK(hipMemcpyAsync(u_new, p->v.u_new, (size_t)M * 4, hipMemcpyDeviceToHost, p->stream));
+  if (c_new)
+    HIPCHK(hipMemcpy2DAsync(c_new, p->v.t * 2, p->v.c_new, p->v.tp * 2, p->v.t * 2, M,
+                            hipMemcpyDeviceToHost, p->stream));
+  if (delta) HIPCHK(hipMemcpyAsync(delta, p->v.delta, (size_t)M * 8, hipMemcpyDeviceToHost, p->stream));
+  if (accept) HIPCHK(hipMemcpyAsync(accept, p->v.accept, M, hipMemcpyDeviceToHost, p->stream));
+  return sync(p);
+}
+
+bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tune_cache, bn_batch* out) {
+  (void)members;
+  (void)m;
+  (void)tune_cache;
+  (void)out;
+  return fail(BN_EUNSUPPORTED, "batches are not supported by this build");
+}
+
+bn_status bn_batch_sweep(bn_batch b, uint32_t k) {
+  (void)b;
+  (void)k;
+  return fail(BN_EUNSUPPORTED, "batches are not supported by this build");
+}
+
+bn_status bn_destroy_batch(bn_batch b) {
+  delete b;
+  return BN_OK;
+}
+
+}  // extern "C"

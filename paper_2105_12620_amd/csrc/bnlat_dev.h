@@ -1,0 +1,55 @@
+// Internal interface between the C-ABI host code and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bnlat {
+
+// Philox stream tags (fourth counter word).
+constexpr uint32_t S_INIT = 0xA;
+constexpr uint32_t S_INTEG = 0xB;
+constexpr uint32_t S_PROP = 0xC;
+
+// Integrand rows are padded to a multiple of this many entries; padded rows
+// have normal (0, 0) and threshold 0, so their hit count is always 0 and they
+// contribute nothing to energies.
+constexpr uint32_t T_ALIGN = 128;
+constexpr uint32_t MAX_RADIUS = 8;
+constexpr uint32_t MAX_N = 4096;
+
+enum CountMode : int { MODE_ALL = 0, MODE_CLASS = 1, MODE_LIST = 2 };
+
+// Everything a kernel needs to know about one problem, passed by value.
+struct DevView {
+  uint32_t n, log2n, w, h, t, tp, k, cw, ch, pc;
+  uint32_t problem, seed_lo, seed_hi;
+  int32_t objective;
+  uint32_t radius, ncls;
+  const uint32_t* lat;       // [n] lattice points, x | y << 16, index order i
+  const int2* ihp;           // [tp] (nx | ny << 16, D' = n . (C - 2^15))
+  const float* area;         // [tp] FP32 exact integrals (0 for padding)
+  const double* wd;          // [ncls] class weights exp(-d / sigma^2)
+  uint32_t* U;               // [P] offsets, x | y << 16
+  uint16_t* cnt;             // [P][tp] hit counts
+  float* err;                // [P][tp] error vectors
+  uint32_t* u_new;           // [M] proposals of the current phase / list
+  uint16_t* c_new;           // [M][tp] recounted hits of the proposals
+  double* delta;             // [M] energy change
+  uint8_t* accept;           // [M] decision
+  const uint32_t* pix_list;  // [M] pixels (list mode)
+  unsigned long long* ctr;   // [0] sweep index, [1] accepted total
+};
+
+hipError_t launch_init_offsets(const DevView& v, hipStream_t s);
+hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s);
+hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s);
+hipError_t launch_commit(const DevView& v, uint32_t kappa, hipStream_t s);
+hipError_t launch_advance(const DevView& v, hipStream_t s);
+hipError_t launch_points(const DevView& v, uint32_t pixel, uint32_t* out, hipStream_t s);
+hipError_t launch_energy(const DevView& v, unsigned long long* y, hipStream_t s);
+hipError_t launch_blur(const DevView& v, const float* kx, uint32_t nkx, const int32_t* dx,
+                       const float* ky, uint32_t nky, const int32_t* dy, float* tmp,
+                       double* partial, uint32_t* npartial, hipStream_t s);
+uint32_t blur_partials(const DevView& v);
+
+}  // namespace bnlat

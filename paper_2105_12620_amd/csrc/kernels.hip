@@ -1,0 +1,544 @@
+// gfx950 kernels of the screen-space lattice-offset optimiser.
+//
+// Data layout in HBM (P = W*H pixels, Tp = T rounded up to 128):
+//   U    uint32 [P]        offset of pixel p = y*W + x, Q0.16 x | y << 16
+//   cnt  uint16 [P][Tp]    hit counts, integrand-contiguous rows
+//   err  float  [P][Tp]    error vectors c/N - A_t
+//   lat  uint32 [N]        rank-1 lattice points (Sec. 3.2), x | y << 16
+//   ihp  int2   [Tp]       Heaviside (n packed as two int16, D' = n.(C - 2^15))
+// Side buffers of one colour phase (M class pixels): u_new [M], c_new [M][Tp],
+// delta [M], accept [M].
+//
+// All arithmetic that decides anything is exact: sample coordinates are
+// Q0.16, the Heaviside predicate n.(S - 2^15) > D' is an int16 dot product
+// against an int32 threshold, and the energy change is assembled from
+// integer class sums before one FP64 weighted sum in a fixed order.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bnlat_dev.h"
+
+namespace bnlat {
+namespace {
+
+typedef short v2i16 __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------- helpers
+
+// Philox4x32-10 (Salmon et al., SC 2011): two 32x32->64 products per round,
+// key advanced by the Weyl constants between rounds.  Returns words 0 and 1.
+__device__ inline uint2 philox_w01(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                   uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return make_uint2(c0, c1);
+}
+
+// Q0.16 pair from the top halves of words 0 and 1.
+__device__ inline uint32_t q16_pair(uint2 w) { return (w.x >> 16) | (w.y & 0xFFFF0000u); }
+
+// Componentwise (a + b) mod 2^16 of two packed Q0.16 pairs: the toroidal
+// shift mod(s + u, 1) of Sec. 3.2.
+__device__ inline uint32_t wrap_add(uint32_t a, uint32_t b) {
+  return ((a + b) & 0xFFFFu) | (((a >> 16) + (b >> 16)) << 16);
+}
+
+// S - 2^15 per component, as two int16.
+__device__ inline uint32_t centre(uint32_t s) { return s ^ 0x80008000u; }
+
+// Signed int16x2 dot product plus accumulator (v_dot2_i32_i16).  The clamp
+// bit keeps the three-operand encoding; it never engages because every
+// product sum here stays below 2^31 in magnitude.
+__device__ inline int dot2(uint32_t a, uint32_t b, int c) {
+  return __builtin_amdgcn_sdot2(__builtin_bit_cast(v2i16, a), __builtin_bit_cast(v2i16, b), c, true);
+}
+
+__device__ inline uint32_t wave_id() {
+  return __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+}
+
+__device__ inline uint32_t class_pixel(const DevView& v, uint32_t kappa, uint32_t j) {
+  const uint32_t ky = kappa / v.k, kx = kappa - ky * v.k;
+  const uint32_t a = j / v.cw, b = j - a * v.cw;
+  return (ky + v.k * a) * v.w + (kx + v.k * b);
+}
+
+__device__ inline uint32_t proposal(const DevView& v, uint32_t p, uint32_t sweep) {
+  return q16_pair(philox_w01(p, sweep, v.problem, S_PROP, v.seed_lo, v.seed_hi));
+}
+
+// Resolve the pixel, offset and output row of work item j of a count launch.
+template <int MODE>
+__device__ inline void count_target(const DevView& v, uint32_t kappa, uint32_t j, uint32_t& p,
+                                    uint32_t& u, uint16_t*& row) {
+  if (MODE == MODE_ALL) {
+    p = j;
+    u = v.U[p];
+    row = v.cnt + (size_t)p * v.tp;
+  } else if (MODE == MODE_CLASS) {
+    p = class_pixel(v, kappa, j);
+    u = proposal(v, p, (uint32_t)v.ctr[0]);
+    row = v.c_new + (size_t)j * v.tp;
+  } else {
+    p = v.pix_list[j];
+    u = v.u_new[j];
+    row = v.c_new + (size_t)j * v.tp;
+  }
+}
+
+// ----------------------------------------------------------- hit counting
+//
+// Estimator of the test-integrand map (Sec. 2): c[p][t] = number of the N
+// scrambled samples on the hit side of Heaviside t.
+//
+// k_count_points (N >= 64): the 64 lanes of a wave hold 64*PPL samples of one
+// pixel (PPL per lane); the wave walks integrands with wave-uniform
+// parameters in scalar registers.  Per (sample, integrand): one v_dot2 and
+// one v_cmp; the 64 predicate bits of a compare are counted with a scalar
+// popcount.  Counts for 64 consecutive integrands are gathered one per lane
+// and stored as one coalesced 128-byte row segment.  N > 64*PPL is handled
+// in groups of 64*PPL samples.
+template <int PPL, int MODE>
+__global__ __launch_bounds__(256) void k_count_points(DevView v, uint32_t kappa, uint32_t m,
+                                                      uint32_t tch) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = wave_id();
+  const uint32_t nch = (v.tp + tch - 1) / tch;
+  const uint32_t j = wave / nch, ch = wave - j * nch;
+  if (j >= m) return;
+  uint32_t p, u;
+  uint16_t* row;
+  count_target<MODE>(v, kappa, j, p, u, row);
+  if (MODE == MODE_CLASS && ch == 0 && lane == 0) v.u_new[j] = u;
+
+  const uint32_t groups = v.n / (64u * PPL);
+  uint32_t sp[PPL];
+  if (groups == 1) {
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) sp[k] = centre(wrap_add(v.lat[lane + 64 * k], u));
+  }
+  const float inv_n = 1.0f / (float)v.n;
+  const uint32_t t0 = ch * tch, t1 = min(t0 + tch, v.tp);
+  for (uint32_t tb = t0; tb < t1; tb += 64) {
+    int myc = 0;
+    if (tb < v.t) {
+      for (uint32_t g = 0; g < groups; ++g) {
+        if (groups > 1) {
+#pragma unroll
+          for (int k = 0; k < PPL; ++k)
+            sp[k] = centre(wrap_add(v.lat[g * 64 * PPL + lane + 64 * k], u));
+        }
+        const int2* ip = v.ihp + tb;
+#pragma unroll 8
+        for (uint32_t tt = 0; tt < 64; ++tt) {
+          const int2 q = ip[tt];
+          int c = 0;
+#pragma unroll
+          for (int k = 0; k < PPL; ++k)
+            c += __popcll(__ballot(dot2((uint32_t)q.x, sp[k], 0) > q.y));
+          myc += (lane == tt) ? c : 0;
+        }
+      }
+    }
+    row[tb + lane] = (uint16_t)myc;
+    if (MODE == MODE_ALL)
+      v.err[(size_t)p * v.tp + tb + lane] = (float)myc * inv_n - v.area[tb + lane];
+  }
+}
+
+// k_count_integrands (N < 64): lanes hold 64 integrands of one pixel and walk
+// the N samples, which are wave-uniform.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_count_integrands(DevView v, uint32_t kappa, uint32_t m) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = wave_id();
+  const uint32_t nch = v.tp >> 6;
+  const uint32_t j = wave / nch, ch = wave - j * nch;
+  if (j >= m) return;
+  uint32_t p, u;
+  uint16_t* row;
+  count_target<MODE>(v, kappa, j, p, u, row);
+  if (MODE == MODE_CLASS && ch == 0 && lane == 0) v.u_new[j] = u;
+  const uint32_t t = ch * 64 + lane;
+  const int2 q = v.ihp[t];
+  int c = 0;
+  for (uint32_t i = 0; i < v.n; ++i) c += dot2((uint32_t)q.x, centre(wrap_add(v.lat[i], u)), 0) > q.y;
+  row[t] = (uint16_t)c;
+  if (MODE == MODE_ALL) v.err[(size_t)p * v.tp + t] = (float)c * (1.0f / (float)v.n) - v.area[t];
+}
+
+// --------------------------------------------------------- window tables
+
+// Offsets of the (2R+1)^2 - 1 window grouped by squared distance d in
+// increasing d (row-major inside a group), with their group index.
+template <int R>
+struct Window {
+  static constexpr int M = (2 * R + 1) * (2 * R + 1) - 1;
+  static constexpr int DMAX = 2 * R * R;
+  int ox[M], oy[M], cls[M];
+  int ncls;
+  int d[DMAX + 1], csize[DMAX + 1];
+  constexpr Window() : ox(), oy(), cls(), ncls(0), d(), csize() {
+    int idx = 0;
+    for (int dd = 1; dd <= DMAX; ++dd) {
+      int found = 0;
+      for (int y = -R; y <= R; ++y)
+        for (int x = -R; x <= R; ++x)
+          if (x * x + y * y == dd) {
+            ox[idx] = x;
+            oy[idx] = y;
+            cls[idx] = ncls;
+            ++idx;
+            ++found;
+          }
+      if (found) {
+        d[ncls] = dd;
+        csize[ncls] = found;
+        ++ncls;
+      }
+    }
+  }
+};
+
+template <int R>
+struct WinConst {
+  static constexpr Window<R> w{};
+  static constexpr int NCLS = w.ncls;
+};
+
+// ------------------------------------------------------------ energy change
+//
+// Energy change of one pixel's move (Eq. (1) over the window, both pair
+// orderings):  dE = (2/N^2) sum_d w(d) X_d,
+//   X_d = |class d| * Z0 - 2 Z_d,  Z0 = sum_t dc_t (c'_t + c_t),
+//   Z_d = sum_{o in class d} sum_t dc_t c_{p+o,t},  dc = c' - c,
+// all in exact integers.  One wave per moved pixel; a lane handles two
+// adjacent integrands, so each neighbour read is one 256-byte row segment and
+// each (neighbour, integrand pair) costs one v_dot2 of packed int16 pairs.
+template <int R, int MODE>
+__global__ __launch_bounds__(256) void k_delta(DevView v, uint32_t kappa, uint32_t m) {
+  constexpr Window<R> W = WinConst<R>::w;
+  constexpr int NCLS = WinConst<R>::NCLS;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t j = wave_id();
+  if (j >= m) return;
+  const uint32_t p = (MODE == MODE_CLASS) ? class_pixel(v, kappa, j) : v.pix_list[j];
+  const uint32_t y = p / v.w, x = p - y * v.w;
+  uint32_t rowq[2 * R + 1], colq[2 * R + 1];
+#pragma unroll
+  for (int i = 0; i < 2 * R + 1; ++i) {
+    rowq[i] = ((y + v.h + i - R) % v.h) * v.w;
+    colq[i] = (x + v.w + i - R) % v.w;
+  }
+  const uint16_t* cn_row = v.c_new + (size_t)j * v.tp;
+  const uint16_t* co_row = v.cnt + (size_t)p * v.tp;
+  long long z0 = 0;
+  long long zd[NCLS];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) zd[c] = 0;
+
+  for (uint32_t base = 0; base < v.tp; base += 128) {
+    const uint32_t t = base + 2 * lane;
+    const uint32_t cn = *(const uint32_t*)(cn_row + t);
+    const uint32_t co = *(const uint32_t*)(co_row + t);
+    const int n0 = (int)(cn & 0xFFFFu), n1 = (int)(cn >> 16);
+    const int o0 = (int)(co & 0xFFFFu), o1 = (int)(co >> 16);
+    const int dc0 = n0 - o0, dc1 = n1 - o1;
+    const uint32_t dcp = ((uint32_t)dc0 & 0xFFFFu) | ((uint32_t)dc1 << 16);
+    z0 += (long long)(dc0 * (n0 + o0) + dc1 * (n1 + o1));
+    int part = 0;
+#pragma unroll
+    for (int mm = 0; mm < W.M; ++mm) {
+      const uint32_t q = rowq[W.oy[mm] + R] + colq[W.ox[mm] + R];
+      const uint32_t cq = *(const uint32_t*)(v.cnt + (size_t)q * v.tp + t);
+      part = dot2(dcp, cq, part);
+      if (mm == W.M - 1 || W.cls[mm + 1] != W.cls[mm]) {
+        zd[W.cls[mm]] += part;
+        part = 0;
+      }
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) {
+    long long xv = (long long)W.csize[c] * z0 - 2 * zd[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
+    acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)xv));
+  }
+  if (lane == 0) {
+    v.delta[j] = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+    v.accept[j] = (v.objective > 0) ? (acc < 0.0) : (acc > 0.0);
+  }
+}
+
+// ------------------------------------------------------------------ commit
+// Accepted moves of the phase become the state (Sec. 3.4): offset, hit
+// counts and FP32 errors of the pixel.
+__global__ __launch_bounds__(256) void k_commit(DevView v, uint32_t kappa) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t j = wave_id();
+  if (j >= v.pc || !v.accept[j]) return;
+  const uint32_t p = class_pixel(v, kappa, j);
+  if (lane == 0) {
+    v.U[p] = v.u_new[j];
+    atomicAdd(&v.ctr[1], 1ull);
+  }
+  const uint16_t* src = v.c_new + (size_t)j * v.tp;
+  uint16_t* dst = v.cnt + (size_t)p * v.tp;
+  float* e = v.err + (size_t)p * v.tp;
+  const float inv_n = 1.0f / (float)v.n;
+  for (uint32_t t = lane * 8; t < v.tp; t += 512) {
+    const uint4 c8 = *(const uint4*)(src + t);
+    *(uint4*)(dst + t) = c8;
+    const uint32_t w4[4] = {c8.x, c8.y, c8.z, c8.w};
+    float4 a = *(const float4*)(v.area + t), b = *(const float4*)(v.area + t + 4);
+    float4 lo, hi;
+    lo.x = (float)(w4[0] & 0xFFFFu) * inv_n - a.x;
+    lo.y = (float)(w4[0] >> 16) * inv_n - a.y;
+    lo.z = (float)(w4[1] & 0xFFFFu) * inv_n - a.z;
+    lo.w = (float)(w4[1] >> 16) * inv_n - a.w;
+    hi.x = (float)(w4[2] & 0xFFFFu) * inv_n - b.x;
+    hi.y = (float)(w4[2] >> 16) * inv_n - b.y;
+    hi.z = (float)(w4[3] & 0xFFFFu) * inv_n - b.z;
+    hi.w = (float)(w4[3] >> 16) * inv_n - b.w;
+    *(float4*)(e + t) = lo;
+    *(float4*)(e + t + 4) = hi;
+  }
+}
+
+__global__ void k_advance(unsigned long long* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&ctr[0], 1ull);
+}
+
+__global__ __launch_bounds__(256) void k_init_offsets(DevView v) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= v.w * v.h) return;
+  v.U[p] = q16_pair(philox_w01(p, 0, v.problem, S_INIT, v.seed_lo, v.seed_hi));
+}
+
+// The N samples of one pixel in van der Corput order: s^k = L(bitrev_m(k)).
+__global__ void k_points(DevView v, uint32_t pixel, uint32_t* out) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= v.n) return;
+  const uint32_t i = v.log2n ? (__brev(k) >> (32 - v.log2n)) : 0u;
+  out[k] = wrap_add(v.lat[i], v.U[pixel]);
+}
+
+// ------------------------------------------------------------------ energy
+// Y_d = sum_{o in class d} sum_p sum_t (c_p - c_{p+o})^2 over the half window
+// (the other half gives the same total); one wave per pixel, atomics on
+// integers only.
+template <int R>
+__global__ __launch_bounds__(256) void k_energy(DevView v, unsigned long long* ysum) {
+  constexpr Window<R> W = WinConst<R>::w;
+  constexpr int NCLS = WinConst<R>::NCLS;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t p = wave_id();
+  if (p >= v.w * v.h) return;
+  const uint32_t y = p / v.w, x = p - y * v.w;
+  long long yd[NCLS];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) yd[c] = 0;
+  const uint16_t* prow = v.cnt + (size_t)p * v.tp;
+  for (uint32_t base = 0; base < v.tp; base += 128) {
+    const uint32_t t = base + 2 * lane;
+    const uint32_t cp = *(const uint32_t*)(prow + t);
+    int part = 0;
+#pragma unroll
+    for (int mm = 0; mm < W.M; ++mm) {
+      const bool half = W.oy[mm] > 0 || (W.oy[mm] == 0 && W.ox[mm] > 0);
+      if (half) {
+        const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
+        const uint32_t cq = *(const uint32_t*)(v.cnt + (size_t)q * v.tp + t);
+        const int d0 = (int)(cp & 0xFFFFu) - (int)(cq & 0xFFFFu);
+        const int d1 = (int)(cp >> 16) - (int)(cq >> 16);
+        const uint32_t dp = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
+        part = dot2(dp, dp, part);
+      }
+      if (mm == W.M - 1 || W.cls[mm + 1] != W.cls[mm]) {
+        yd[W.cls[mm]] += part;
+        part = 0;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) {
+    long long s = yd[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0 && s) atomicAdd(&ysum[c], (unsigned long long)s);
+  }
+}
+
+// ------------------------------------------------------------ blur criterion
+// Separable periodised Gaussian blur of the error tile (Sec. 3.3): taps
+// (d_i, k_i) with d_i in [0, W); b(x) = sum_i k_i e((x - d_i) mod W).
+__global__ __launch_bounds__(256) void k_blur_x(DevView v, const float* __restrict__ kx,
+                                                const int32_t* __restrict__ dx, uint32_t nk,
+                                                float* __restrict__ out) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = wave_id();
+  const uint32_t nch = v.tp >> 6;
+  const uint32_t p = wave / nch, ch = wave - p * nch;
+  if (p >= v.w * v.h) return;
+  const uint32_t y = p / v.w, x = p - y * v.w;
+  const uint32_t t = ch * 64 + lane;
+  const float* rowbase = v.err + (size_t)y * v.w * v.tp + t;
+  float acc = 0.0f;
+  for (uint32_t i = 0; i < nk; ++i) {
+    uint32_t xs = x + v.w - (uint32_t)dx[i];
+    if (xs >= v.w) xs -= v.w;
+    acc = fmaf(kx[i], rowbase[(size_t)xs * v.tp], acc);
+  }
+  out[(size_t)p * v.tp + t] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_blur_y_sq(DevView v, const float* __restrict__ ky,
+                                                   const int32_t* __restrict__ dy, uint32_t nk,
+                                                   const float* __restrict__ in,
+                                                   double* __restrict__ partial) {
+  __shared__ double red[4];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = wave_id();
+  const uint32_t nch = v.tp >> 6;
+  const uint32_t p = wave / nch, ch = wave - p * nch;
+  double sq = 0.0;
+  if (p < v.w * v.h) {
+    const uint32_t y = p / v.w, x = p - y * v.w;
+    const uint32_t t = ch * 64 + lane;
+    float acc = 0.0f;
+    for (uint32_t i = 0; i < nk; ++i) {
+      uint32_t ys = y + v.h - (uint32_t)dy[i];
+      if (ys >= v.h) ys -= v.h;
+      acc = fmaf(ky[i], in[((size_t)ys * v.w + x) * v.tp + t], acc);
+    }
+    if (t < v.t) sq = (double)acc * (double)acc;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+  if (lane == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <int MODE>
+hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  if (v.n < 64) {
+    const uint64_t waves = (uint64_t)m * (v.tp >> 6);
+    hipLaunchKernelGGL(k_count_integrands<MODE>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
+                       v, kappa, m);
+    return hipGetLastError();
+  }
+  const uint32_t tch = v.tp >= 256 ? 256 : v.tp;
+  const uint64_t waves = (uint64_t)m * ((v.tp + tch - 1) / tch);
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+  switch (v.n) {
+    case 64: hipLaunchKernelGGL((k_count_points<1, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
+    case 128: hipLaunchKernelGGL((k_count_points<2, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
+    case 256: hipLaunchKernelGGL((k_count_points<4, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
+    case 512: hipLaunchKernelGGL((k_count_points<8, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
+    default: hipLaunchKernelGGL((k_count_points<16, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
+  }
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t delta_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const dim3 grid((m + 3) / 4), block(256);
+  switch (v.radius) {
+    case 1: hipLaunchKernelGGL((k_delta<1, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 2: hipLaunchKernelGGL((k_delta<2, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 3: hipLaunchKernelGGL((k_delta<3, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 4: hipLaunchKernelGGL((k_delta<4, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 5: hipLaunchKernelGGL((k_delta<5, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 6: hipLaunchKernelGGL((k_delta<6, MODE>), grid, block, 0, s, v, kappa, m); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_init_offsets(const DevView& v, hipStream_t s) {
+  const uint32_t P = v.w * v.h;
+  hipLaunchKernelGGL(k_init_offsets, dim3((P + 255) / 256), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
+  switch (mode) {
+    case MODE_ALL: return count_dispatch<MODE_ALL>(v, kappa, m, s);
+    case MODE_CLASS: return count_dispatch<MODE_CLASS>(v, kappa, m, s);
+    default: return count_dispatch<MODE_LIST>(v, kappa, m, s);
+  }
+}
+
+hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
+  return mode == MODE_CLASS ? delta_dispatch<MODE_CLASS>(v, kappa, m, s)
+                            : delta_dispatch<MODE_LIST>(v, kappa, m, s);
+}
+
+hipError_t launch_commit(const DevView& v, uint32_t kappa, hipStream_t s) {
+  hipLaunchKernelGGL(k_commit, dim3((v.pc + 3) / 4), dim3(256), 0, s, v, kappa);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(const DevView& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, v.ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_points(const DevView& v, uint32_t pixel, uint32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_points, dim3((v.n + 255) / 256), dim3(256), 0, s, v, pixel, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const DevView& v, unsigned long long* y, hipStream_t s) {
+  const uint32_t P = v.w * v.h;
+  const dim3 grid((P + 3) / 4), block(256);
+  switch (v.radius) {
+    case 1: hipLaunchKernelGGL(k_energy<1>, grid, block, 0, s, v, y); break;
+    case 2: hipLaunchKernelGGL(k_energy<2>, grid, block, 0, s, v, y); break;
+    case 3: hipLaunchKernelGGL(k_energy<3>, grid, block, 0, s, v, y); break;
+    case 4: hipLaunchKernelGGL(k_energy<4>, grid, block, 0, s, v, y); break;
+    case 5: hipLaunchKernelGGL(k_energy<5>, grid, block, 0, s, v, y); break;
+    case 6: hipLaunchKernelGGL(k_energy<6>, grid, block, 0, s, v, y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+uint32_t blur_partials(const DevView& v) {
+  const uint64_t waves = (uint64_t)v.w * v.h * (v.tp >> 6);
+  return (uint32_t)((waves + 3) / 4);
+}
+
+hipError_t launch_blur(const DevView& v, const float* kx, uint32_t nkx, const int32_t* dx,
+                       const float* ky, uint32_t nky, const int32_t* dy, float* tmp,
+                       double* partial, uint32_t* npartial, hipStream_t s) {
+  const uint32_t blocks = blur_partials(v);
+  hipLaunchKernelGGL(k_blur_x, dim3(blocks), dim3(256), 0, s, v, kx, dx, nkx, tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_blur_y_sq, dim3(blocks), dim3(256), 0, s, v, ky, dy, nky, (const float*)tmp,
+                     partial);
+  *npartial = blocks;
+  return hipGetLastError();
+}
+
+}  // namespace bnlat

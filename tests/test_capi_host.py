@@ -1,0 +1,109 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+entry point, validates configurations before any device work, and its host
+tables (window classes, Heaviside integrals, Philox-drawn integrands) agree
+with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import energy, integrands
+import synthgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+bnlat = pytest.importorskip("paper_2105_12620_amd.bnlat")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(bnlat.LIB_PATH):
+        pytest.skip("libbnlat.so is not built")
+    return bnlat.lib()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "bnlat.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bn_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 29
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def cfg(**kw):
+    base = dict(synthgen.WORKLOADS["tile32_n16_t64"])
+    base.update(kw)
+    return bnlat.make_config(**base)
+
+
+@pytest.mark.parametrize("kw", [dict(n=12), dict(n=0), dict(g=(2, 7)), dict(colour_k=3),
+                                dict(radius=0), dict(radius=32), dict(radius=9), dict(sigma=0.0),
+                                dict(t_heaviside=0), dict(objective=0), dict(width=30, colour_k=4)])
+def test_validation_rejects(L, kw):
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.validate_config(cfg(**kw))
+    assert e.value.status == bnlat.BN_EINVAL
+
+
+def test_validation_accepts_workloads(L):
+    for wl in synthgen.WORKLOADS.values():
+        bnlat.validate_config(bnlat.make_config(**wl))
+    for wl in synthgen.dimension_pair_batch():
+        bnlat.validate_config(bnlat.make_config(**wl))
+
+
+def test_create_rejects_bad_config_before_device(L):
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.Problem(cfg(n=12))
+    assert e.value.status == bnlat.BN_EINVAL
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.Problem(cfg(t_gauss=4))
+    assert e.value.status == bnlat.BN_EUNSUPPORTED
+
+
+def test_create_rejects_bad_normal_before_device(L):
+    h = bnlat.heaviside_array(synthgen.heaviside_table(64, seed=0))
+    h["nx"][3], h["ny"][3] = 0, 0
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.Problem(cfg(), h)
+    assert e.value.status == bnlat.BN_EINVAL
+
+
+def test_window_classes_match_oracle_bitwise(L):
+    for r, sigma in ((3, 2.1), (4, 2.1), (5, 2.1), (2, 0.7), (6, 3.3)):
+        d, w = bnlat.window_classes(cfg(radius=r, sigma=sigma, width=64, height=64))
+        assert list(d) == energy.distance_classes(r)
+        np.testing.assert_array_equal(w, energy.class_weights(r, sigma))
+
+
+def test_heaviside_areas_match_oracle(L):
+    t = synthgen.heaviside_table(500, seed=11)
+    for nx, ny, cx, cy in zip(t["nx"], t["ny"], t["cx"], t["cy"]):
+        assert bnlat.heaviside_area(nx, ny, cx, cy) == pytest.approx(
+            integrands.heaviside_area(nx, ny, cx, cy), abs=2e-16)
+    for args in ((16384, 0, 1000, 5), (0, -16384, 9, 40000), (1000, 1000, 50000, 50000)):
+        assert bnlat.heaviside_area(*args) == pytest.approx(integrands.heaviside_area(*args), abs=2e-16)
+
+
+def test_drawn_heavisides_match_oracle_draw(L):
+    got = bnlat.draw_heavisides(seed=5, problem_id=3, t=2000)
+    want = integrands.heaviside_table_philox(2000, seed=5, problem=3)
+    for k in ("nx", "ny", "cx", "cy"):
+        np.testing.assert_array_equal(got[k], want[k])
+
+
+def test_device_calls_fail_loudly_without_gpu(L):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.Problem(cfg())
+    assert e.value.status == bnlat.BN_EHIP

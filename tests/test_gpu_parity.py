@@ -1,0 +1,251 @@
+"""Parity of the gfx950 path (through the C ABI) against the CPU oracle.
+
+Bars: hit counts, lattice points, offsets and trajectories bit-exact; error
+vectors within 1e-6 of the larger operand of c/N - A; energy changes and
+energies within 1e-12 relative (both sides evaluate the same integer class
+sums with the same FP64 weights in the same order); blur criterion within
+1e-5 relative (FP32 convolution against FP64)."""
+import numpy as np
+import pytest
+
+from oracle import energy, estimator, lattice, quality, sweep as osw
+import synthgen
+
+pytestmark = pytest.mark.gpu
+bnlat = pytest.importorskip("paper_2105_12620_amd.bnlat")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def workload(name=None, **kw):
+    w = dict(synthgen.WORKLOADS[name]) if name else dict(
+        n=16, g=(1, 7), width=16, height=16, t_heaviside=12, t_gauss=0, sigma=2.1, radius=3,
+        colour_k=2, sweeps=3, seed=7, problem_id=0)
+    w.update(kw)
+    return w
+
+
+EDGE = {
+    "n1": workload(n=1, g=(1, 1), t_heaviside=5),
+    "n4_ragged": workload(n=4, g=(1, 3), t_heaviside=70),
+    "n32": workload(n=32, g=(1, 13), t_heaviside=40),
+    "n128": workload(n=128, g=(1, 45), t_heaviside=130, width=8, height=8, radius=2),
+    "n256_r4": workload(n=256, g=(1, 79), t_heaviside=200, width=12, height=12, radius=4),
+    "n512": workload(n=512, g=(3, 101), t_heaviside=64, width=8, height=8, radius=3),
+    "n1024_r5": workload(n=1024, g=(1, 381), t_heaviside=66, width=12, height=12, radius=5),
+    "n2048": workload(n=2048, g=(1, 763), t_heaviside=65, width=8, height=8, radius=2),
+    "tile4_alias": workload(width=4, height=4, radius=3, t_heaviside=9),
+    "k1": workload(colour_k=1, width=8, height=8, radius=2),
+    "k4_conflict_free": workload(colour_k=4, width=16, height=16, radius=3),
+    "rect_ascend": workload(width=12, height=8, radius=3, objective=-1),
+    "r6": workload(width=16, height=16, radius=6, n=64, g=(1, 19), t_heaviside=20),
+}
+
+
+def oracle_problem(w, inp):
+    return osw.Problem(n=w["n"], g=w["g"], width=w["width"], height=w["height"], radius=w["radius"],
+                       sigma=w["sigma"], colour_k=w["colour_k"], seed=w["seed"],
+                       problem_id=w.get("problem_id", 0), table=inp["heaviside"],
+                       objective=w.get("objective", 1))
+
+
+def gpu_problem(w, inp):
+    p = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]))
+    p.init_offsets(inp["offsets"])
+    p.compute_errors()
+    return p
+
+
+def check_errors(err32, counts, n, areas):
+    e64 = counts / n - areas
+    scale = np.maximum(np.maximum(np.abs(e64), areas), counts / n)
+    assert np.all(np.abs(err32.astype(np.float64) - e64) <= 1e-6 * scale + 1e-30)
+
+
+@pytest.mark.parametrize("name", list(EDGE) + ["tile32_n16_t64", "tile128_n64_t256"])
+def test_counts_errors_and_points(name):
+    w = EDGE.get(name) or workload(name)
+    say("case", name, {k: w[k] for k in ("n", "width", "height", "t_heaviside", "radius", "colour_k")})
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    c_ref = estimator.hit_counts(w["n"], w["g"], inp["offsets"].reshape(-1, 2), inp["heaviside"])
+    with gpu_problem(w, inp) as p:
+        np.testing.assert_array_equal(p.get_counts(), c_ref)
+        check_errors(p.get_errors(), c_ref, w["n"], ref.areas)
+        h, a = p.get_integrands()
+        np.testing.assert_array_equal(a, ref.areas)
+        seq = lattice.sequence_q16(w["n"], w["g"])
+        P = w["width"] * w["height"]
+        for pix in (0, P // 3, P - 1):
+            want = lattice.scramble(seq, inp["offsets"].reshape(-1, 2)[pix].astype(np.int64))
+            np.testing.assert_array_equal(p.get_points(pix), want)
+
+
+def test_philox_offsets_match_oracle():
+    w = workload(width=40, height=24, colour_k=2, seed=123456789012, problem_id=5)
+    inp = synthgen.problem_inputs(w)
+    with bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"])) as p:
+        p.init_offsets(None)
+        np.testing.assert_array_equal(p.get_offsets(), osw.philox_offsets(oracle_problem(w, inp)))
+
+
+def test_drawn_integrands_used_when_none_given():
+    w = workload(t_heaviside=33, seed=9)
+    with bnlat.create_problem(w, None) as p:
+        h, _ = p.get_integrands()
+    np.testing.assert_array_equal(h, bnlat.draw_heavisides(9, 0, 33))
+
+
+@pytest.mark.parametrize("name", ["n4_ragged", "n256_r4", "tile4_alias", "k4_conflict_free",
+                                  "rect_ascend", "n1024_r5", "tile32_n16_t64"])
+def test_phase_steps_match_oracle(name):
+    """Every step of two sweeps' phases: proposals, recounts, energy changes,
+    decisions and the committed state."""
+    w = EDGE.get(name) or workload(name)
+    say("case", name)
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.initial_state(ref, inp["offsets"])
+    with gpu_problem(w, inp) as p:
+        for s in range(2):
+            for kappa in range(w["colour_k"] ** 2):
+                p.phase_propose(kappa)
+                p.phase_evaluate(kappa)
+                got = p.get_phase()
+                ph = osw.phase(ref, st, kappa)
+                np.testing.assert_array_equal(got["u_new"], ph["u_new"])
+                np.testing.assert_array_equal(got["c_new"], ph["c_new"])
+                np.testing.assert_allclose(got["delta"], ph["delta"], rtol=1e-12, atol=0)
+                np.testing.assert_array_equal(got["accept"], ph["accept"])
+                p.phase_commit(kappa)
+            p.phase_advance()
+            st.sweep += 1
+        np.testing.assert_array_equal(p.get_offsets(), st.u)
+        np.testing.assert_array_equal(p.get_counts(), st.c.reshape(-1, w["t_heaviside"]))
+        assert p.get_sweep_index() == 2
+
+
+@pytest.mark.parametrize("name,k", [("tile32_n16_t64", 100), ("tile128_n64_t256", 2),
+                                    ("n256_r4", 4), ("k1", 3), ("rect_ascend", 5)])
+def test_sweep_trajectory_matches_oracle(name, k):
+    """bn_sweep (graph-replayed) gives the oracle's trajectory bit for bit,
+    and the same energy and blur criterion."""
+    w = EDGE.get(name) or workload(name)
+    say("case", name, "sweeps", k)
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.run(ref, osw.initial_state(ref, inp["offsets"]), k)
+    with gpu_problem(w, inp) as p:
+        stats = p.sweep(k, stats=True)
+        assert stats["sweep_index"] == k
+        assert stats["accepts"] == sum(st.accepts)
+        np.testing.assert_array_equal(p.get_offsets(), st.u)
+        np.testing.assert_array_equal(p.get_counts(), st.c.reshape(-1, w["t_heaviside"]))
+        e_ref = osw.energy_of(ref, st)
+        assert p.energy() == pytest.approx(e_ref, rel=1e-12)
+        assert p.energy() == pytest.approx(energy.energy_plain(osw.errors(ref, st), w["radius"], w["sigma"]),
+                                           rel=1e-9)
+        sig = (0.25, 1.0, 4.0, 20.0)
+        np.testing.assert_allclose(p.quality_metric(sig), quality.quality(osw.errors(ref, st), sig),
+                                   rtol=1e-5)
+
+
+def test_delta_energy_list_matches_oracle():
+    w = EDGE["n256_r4"]
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.initial_state(ref, inp["offsets"])
+    P = w["width"] * w["height"]
+    pix = synthgen.pixel_sample(P, 40, seed=1)
+    prop = synthgen.proposals(40, seed=2)
+    ys, xs = np.divmod(pix.astype(np.int64), w["width"])
+    c_new = estimator.hit_counts(w["n"], w["g"], prop.astype(np.int64), inp["heaviside"])
+    want = energy.delta_exact(st.c, ys, xs, c_new, w["n"], w["radius"], w["sigma"])
+    e = osw.errors(ref, st)
+    with gpu_problem(w, inp) as p:
+        de, cn = p.delta_energy(pix, prop, counts=True)
+    np.testing.assert_array_equal(cn, c_new)
+    np.testing.assert_allclose(de, want, rtol=1e-12, atol=0)
+    for j in range(len(pix)):
+        plain = energy.delta_plain(e, ys[j], xs[j], c_new[j] / w["n"] - ref.areas, w["radius"], w["sigma"])
+        scale = abs(plain) + 1e-3
+        assert abs(de[j] - plain) <= 1e-5 * scale
+
+
+def test_full_size_tile256_sampled():
+    """256x256 tile, N=256, T=1024, 9x9 window in the benchmark's launch
+    configuration: sampled pixels' hit counts after bn_compute_errors, and the
+    first phase's proposals, recounts, energy changes and decisions for
+    sampled class pixels, each computed by the oracle from the inputs."""
+    w = workload("tile256_n256_t1024")
+    inp = synthgen.problem_inputs(w)
+    W, H, T, r = w["width"], w["height"], w["t_heaviside"], w["radius"]
+    u0 = inp["offsets"].reshape(-1, 2).astype(np.int64)
+    ref = oracle_problem(w, inp)
+    with gpu_problem(w, inp) as p:
+        c_gpu = p.get_counts()
+        e_gpu = p.get_errors()
+        p.phase_propose(0)
+        p.phase_evaluate(0)
+        ph = p.get_phase()
+    sample = synthgen.pixel_sample(W * H, 48, seed=3)
+    c_ref = estimator.hit_counts(w["n"], w["g"], u0[sample], inp["heaviside"])
+    np.testing.assert_array_equal(c_gpu[sample], c_ref)
+    check_errors(e_gpu[sample], c_ref, w["n"], ref.areas)
+    # first phase, class 0: class pixel j sits at (2a, 2b), j = a * W/2 + b
+    js = synthgen.pixel_sample((W // 2) * (H // 2), 6, seed=4)
+    for j in js:
+        y, x = 2 * (int(j) // (W // 2)), 2 * (int(j) % (W // 2))
+        win = [((y + oy) % H, (x + ox) % W) for oy in range(-r, r + 1) for ox in range(-r, r + 1)]
+        ids = np.array([yy * W + xx for yy, xx in win])
+        local = np.zeros((H, W, T), dtype=np.int16)
+        local[tuple(np.array(win).T)] = estimator.hit_counts(w["n"], w["g"], u0[ids], inp["heaviside"])
+        u_new = osw.proposals(ref, np.array([y]), np.array([x]), 0).astype(np.int64)
+        c_new = estimator.hit_counts(w["n"], w["g"], u_new, inp["heaviside"])
+        np.testing.assert_array_equal(ph["u_new"][j], u_new[0])
+        np.testing.assert_array_equal(ph["c_new"][j], c_new[0])
+        d = energy.delta_exact(local, [y], [x], c_new, w["n"], r, w["sigma"])
+        assert ph["delta"][j] == pytest.approx(d[0], rel=1e-12)
+        assert bool(ph["accept"][j]) == bool(d[0] < 0)
+
+
+def test_rerun_and_resume_are_bit_identical():
+    w = EDGE["n256_r4"]
+    inp = synthgen.problem_inputs(w)
+    with gpu_problem(w, inp) as a:
+        a.sweep(3)
+        ua = a.get_offsets()
+    with gpu_problem(w, inp) as b:
+        b.sweep(3)
+        np.testing.assert_array_equal(b.get_offsets(), ua)
+    with gpu_problem(w, inp) as c:
+        c.sweep(1)
+        mid = c.get_offsets()
+    with bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"])) as d:
+        d.init_offsets(mid)
+        d.compute_errors()
+        d.set_sweep_index(1)
+        d.sweep(2)
+        np.testing.assert_array_equal(d.get_offsets(), ua)
+
+
+def test_call_order_is_enforced():
+    w = EDGE["n4_ragged"]
+    inp = synthgen.problem_inputs(w)
+    with bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"])) as p:
+        with pytest.raises(bnlat.BnlatError) as e:
+            p.compute_errors()
+        assert e.value.status == bnlat.BN_ESTATE
+        p.init_offsets(inp["offsets"])
+        with pytest.raises(bnlat.BnlatError) as e:
+            p.sweep(1)
+        assert e.value.status == bnlat.BN_ESTATE
+        p.compute_errors()
+        with pytest.raises(bnlat.BnlatError) as e:
+            p.get_points(w["width"] * w["height"])
+        assert e.value.status == bnlat.BN_EINVAL
+        with pytest.raises(bnlat.BnlatError) as e:
+            p.phase_propose(4)
+        assert e.value.status == bnlat.BN_EINVAL
