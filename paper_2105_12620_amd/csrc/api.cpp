@@ -245,6 +245,19 @@ bn_status sync(bn_problem p) {
   return BN_OK;
 }
 
+// Copy a tiled count buffer ([tp/8][rows][8] uint16 on the device) to host
+// rows [rows][t].  Synchronises.
+bn_status untile_counts(bn_problem p, const uint16_t* dev, uint32_t rows, uint16_t* host) {
+  const uint32_t t = p->v.t, tp = p->v.tp;
+  std::vector<uint16_t> tmp((size_t)rows * tp);
+  HIPCHK(hipMemcpyAsync(tmp.data(), dev, tmp.size() * 2, hipMemcpyDeviceToHost, p->stream));
+  bn_status s = sync(p);
+  if (s != BN_OK) return s;
+  for (uint32_t r = 0; r < rows; ++r)
+    for (uint32_t i = 0; i < t; ++i) host[(size_t)r * t + i] = tmp[((size_t)(i >> 3) * rows + r) * 8 + (i & 7)];
+  return BN_OK;
+}
+
 bn_status ensure_list(bn_problem p, uint32_t m) {
   if (m <= p->list_cap) return BN_OK;
   bn_status s;
@@ -439,7 +452,7 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
       (s = p->alloc(&v.err, P * v.tp)) != BN_OK || (s = p->alloc(&v.u_new, v.pc)) != BN_OK ||
       (s = p->alloc(&v.c_new, (size_t)v.pc * v.tp)) != BN_OK || (s = p->alloc(&v.delta, v.pc)) != BN_OK ||
       (s = p->alloc(&v.accept, v.pc)) != BN_OK || (s = p->alloc(&v.ctr, 2)) != BN_OK ||
-      (s = p->alloc(&p->ysum, v.ncls)) != BN_OK) {
+      (s = p->alloc(&p->ysum, v.ncls)) != BN_OK || (s = p->alloc(&v.xpart, xpart_words(v))) != BN_OK) {
     delete p;
     return s;
   }
@@ -455,6 +468,7 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   if (e == hipSuccess) e = hipMemcpyAsync(area_d, areaf.data(), v.tp * 4, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(wd_d, p->cls_w.data(), v.ncls * 8, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(v.ctr, zero, sizeof zero, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(v.xpart, 0, (size_t)xpart_words(v) * 8, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) {
     delete p;
@@ -605,9 +619,7 @@ bn_status bn_get_offsets(bn_problem p, uint16_t* host_u) {
 bn_status bn_get_counts(bn_problem p, uint16_t* host) {
   if (!p || !host) return fail(BN_EINVAL, "NULL argument");
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
-  HIPCHK(hipMemcpy2DAsync(host, p->v.t * 2, p->v.cnt, p->v.tp * 2, p->v.t * 2, (size_t)p->v.w * p->v.h,
-                          hipMemcpyDeviceToHost, p->stream));
-  return sync(p);
+  return untile_counts(p, p->v.cnt, p->v.w * p->v.h, host);
 }
 
 bn_status bn_get_errors(bn_problem p, float* host) {
@@ -660,9 +672,7 @@ bn_status bn_delta_energy(bn_problem p, const uint32_t* pixels, const uint16_t* 
   HIPCHK(launch_count(lv, MODE_LIST, 0, m, p->stream));
   HIPCHK(launch_delta(lv, MODE_LIST, 0, m, p->stream));
   HIPCHK(hipMemcpyAsync(out_de, p->list_delta, (size_t)m * 8, hipMemcpyDeviceToHost, p->stream));
-  if (out_counts)
-    HIPCHK(hipMemcpy2DAsync(out_counts, p->v.t * 2, p->list_cnt, p->v.tp * 2, p->v.t * 2, m,
-                            hipMemcpyDeviceToHost, p->stream));
+  if (out_counts) return untile_counts(p, p->list_cnt, m, out_counts);
   return sync(p);
 }
 
@@ -722,9 +732,10 @@ bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* d
   if (!p) return fail(BN_EINVAL, "NULL problem");
   const uint32_t M = p->v.pc;
   if (u_new) HIPCHK(hipMemcpyAsync(u_new, p->v.u_new, (size_t)M * 4, hipMemcpyDeviceToHost, p->stream));
-  if (c_new)
-    HIPCHK(hipMemcpy2DAsync(c_new, p->v.t * 2, p->v.c_new, p->v.tp * 2, p->v.t * 2, M,
-                            hipMemcpyDeviceToHost, p->stream));
+  if (c_new) {
+    bn_status s = untile_counts(p, p->v.c_new, M, c_new);
+    if (s != BN_OK) return s;
+  }
   if (delta) HIPCHK(hipMemcpyAsync(delta, p->v.delta, (size_t)M * 8, hipMemcpyDeviceToHost, p->stream));
   if (accept) HIPCHK(hipMemcpyAsync(accept, p->v.accept, M, hipMemcpyDeviceToHost, p->stream));
   return sync(p);

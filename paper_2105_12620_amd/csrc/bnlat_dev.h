@@ -30,19 +30,21 @@ struct DevView {
   const float* area;         // [tp] FP32 exact integrals (0 for padding)
   const double* wd;          // [ncls] class weights exp(-d / sigma^2)
   uint32_t* U;               // [P] offsets, x | y << 16
-  uint16_t* cnt;             // [P][tp] hit counts
+  uint16_t* cnt;             // [tp/8][P][8] hit counts (16-byte integrand tiles)
   float* err;                // [P][tp] error vectors
   uint32_t* u_new;           // [M] proposals of the current phase / list
-  uint16_t* c_new;           // [M][tp] recounted hits of the proposals
+  uint16_t* c_new;           // [tp/8][M][8] recounted hits of the proposals
   double* delta;             // [M] energy change
   uint8_t* accept;           // [M] decision
   const uint32_t* pix_list;  // [M] pixels (list mode)
   unsigned long long* ctr;   // [0] sweep index, [1] accepted total
+  long long* xpart;          // [ncls][pc] integer class sums of the staged evaluation (kept zero between phases)
 };
 
 hipError_t launch_init_offsets(const DevView& v, hipStream_t s);
 hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s);
 hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s);
+uint32_t xpart_words(const DevView& v);
 hipError_t launch_commit(const DevView& v, uint32_t kappa, hipStream_t s);
 hipError_t launch_advance(const DevView& v, hipStream_t s);
 hipError_t launch_points(const DevView& v, uint32_t pixel, uint32_t* out, hipStream_t s);

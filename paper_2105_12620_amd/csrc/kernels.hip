@@ -2,12 +2,16 @@
 //
 // Data layout in HBM (P = W*H pixels, Tp = T rounded up to 128):
 //   U    uint32 [P]        offset of pixel p = y*W + x, Q0.16 x | y << 16
-//   cnt  uint16 [P][Tp]    hit counts, integrand-contiguous rows
+//   cnt  uint16 [Tp/8][P][8] hit counts in 16-byte integrand tiles: the 8
+//                          counts of integrands 8i..8i+7 of a pixel are
+//                          contiguous and neighbouring pixels' tiles are
+//                          adjacent, so a row of pixels for 8 integrands is
+//                          one contiguous run
 //   err  float  [P][Tp]    error vectors c/N - A_t
 //   lat  uint32 [N]        rank-1 lattice points (Sec. 3.2), x | y << 16
 //   ihp  int2   [Tp]       Heaviside (n packed as two int16, D' = n.(C - 2^15))
-// Side buffers of one colour phase (M class pixels): u_new [M], c_new [M][Tp],
-// delta [M], accept [M].
+// Side buffers of one colour phase (M class pixels): u_new [M],
+// c_new [Tp/8][M][8] (same tiling), delta [M], accept [M].
 //
 // All arithmetic that decides anything is exact: sample coordinates are
 // Q0.16, the Heaviside predicate n.(S - 2^15) > D' is an int16 dot product
@@ -58,6 +62,11 @@ __device__ inline uint32_t wrap_add(uint32_t a, uint32_t b) {
 // S - 2^15 per component, as two int16.
 __device__ inline uint32_t centre(uint32_t s) { return s ^ 0x80008000u; }
 
+// Element (row, t) of a tiled count buffer with `rows` rows.
+__device__ inline size_t tix(uint32_t row, uint32_t t, uint32_t rows) {
+  return ((size_t)(t >> 3) * rows + row) * 8 + (t & 7);
+}
+
 // Signed int16x2 dot product plus accumulator (v_dot2_i32_i16).  The clamp
 // bit keeps the three-operand encoding; it never engages because every
 // product sum here stays below 2^31 in magnitude.
@@ -79,22 +88,30 @@ __device__ inline uint32_t proposal(const DevView& v, uint32_t p, uint32_t sweep
   return q16_pair(philox_w01(p, sweep, v.problem, S_PROP, v.seed_lo, v.seed_hi));
 }
 
-// Resolve the pixel, offset and output row of work item j of a count launch.
+// Resolve the pixel, offset and output buffer (row index, row count) of work
+// item j of a count launch.
 template <int MODE>
-__device__ inline void count_target(const DevView& v, uint32_t kappa, uint32_t j, uint32_t& p,
-                                    uint32_t& u, uint16_t*& row) {
+__device__ inline void count_target(const DevView& v, uint32_t kappa, uint32_t j, uint32_t m,
+                                    uint32_t& p, uint32_t& u, uint16_t*& buf, uint32_t& row,
+                                    uint32_t& rows) {
   if (MODE == MODE_ALL) {
     p = j;
     u = v.U[p];
-    row = v.cnt + (size_t)p * v.tp;
+    buf = v.cnt;
+    row = p;
+    rows = v.w * v.h;
   } else if (MODE == MODE_CLASS) {
     p = class_pixel(v, kappa, j);
     u = proposal(v, p, (uint32_t)v.ctr[0]);
-    row = v.c_new + (size_t)j * v.tp;
+    buf = v.c_new;
+    row = j;
+    rows = v.pc;
   } else {
     p = v.pix_list[j];
     u = v.u_new[j];
-    row = v.c_new + (size_t)j * v.tp;
+    buf = v.c_new;
+    row = j;
+    rows = m;
   }
 }
 
@@ -118,9 +135,9 @@ __global__ __launch_bounds__(256) void k_count_points(DevView v, uint32_t kappa,
   const uint32_t nch = (v.tp + tch - 1) / tch;
   const uint32_t j = wave / nch, ch = wave - j * nch;
   if (j >= m) return;
-  uint32_t p, u;
-  uint16_t* row;
-  count_target<MODE>(v, kappa, j, p, u, row);
+  uint32_t p, u, row, rows;
+  uint16_t* buf;
+  count_target<MODE>(v, kappa, j, m, p, u, buf, row, rows);
   if (MODE == MODE_CLASS && ch == 0 && lane == 0) v.u_new[j] = u;
 
   const uint32_t groups = v.n / (64u * PPL);
@@ -152,7 +169,7 @@ __global__ __launch_bounds__(256) void k_count_points(DevView v, uint32_t kappa,
         }
       }
     }
-    row[tb + lane] = (uint16_t)myc;
+    buf[tix(row, tb + lane, rows)] = (uint16_t)myc;
     if (MODE == MODE_ALL)
       v.err[(size_t)p * v.tp + tb + lane] = (float)myc * inv_n - v.area[tb + lane];
   }
@@ -167,15 +184,15 @@ __global__ __launch_bounds__(256) void k_count_integrands(DevView v, uint32_t ka
   const uint32_t nch = v.tp >> 6;
   const uint32_t j = wave / nch, ch = wave - j * nch;
   if (j >= m) return;
-  uint32_t p, u;
-  uint16_t* row;
-  count_target<MODE>(v, kappa, j, p, u, row);
+  uint32_t p, u, row, rows;
+  uint16_t* buf;
+  count_target<MODE>(v, kappa, j, m, p, u, buf, row, rows);
   if (MODE == MODE_CLASS && ch == 0 && lane == 0) v.u_new[j] = u;
   const uint32_t t = ch * 64 + lane;
   const int2 q = v.ihp[t];
   int c = 0;
   for (uint32_t i = 0; i < v.n; ++i) c += dot2((uint32_t)q.x, centre(wrap_add(v.lat[i], u)), 0) > q.y;
-  row[t] = (uint16_t)c;
+  buf[tix(row, t, rows)] = (uint16_t)c;
   if (MODE == MODE_ALL) v.err[(size_t)p * v.tp + t] = (float)c * (1.0f / (float)v.n) - v.area[t];
 }
 
@@ -225,8 +242,9 @@ struct WinConst {
 //   X_d = |class d| * Z0 - 2 Z_d,  Z0 = sum_t dc_t (c'_t + c_t),
 //   Z_d = sum_{o in class d} sum_t dc_t c_{p+o,t},  dc = c' - c,
 // all in exact integers.  One wave per moved pixel; a lane handles two
-// adjacent integrands, so each neighbour read is one 256-byte row segment and
-// each (neighbour, integrand pair) costs one v_dot2 of packed int16 pairs.
+// adjacent integrands and each (neighbour, integrand pair) costs one v_dot2 of
+// packed int16 pairs.  Used for explicit pixel lists; colour phases use the
+// LDS-staged kernel below.
 template <int R, int MODE>
 __global__ __launch_bounds__(256) void k_delta(DevView v, uint32_t kappa, uint32_t m) {
   constexpr Window<R> W = WinConst<R>::w;
@@ -242,8 +260,7 @@ __global__ __launch_bounds__(256) void k_delta(DevView v, uint32_t kappa, uint32
     rowq[i] = ((y + v.h + i - R) % v.h) * v.w;
     colq[i] = (x + v.w + i - R) % v.w;
   }
-  const uint16_t* cn_row = v.c_new + (size_t)j * v.tp;
-  const uint16_t* co_row = v.cnt + (size_t)p * v.tp;
+  const uint32_t P = v.w * v.h;
   long long z0 = 0;
   long long zd[NCLS];
 #pragma unroll
@@ -251,8 +268,8 @@ __global__ __launch_bounds__(256) void k_delta(DevView v, uint32_t kappa, uint32
 
   for (uint32_t base = 0; base < v.tp; base += 128) {
     const uint32_t t = base + 2 * lane;
-    const uint32_t cn = *(const uint32_t*)(cn_row + t);
-    const uint32_t co = *(const uint32_t*)(co_row + t);
+    const uint32_t cn = *(const uint32_t*)(v.c_new + tix(j, t, m));
+    const uint32_t co = *(const uint32_t*)(v.cnt + tix(p, t, P));
     const int n0 = (int)(cn & 0xFFFFu), n1 = (int)(cn >> 16);
     const int o0 = (int)(co & 0xFFFFu), o1 = (int)(co >> 16);
     const int dc0 = n0 - o0, dc1 = n1 - o1;
@@ -262,7 +279,7 @@ __global__ __launch_bounds__(256) void k_delta(DevView v, uint32_t kappa, uint32
 #pragma unroll
     for (int mm = 0; mm < W.M; ++mm) {
       const uint32_t q = rowq[W.oy[mm] + R] + colq[W.ox[mm] + R];
-      const uint32_t cq = *(const uint32_t*)(v.cnt + (size_t)q * v.tp + t);
+      const uint32_t cq = *(const uint32_t*)(v.cnt + tix(q, t, P));
       part = dot2(dcp, cq, part);
       if (mm == W.M - 1 || W.cls[mm + 1] != W.cls[mm]) {
         zd[W.cls[mm]] += part;
@@ -284,6 +301,176 @@ __global__ __launch_bounds__(256) void k_delta(DevView v, uint32_t kappa, uint32
   }
 }
 
+// LDS-staged energy change for one colour phase.  A workgroup owns a block of
+// 32 x BY class pixels (one per thread) and a slice of the integrands.  For
+// 16 integrands at a time it stages the counts of the block plus its window
+// halo into LDS (region of RH x RW pixels, one plane per integrand pair), and
+// the class pixels' recounted rows.  Region columns are stored grouped by
+// their residue mod K, so the 32 lanes of a class row read 32 consecutive
+// words for every window offset (no bank conflicts), and every offset is a
+// compile-time displacement from the thread's own word.  The integer class
+// sums of the slice are added into xsum[class][pixel] with 64-bit integer
+// atomics (exact, so the order of the slices does not matter);
+// k_delta_finish takes the decision and clears xsum for the next phase.
+template <int R, int K, int BY, int PAIRS_>
+struct StageGeom {
+  static constexpr int BX = 32;
+  static constexpr int RH = K * BY + 2 * R;
+  static constexpr int RW = ((K * BX + 2 * R + K - 1) / K) * K;
+  static constexpr int RWK = RW / K;
+  static constexpr int RA = RH * RW;           // words per integrand-pair plane
+  static constexpr int PAIRS = PAIRS_;         // integrand pairs per stage (4 or 8)
+  static constexpr int V4 = PAIRS / 4;         // 16-byte loads per pixel per stage
+  static constexpr int NB = BX * BY;           // class pixels per block
+  static constexpr int LDS_WORDS = PAIRS * RA + PAIRS * NB;
+  // word displacement of region position (K*ty + R + oy, K*tx + R + ox) from
+  // that of (K*ty + R, tx) in the residue-grouped layout
+  static constexpr int disp(int ox, int oy) {
+    return oy * RW + ((R + ox) % K) * RWK + (R + ox) / K;
+  }
+};
+
+template <int R, int K, int BY, int PAIRS>
+__global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kappa, uint32_t trlen,
+                                                         long long* __restrict__ xpart) {
+  using G = StageGeom<R, K, BY, PAIRS>;
+  constexpr Window<R> W = WinConst<R>::w;
+  constexpr int NCLS = WinConst<R>::NCLS;
+  extern __shared__ uint32_t lds[];
+  uint32_t* reg = lds;
+  uint32_t* cnb = lds + G::PAIRS * G::RA;
+  const uint32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const uint32_t a0 = blockIdx.y * BY, b0 = blockIdx.x * G::BX;
+  const uint32_t a = a0 + ty, b = b0 + tx;
+  const bool active = (a < v.ch) && (b < v.cw);
+  const uint32_t ky = kappa / K, kx = kappa - ky * K;
+  // top-left region pixel, made non-negative modulo the tile
+  const uint32_t ys = (ky + K * a0 + v.h * (R / v.h + 1) - R) % v.h;
+  const uint32_t xs = (kx + K * b0 + v.w * (R / v.w + 1) - R) % v.w;
+  const int own = (K * ty + R) * G::RW + (R % K) * G::RWK + tx + R / K;
+  const int base = (K * ty + R) * G::RW + tx;
+  const bool small_n = v.n <= 2048;
+
+  long long z0 = 0;
+  long long zd[NCLS];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) zd[c] = 0;
+
+  const uint32_t t_begin = blockIdx.z * trlen, t_end = min(t_begin + trlen, v.tp);
+  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 2 * G::PAIRS) {
+    __syncthreads();
+    {
+      // issue every staging load of this thread before the first LDS write
+      constexpr int NT = 32 * BY;
+      constexpr int ITER = (G::V4 * G::RA + NT - 1) / NT;
+      uint4 q[ITER];
+      uint32_t wi[ITER];
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        const uint32_t i = threadIdx.x + it * NT;
+        wi[it] = 0xFFFFFFFFu;
+        q[it] = make_uint4(0, 0, 0, 0);
+        if (i < (uint32_t)(G::V4 * G::RA)) {
+          const uint32_t pix = G::V4 == 1 ? i : (i >> 1), half = G::V4 == 1 ? 0 : (i & 1);
+          const uint32_t rr = pix / G::RW, cc = pix - rr * G::RW;
+          uint32_t gy = ys + rr, gx = xs + cc;
+          while (gy >= v.h) gy -= v.h;
+          while (gx >= v.w) gx -= v.w;
+          q[it] = *(const uint4*)(v.cnt + tix(gy * v.w + gx, t0 + 8 * half, v.w * v.h));
+          wi[it] = rr * G::RW + (cc % K) * G::RWK + cc / K + 4 * half * G::RA;
+        }
+      }
+      constexpr int ITC = (G::V4 * G::NB + NT - 1) / NT;
+      uint4 qc[ITC];
+#pragma unroll
+      for (int it = 0; it < ITC; ++it) {
+        const uint32_t i = threadIdx.x + it * NT;
+        const uint32_t cp = G::V4 == 1 ? i : (i >> 1), half = G::V4 == 1 ? 0 : (i & 1);
+        const uint32_t aa = a0 + cp / G::BX, bb = b0 + cp % G::BX;
+        qc[it] = make_uint4(0, 0, 0, 0);
+        if (i < (uint32_t)(G::V4 * G::NB) && aa < v.ch && bb < v.cw)
+          qc[it] = *(const uint4*)(v.c_new + tix(aa * v.cw + bb, t0 + 8 * half, v.pc));
+      }
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        if (wi[it] != 0xFFFFFFFFu) {
+          reg[wi[it]] = q[it].x;
+          reg[wi[it] + G::RA] = q[it].y;
+          reg[wi[it] + 2 * G::RA] = q[it].z;
+          reg[wi[it] + 3 * G::RA] = q[it].w;
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < ITC; ++it) {
+        const uint32_t i = threadIdx.x + it * NT;
+        if (i < (uint32_t)(G::V4 * G::NB)) {
+          const uint32_t cp = G::V4 == 1 ? i : (i >> 1), half = G::V4 == 1 ? 0 : (i & 1);
+          const uint32_t wc = cp + 4 * half * G::NB;
+          cnb[wc] = qc[it].x;
+          cnb[wc + G::NB] = qc[it].y;
+          cnb[wc + 2 * G::NB] = qc[it].z;
+          cnb[wc + 3 * G::NB] = qc[it].w;
+        }
+      }
+    }
+    __syncthreads();
+    if (active) {
+      int z0p = 0;
+      int part[NCLS];
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) part[c] = 0;
+#pragma unroll
+      for (int tp = 0; tp < G::PAIRS; ++tp) {
+        const uint32_t cn = cnb[tp * G::NB + threadIdx.x];
+        const uint32_t co = reg[tp * G::RA + own];
+        const int n0 = (int)(cn & 0xFFFFu), n1 = (int)(cn >> 16);
+        const int o0 = (int)(co & 0xFFFFu), o1 = (int)(co >> 16);
+        const int dc0 = n0 - o0, dc1 = n1 - o1;
+        const uint32_t dcp = ((uint32_t)dc0 & 0xFFFFu) | ((uint32_t)dc1 << 16);
+        z0p += dc0 * (n0 + o0) + dc1 * (n1 + o1);
+#pragma unroll
+        for (int mm = 0; mm < W.M; ++mm) {
+          const uint32_t cq = reg[tp * G::RA + base + G::disp(W.ox[mm], W.oy[mm])];
+          part[W.cls[mm]] = dot2(dcp, cq, part[W.cls[mm]]);
+        }
+        if (!small_n) {
+#pragma unroll
+          for (int c = 0; c < NCLS; ++c) {
+            zd[c] += part[c];
+            part[c] = 0;
+          }
+          z0 += z0p;
+          z0p = 0;
+        }
+      }
+      z0 += z0p;
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) zd[c] += part[c];
+    }
+  }
+  if (active) {
+    const uint32_t j = a * v.cw + b;
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c)
+      atomicAdd((unsigned long long*)&xpart[(size_t)c * v.pc + j],
+                (unsigned long long)((long long)W.csize[c] * z0 - 2 * zd[c]));
+  }
+}
+
+// Decide from the summed class sums (one thread per pixel) and clear them.
+__global__ __launch_bounds__(256) void k_delta_finish(DevView v, long long* __restrict__ xsum) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= v.pc) return;
+  double acc = 0.0;
+  for (uint32_t c = 0; c < v.ncls; ++c) {
+    const long long x = xsum[(size_t)c * v.pc + j];
+    xsum[(size_t)c * v.pc + j] = 0;
+    acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)x));
+  }
+  v.delta[j] = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+  v.accept[j] = (v.objective > 0) ? (acc < 0.0) : (acc > 0.0);
+}
+
 // ------------------------------------------------------------------ commit
 // Accepted moves of the phase become the state (Sec. 3.4): offset, hit
 // counts and FP32 errors of the pixel.
@@ -296,24 +483,23 @@ __global__ __launch_bounds__(256) void k_commit(DevView v, uint32_t kappa) {
     v.U[p] = v.u_new[j];
     atomicAdd(&v.ctr[1], 1ull);
   }
-  const uint16_t* src = v.c_new + (size_t)j * v.tp;
-  uint16_t* dst = v.cnt + (size_t)p * v.tp;
+  const uint32_t P = v.w * v.h;
   float* e = v.err + (size_t)p * v.tp;
   const float inv_n = 1.0f / (float)v.n;
-  for (uint32_t t = lane * 8; t < v.tp; t += 512) {
-    const uint4 c8 = *(const uint4*)(src + t);
-    *(uint4*)(dst + t) = c8;
-    const uint32_t w4[4] = {c8.x, c8.y, c8.z, c8.w};
-    float4 a = *(const float4*)(v.area + t), b = *(const float4*)(v.area + t + 4);
+  for (uint32_t tt = lane; tt < (v.tp >> 3); tt += 64) {
+    const uint4 c8 = *(const uint4*)(v.c_new + ((size_t)tt * v.pc + j) * 8);
+    *(uint4*)(v.cnt + ((size_t)tt * P + p) * 8) = c8;
+    const uint32_t t = tt * 8;
+    const float4 a = *(const float4*)(v.area + t), b = *(const float4*)(v.area + t + 4);
     float4 lo, hi;
-    lo.x = (float)(w4[0] & 0xFFFFu) * inv_n - a.x;
-    lo.y = (float)(w4[0] >> 16) * inv_n - a.y;
-    lo.z = (float)(w4[1] & 0xFFFFu) * inv_n - a.z;
-    lo.w = (float)(w4[1] >> 16) * inv_n - a.w;
-    hi.x = (float)(w4[2] & 0xFFFFu) * inv_n - b.x;
-    hi.y = (float)(w4[2] >> 16) * inv_n - b.y;
-    hi.z = (float)(w4[3] & 0xFFFFu) * inv_n - b.z;
-    hi.w = (float)(w4[3] >> 16) * inv_n - b.w;
+    lo.x = (float)(c8.x & 0xFFFFu) * inv_n - a.x;
+    lo.y = (float)(c8.x >> 16) * inv_n - a.y;
+    lo.z = (float)(c8.y & 0xFFFFu) * inv_n - a.z;
+    lo.w = (float)(c8.y >> 16) * inv_n - a.w;
+    hi.x = (float)(c8.z & 0xFFFFu) * inv_n - b.x;
+    hi.y = (float)(c8.z >> 16) * inv_n - b.y;
+    hi.z = (float)(c8.w & 0xFFFFu) * inv_n - b.z;
+    hi.w = (float)(c8.w >> 16) * inv_n - b.w;
     *(float4*)(e + t) = lo;
     *(float4*)(e + t + 4) = hi;
   }
@@ -352,17 +538,17 @@ __global__ __launch_bounds__(256) void k_energy(DevView v, unsigned long long* y
   long long yd[NCLS];
 #pragma unroll
   for (int c = 0; c < NCLS; ++c) yd[c] = 0;
-  const uint16_t* prow = v.cnt + (size_t)p * v.tp;
+  const uint32_t P = v.w * v.h;
   for (uint32_t base = 0; base < v.tp; base += 128) {
     const uint32_t t = base + 2 * lane;
-    const uint32_t cp = *(const uint32_t*)(prow + t);
+    const uint32_t cp = *(const uint32_t*)(v.cnt + tix(p, t, P));
     int part = 0;
 #pragma unroll
     for (int mm = 0; mm < W.M; ++mm) {
       const bool half = W.oy[mm] > 0 || (W.oy[mm] == 0 && W.ox[mm] > 0);
       if (half) {
         const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
-        const uint32_t cq = *(const uint32_t*)(v.cnt + (size_t)q * v.tp + t);
+        const uint32_t cq = *(const uint32_t*)(v.cnt + tix(q, t, P));
         const int d0 = (int)(cp & 0xFFFFu) - (int)(cq & 0xFFFFu);
         const int d1 = (int)(cp >> 16) - (int)(cq >> 16);
         const uint32_t dp = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
@@ -472,6 +658,47 @@ hipError_t delta_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
   return hipGetLastError();
 }
 
+// Integrand slices for the staged kernel: enough workgroups to fill the chip.
+// Integrand slices: about 512 workgroups in total, each slice a whole number
+// of 16-integrand stages.
+inline uint32_t stage_slices(const DevView& v, uint32_t blocks, uint32_t* trlen) {
+  const uint32_t chunks = v.tp / 16;
+  uint32_t want = (512 + blocks - 1) / blocks;
+  if (want > chunks) want = chunks;
+  const uint32_t per = (chunks + want - 1) / want;
+  *trlen = per * 16;
+  return (chunks + per - 1) / per;
+}
+
+template <int R, int K, int BY>
+hipError_t stage_launch(const DevView& v, uint32_t kappa, long long* xpart, hipStream_t s) {
+  // 4 integrand pairs per stage: about 32 KiB of LDS per block, so several
+  // blocks share a CU and one block's staging overlaps another's compute
+  using G = StageGeom<R, K, BY, 4>;
+  static_assert(G::LDS_WORDS * 4 <= 65536, "staged block exceeds 64 KiB of LDS");
+  uint32_t trlen = 0;
+  const uint32_t blocks = ((v.cw + G::BX - 1) / G::BX) * ((v.ch + BY - 1) / BY);
+  const uint32_t ns = stage_slices(v, blocks, &trlen);
+  const dim3 grid((v.cw + G::BX - 1) / G::BX, (v.ch + BY - 1) / BY, ns);
+  const size_t lds = (size_t)G::LDS_WORDS * 4;
+  hipLaunchKernelGGL((k_delta_stage<R, K, BY, G::PAIRS>), grid, dim3(32 * BY), lds, s, v, kappa, trlen,
+                     xpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_delta_finish, dim3((v.pc + 255) / 256), dim3(256), 0, s, v, xpart);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t stage_by_k(const DevView& v, uint32_t kappa, long long* xpart, hipStream_t s) {
+  switch (v.k) {
+    case 1: return stage_launch<R, 1, 8>(v, kappa, xpart, s);
+    case 2: return stage_launch<R, 2, 8>(v, kappa, xpart, s);
+    case 4: return stage_launch<R, 4, 2>(v, kappa, xpart, s);
+    default: return delta_dispatch<MODE_CLASS>(v, kappa, v.pc, s);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_init_offsets(const DevView& v, hipStream_t s) {
@@ -489,9 +716,22 @@ hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
 }
 
 hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
+  if (mode == MODE_CLASS && v.xpart) {
+    switch (v.radius) {
+      case 1: return stage_by_k<1>(v, kappa, v.xpart, s);
+      case 2: return stage_by_k<2>(v, kappa, v.xpart, s);
+      case 3: return stage_by_k<3>(v, kappa, v.xpart, s);
+      case 4: return stage_by_k<4>(v, kappa, v.xpart, s);
+      case 5: return stage_by_k<5>(v, kappa, v.xpart, s);
+      case 6: return stage_by_k<6>(v, kappa, v.xpart, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   return mode == MODE_CLASS ? delta_dispatch<MODE_CLASS>(v, kappa, m, s)
                             : delta_dispatch<MODE_LIST>(v, kappa, m, s);
 }
+
+uint32_t xpart_words(const DevView& v) { return v.ncls * v.pc; }
 
 hipError_t launch_commit(const DevView& v, uint32_t kappa, hipStream_t s) {
   hipLaunchKernelGGL(k_commit, dim3((v.pc + 3) / 4), dim3(256), 0, s, v, kappa);

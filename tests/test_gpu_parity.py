@@ -41,6 +41,9 @@ EDGE = {
     "k4_conflict_free": workload(colour_k=4, width=16, height=16, radius=3),
     "rect_ascend": workload(width=12, height=8, radius=3, objective=-1),
     "r6": workload(width=16, height=16, radius=6, n=64, g=(1, 19), t_heaviside=20),
+    "n4096": workload(n=4096, g=(1, 1365), t_heaviside=40, width=8, height=8, radius=2),
+    "k4_r6": workload(colour_k=4, width=16, height=16, radius=6, t_heaviside=150),
+    "wide64": workload(width=64, height=32, radius=4, n=64, g=(1, 19), t_heaviside=140),
 }
 
 
@@ -99,7 +102,8 @@ def test_drawn_integrands_used_when_none_given():
 
 
 @pytest.mark.parametrize("name", ["n4_ragged", "n256_r4", "tile4_alias", "k4_conflict_free",
-                                  "rect_ascend", "n1024_r5", "tile32_n16_t64"])
+                                  "rect_ascend", "n1024_r5", "tile32_n16_t64", "r6", "n4096",
+                                  "k4_r6", "wide64", "k1"])
 def test_phase_steps_match_oracle(name):
     """Every step of two sweeps' phases: proposals, recounts, energy changes,
     decisions and the committed state."""
