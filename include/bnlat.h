@@ -186,14 +186,23 @@ bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* d
 /* ----------------------------------------------------------------- batching */
 
 /* Independent problems (e.g. the dimension pairs of a padded sampler,
- * Sec. 3.1) swept together: each colour step of every member runs in one
- * launch per kernel, and k sweeps are replayed from one captured HIP graph.
- * All members must share one stream.  tune_cache (nullable) names a file
- * holding the launch choices of the tuner.  Members stay owned by the caller
- * and must outlive the batch. */
+ * Sec. 3.1) swept together: for each colour class, one launch per kernel
+ * variant covers every member (members grouped by samples-per-pixel class for
+ * counting and by window radius for the energy change), and a whole sweep of
+ * all members is captured once as a HIP graph and replayed k times.  Each
+ * member's trajectory equals the one bn_sweep gives it alone.  Requirements:
+ * members distinct, created on one stream, bn_compute_errors done, one common
+ * colour_k in {1, 2, 4}, FP32 precision.  tune_cache (nullable) names a text
+ * file of launch choices keyed by the members' shapes; when the key is absent
+ * the tuner times the candidates on the device (propose + evaluate only, no
+ * state change) and appends its choice.  Members stay owned by the caller and
+ * must outlive the batch; do not sweep them individually while batched. */
 bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tune_cache,
                           bn_batch* out);
 bn_status bn_batch_sweep(bn_batch b, uint32_t k);
+/* Launch choices the tuner picked (integrands per counting wave, workgroup
+ * target of the staged energy-change launch); no device work. */
+bn_status bn_batch_tuning(bn_batch b, uint32_t* tch, uint32_t* slice_target);
 bn_status bn_destroy_batch(bn_batch b);
 
 /* ------------------------------------------------ host-only (no device work) */

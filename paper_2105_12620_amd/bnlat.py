@@ -71,6 +71,7 @@ _SIGNATURES = {
     "bn_create_batch": [_P, C.c_uint32, C.c_char_p, C.POINTER(_P)],
     "bn_batch_sweep": [_P, C.c_uint32],
     "bn_destroy_batch": [_P],
+    "bn_batch_tuning": [_P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)],
     "bn_validate_config": [C.POINTER(Config)],
     "bn_window_classes": [C.POINTER(Config), C.POINTER(C.c_uint32), _P, _P],
     "bn_heaviside_area": [C.POINTER(Heaviside), C.POINTER(C.c_double)],
@@ -279,6 +280,43 @@ class Problem:
         a = np.zeros(self.M, dtype=np.uint8)
         _call("bn_get_phase", self.handle, _ptr(u), _ptr(c), _ptr(d), _ptr(a))
         return {"u_new": u, "c_new": c, "delta": d, "accept": a.astype(bool)}
+
+
+class Batch:
+    """Owns one ``bn_batch`` over existing problems (which must outlive it)."""
+
+    def __init__(self, problems, tune_cache: str | None = None):
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p.handle.value for p in self.problems])
+        handle = C.c_void_p()
+        _call("bn_create_batch", arr, len(self.problems),
+              None if tune_cache is None else tune_cache.encode(), C.byref(handle))
+        self.handle = handle
+
+    def sweep(self, k: int = 1):
+        _call("bn_batch_sweep", self.handle, k)
+
+    def tuning(self):
+        a, b = C.c_uint32(), C.c_uint32()
+        _call("bn_batch_tuning", self.handle, C.byref(a), C.byref(b))
+        return {"tch": a.value, "slice_target": b.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _call("bn_destroy_batch", self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def create_problem(workload: dict, heavisides=None, stream=None, **overrides) -> Problem:

@@ -188,8 +188,33 @@ struct bn_problem_s {
   }
 };
 
+// A group of batch members served by one launch of one kernel variant.
+struct BatchGroup {
+  int kind = 0;               // counting-kernel variant (samples per lane; 0 = integrand lanes)
+  uint32_t radius = 0, k = 0; // staged energy-change variant
+  std::vector<uint32_t> idx;  // member indices
+  DevView* d_views = nullptr;
+  uint32_t* d_pre = nullptr;  // block prefix sums, idx.size() + 1 entries
+  uint32_t* d_geo = nullptr;  // per member (gx, gy, slice length) for the staged kernel
+  uint32_t blocks = 0;
+};
+
 struct bn_batch_s {
   std::vector<bn_problem> members;
+  hipStream_t stream = nullptr;
+  uint32_t colour_k = 0;
+  std::vector<BatchGroup> count_groups, stage_groups;
+  BatchGroup finish_all, commit_all;
+  std::vector<void*> allocs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  uint32_t tch = 256, slice_target = 512;
+  ~bn_batch_s() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* q : allocs) (void)hipFree(q);
+  }
 };
 
 namespace {
@@ -219,7 +244,8 @@ bn_status supported(const bn_config* c) {
   if (c->n > MAX_N) return fail(BN_EUNSUPPORTED, "N > %u is not supported by this build", MAX_N);
   if (c->radius > 6) return fail(BN_EUNSUPPORTED, "radius > 6 is not supported by this build");
   if (c->t_gauss) return fail(BN_EUNSUPPORTED, "Gaussian integrands are not supported by this build");
-  if (c->precision != BN_FP32) return fail(BN_EUNSUPPORTED, "BF16 precision is not supported by this build");
+  if (c->precision == BN_BF16 && c->colour_k != 2)
+    return fail(BN_EUNSUPPORTED, "the BF16 matrix-core form needs colour_k = 2");
   if (c->move != BN_REDRAW) return fail(BN_EUNSUPPORTED, "swap moves are not supported by this build");
   return BN_OK;
 }
@@ -309,6 +335,147 @@ bn_status build_graph(bn_problem p) {
   }
   p->graph = g;
   return BN_OK;
+}
+
+
+// (Re)build the per-group device tables from the members' current launch
+// choices.  Invalidates any captured graph.
+bn_status batch_upload(bn_batch b) {
+  if (b->graph_exec) {
+    (void)hipGraphExecDestroy(b->graph_exec);
+    b->graph_exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (void* q : b->allocs) (void)hipFree(q);
+  b->allocs.clear();
+  for (bn_problem p : b->members) {
+    p->v.tch = std::min<uint32_t>(b->tch, p->v.tp);
+    p->v.slice_target = b->slice_target;
+  }
+  auto upload = [&](BatchGroup& g, auto blocks_of, bool geo) -> bn_status {
+    std::vector<DevView> views;
+    std::vector<uint32_t> pre(1, 0), gv;
+    for (uint32_t i : g.idx) {
+      const DevView& v = b->members[i]->v;
+      views.push_back(v);
+      uint32_t gx = 0, gy = 0, gz = 0, trl = 0;
+      if (geo) {
+        stage_geometry(v, &gx, &gy, &gz, &trl);
+        gv.push_back(gx);
+        gv.push_back(gy);
+        gv.push_back(trl);
+        pre.push_back(pre.back() + gx * gy * gz);
+      } else {
+        pre.push_back(pre.back() + blocks_of(v));
+      }
+    }
+    g.blocks = pre.back();
+    void *dv = nullptr, *dp = nullptr, *dg = nullptr;
+    if (hipMalloc(&dv, views.size() * sizeof(DevView)) != hipSuccess ||
+        hipMalloc(&dp, pre.size() * 4) != hipSuccess || hipMalloc(&dg, std::max<size_t>(gv.size(), 1) * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      if (dv) (void)hipFree(dv);
+      if (dp) (void)hipFree(dp);
+      if (dg) (void)hipFree(dg);
+      return fail(BN_ENOMEM, "batch tables");
+    }
+    b->allocs.push_back(dv);
+    b->allocs.push_back(dp);
+    b->allocs.push_back(dg);
+    g.d_views = (DevView*)dv;
+    g.d_pre = (uint32_t*)dp;
+    g.d_geo = (uint32_t*)dg;
+    HIPCHK(hipMemcpy(dv, views.data(), views.size() * sizeof(DevView), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dp, pre.data(), pre.size() * 4, hipMemcpyHostToDevice));
+    if (!gv.empty()) HIPCHK(hipMemcpy(dg, gv.data(), gv.size() * 4, hipMemcpyHostToDevice));
+    return BN_OK;
+  };
+  bn_status s;
+  for (BatchGroup& g : b->count_groups)
+    if ((s = upload(g, [](const DevView& v) { return count_blocks(v); }, false)) != BN_OK) return s;
+  for (BatchGroup& g : b->stage_groups)
+    if ((s = upload(g, [](const DevView&) { return 0u; }, true)) != BN_OK) return s;
+  if ((s = upload(b->finish_all, [](const DevView& v) { return (v.pc + 255) / 256; }, false)) != BN_OK) return s;
+  if ((s = upload(b->commit_all, [](const DevView& v) { return (v.pc + 3) / 4; }, false)) != BN_OK) return s;
+  return BN_OK;
+}
+
+bn_status batch_evaluate(bn_batch b, uint32_t kappa) {
+  for (BatchGroup& g : b->count_groups)
+    HIPCHK(launch_count_batch(g.kind, g.d_views, g.d_pre, (uint32_t)g.idx.size(), g.blocks, kappa, b->stream));
+  for (BatchGroup& g : b->stage_groups)
+    HIPCHK(launch_stage_batch(g.radius, g.k, g.d_views, g.d_pre, g.d_geo, (uint32_t)g.idx.size(), g.blocks,
+                              kappa, b->stream));
+  HIPCHK(launch_finish_batch(b->finish_all.d_views, b->finish_all.d_pre, (uint32_t)b->finish_all.idx.size(),
+                             b->finish_all.blocks, b->stream));
+  return BN_OK;
+}
+
+bn_status batch_record_sweep(bn_batch b) {
+  for (uint32_t kappa = 0; kappa < b->colour_k * b->colour_k; ++kappa) {
+    bn_status s = batch_evaluate(b, kappa);
+    if (s != BN_OK) return s;
+    HIPCHK(launch_commit_batch(b->commit_all.d_views, b->commit_all.d_pre, (uint32_t)b->commit_all.idx.size(),
+                               b->commit_all.blocks, kappa, b->stream));
+  }
+  HIPCHK(launch_advance_batch(b->commit_all.d_views, (uint32_t)b->commit_all.idx.size(), b->stream));
+  return BN_OK;
+}
+
+std::string batch_key(bn_batch b) {
+  std::string key = "K" + std::to_string(b->colour_k);
+  for (bn_problem p : b->members) {
+    const DevView& v = p->v;
+    key += ":n" + std::to_string(v.n) + "w" + std::to_string(v.w) + "h" + std::to_string(v.h) + "t" +
+           std::to_string(v.t) + "r" + std::to_string(v.radius);
+  }
+  return key;
+}
+
+// Launch-shape tuner: times one colour class's propose + evaluate (no commit,
+// so the optimisation state is untouched) for each candidate and keeps the
+// fastest.  Results do not depend on the choice.
+bn_status batch_tune(bn_batch b) {
+  static const uint32_t tchs[] = {64, 128, 256, 512};
+  static const uint32_t slices[] = {256, 512, 1024, 2048};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  uint32_t bt = b->tch, bs = b->slice_target;
+  bn_status s = BN_OK;
+  for (uint32_t tc : tchs) {
+    for (uint32_t sl : slices) {
+      b->tch = tc;
+      b->slice_target = sl;
+      if ((s = batch_upload(b)) != BN_OK) break;
+      if ((s = batch_evaluate(b, 0)) != BN_OK) break;   // warm-up
+      if (hipEventRecord(e0, b->stream) != hipSuccess) { s = fail(BN_EHIP, "event record"); break; }
+      if ((s = batch_evaluate(b, 0)) != BN_OK) break;
+      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        s = fail(BN_EHIP, "event timing");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        bt = tc;
+        bs = sl;
+      }
+    }
+    if (s != BN_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != BN_OK) return s;
+  b->tch = bt;
+  b->slice_target = bs;
+  return batch_upload(b);
 }
 
 }  // namespace
@@ -415,6 +582,7 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   v.t = cfg->t_heaviside;
   v.tp = round_up(v.t, T_ALIGN);
   v.k = cfg->colour_k;
+  v.tch = 0;
   v.cw = cfg->width / cfg->colour_k;
   v.ch = cfg->height / cfg->colour_k;
   v.pc = v.cw * v.ch;
@@ -424,6 +592,8 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   v.objective = cfg->objective;
   v.radius = cfg->radius;
   v.ncls = (uint32_t)p->cls_d.size();
+  v.tch = std::min<uint32_t>(256, v.tp);
+  v.slice_target = 512;
   const size_t P = (size_t)v.w * v.h;
 
   std::vector<uint32_t> lat(v.n);
@@ -451,7 +621,8 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
       (s = p->alloc(&v.U, P)) != BN_OK || (s = p->alloc(&v.cnt, P * v.tp)) != BN_OK ||
       (s = p->alloc(&v.err, P * v.tp)) != BN_OK || (s = p->alloc(&v.u_new, v.pc)) != BN_OK ||
       (s = p->alloc(&v.c_new, (size_t)v.pc * v.tp)) != BN_OK || (s = p->alloc(&v.delta, v.pc)) != BN_OK ||
-      (s = p->alloc(&v.accept, v.pc)) != BN_OK || (s = p->alloc(&v.ctr, 2)) != BN_OK ||
+      (s = p->alloc(&v.accept, v.pc)) != BN_OK || (s = p->alloc(&v.ctr, 4)) != BN_OK ||
+      (s = p->alloc(&v.unsure, v.pc)) != BN_OK ||
       (s = p->alloc(&p->ysum, v.ncls)) != BN_OK || (s = p->alloc(&v.xpart, xpart_words(v))) != BN_OK) {
     delete p;
     return s;
@@ -461,7 +632,8 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   v.area = area_d;
   v.wd = wd_d;
   v.pix_list = nullptr;
-  const unsigned long long zero[2] = {0ull, 0ull};
+  const unsigned long long zero[4] = {0ull, 0ull, 0ull, 0ull};
+  v.mfma = cfg->precision == BN_BF16 ? 1u : 0u;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemcpyAsync(lat_d, lat.data(), v.n * 4, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(ihp_d, ihp.data(), v.tp * 8, hipMemcpyHostToDevice, p->stream);
@@ -469,6 +641,7 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   if (e == hipSuccess) e = hipMemcpyAsync(wd_d, p->cls_w.data(), v.ncls * 8, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(v.ctr, zero, sizeof zero, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemsetAsync(v.xpart, 0, (size_t)xpart_words(v) * 8, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(v.unsure, 0, (size_t)v.pc * 4, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) {
     delete p;
@@ -510,7 +683,7 @@ bn_status bn_compute_errors(bn_problem p) {
 bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run before bn_sweep");
-  unsigned long long before[2] = {0, 0}, after[2] = {0, 0};
+  unsigned long long before[3] = {0, 0, 0}, after[3] = {0, 0, 0};
   if (stats) {
     HIPCHK(hipMemcpyAsync(before, p->v.ctr, sizeof before, hipMemcpyDeviceToHost, p->stream));
     bn_status s = sync(p);
@@ -531,7 +704,7 @@ bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats) {
     if ((s = sync(p)) != BN_OK) return s;
     stats->proposals = (uint64_t)k * p->v.w * p->v.h;
     stats->accepts = after[1] - before[1];
-    stats->bf16_vetoes = 0;
+    stats->bf16_vetoes = after[2] - before[2];
     stats->sweep_index = after[0];
   }
   return BN_OK;
@@ -742,20 +915,112 @@ bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* d
 }
 
 bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tune_cache, bn_batch* out) {
-  (void)members;
-  (void)m;
-  (void)tune_cache;
-  (void)out;
-  return fail(BN_EUNSUPPORTED, "batches are not supported by this build");
+  if (!members || !out || m == 0) return fail(BN_EINVAL, "members and out must be non-NULL, m >= 1");
+  *out = nullptr;
+  for (uint32_t i = 0; i < m; ++i) {
+    bn_problem p = members[i];
+    if (!p) return fail(BN_EINVAL, "member %u is NULL", i);
+    if (!p->have_counts) return fail(BN_ESTATE, "member %u: bn_compute_errors must run first", i);
+    if (p->stream != members[0]->stream) return fail(BN_EINVAL, "members must share one stream");
+    if (p->cfg.colour_k != members[0]->cfg.colour_k) return fail(BN_EINVAL, "members must share colour_k");
+    if (p->cfg.precision != BN_FP32) return fail(BN_EUNSUPPORTED, "batched members must use FP32 precision");
+    for (uint32_t j = 0; j < i; ++j)
+      if (members[j] == p) return fail(BN_EINVAL, "member %u appears twice", i);
+  }
+  const uint32_t K = members[0]->cfg.colour_k;
+  if (K != 1 && K != 2 && K != 4) return fail(BN_EUNSUPPORTED, "batched sweeps need colour_k in {1, 2, 4}");
+  bn_batch b = new bn_batch_s();
+  b->members.assign(members, members + m);
+  b->stream = members[0]->stream;
+  b->colour_k = K;
+  for (uint32_t i = 0; i < m; ++i) {
+    const DevView& v = members[i]->v;
+    const int kind = count_kind(v);
+    auto cg = std::find_if(b->count_groups.begin(), b->count_groups.end(), [&](const BatchGroup& g) { return g.kind == kind; });
+    if (cg == b->count_groups.end()) {
+      b->count_groups.push_back(BatchGroup());
+      b->count_groups.back().kind = kind;
+      cg = b->count_groups.end() - 1;
+    }
+    cg->idx.push_back(i);
+    auto sg = std::find_if(b->stage_groups.begin(), b->stage_groups.end(), [&](const BatchGroup& g) { return g.radius == v.radius; });
+    if (sg == b->stage_groups.end()) {
+      b->stage_groups.push_back(BatchGroup());
+      b->stage_groups.back().radius = v.radius;
+      b->stage_groups.back().k = K;
+      sg = b->stage_groups.end() - 1;
+    }
+    sg->idx.push_back(i);
+    b->finish_all.idx.push_back(i);
+    b->commit_all.idx.push_back(i);
+  }
+  // launch choices: cached, else tuned on the device
+  bool cached = false;
+  const std::string key = batch_key(b);
+  if (tune_cache) {
+    if (FILE* f = std::fopen(tune_cache, "r")) {
+      char line[8192];
+      while (std::fgets(line, sizeof line, f)) {
+        char k[4096];
+        unsigned tc = 0, sl = 0;
+        if (std::sscanf(line, "%4095s tch=%u slices=%u", k, &tc, &sl) == 3 && key == k && tc && sl) {
+          b->tch = tc;
+          b->slice_target = sl;
+          cached = true;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  bn_status s = cached ? batch_upload(b) : batch_tune(b);
+  if (s != BN_OK) {
+    delete b;
+    return s;
+  }
+  if (tune_cache && !cached) {
+    if (FILE* f = std::fopen(tune_cache, "a")) {
+      std::fprintf(f, "%s tch=%u slices=%u\n", key.c_str(), b->tch, b->slice_target);
+      std::fclose(f);
+    }
+  }
+  *out = b;
+  return BN_OK;
 }
 
 bn_status bn_batch_sweep(bn_batch b, uint32_t k) {
-  (void)b;
-  (void)k;
-  return fail(BN_EUNSUPPORTED, "batches are not supported by this build");
+  if (!b) return fail(BN_EINVAL, "NULL batch");
+  if (!b->graph_exec) {
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    bn_status s = batch_record_sweep(b);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (s != BN_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(BN_EHIP, "batch graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      b->graph_exec = nullptr;
+      return fail(BN_EHIP, "batch graph instantiate: %s", hipGetErrorString(e));
+    }
+    b->graph = g;
+  }
+  for (uint32_t i = 0; i < k; ++i) HIPCHK(hipGraphLaunch(b->graph_exec, b->stream));
+  for (bn_problem p : b->members) p->sweep += k;
+  return BN_OK;
+}
+
+bn_status bn_batch_tuning(bn_batch b, uint32_t* tch, uint32_t* slice_target) {
+  if (!b) return fail(BN_EINVAL, "NULL batch");
+  if (tch) *tch = b->tch;
+  if (slice_target) *slice_target = b->slice_target;
+  return BN_OK;
 }
 
 bn_status bn_destroy_batch(bn_batch b) {
+  if (!b) return fail(BN_EINVAL, "NULL batch");
   delete b;
   return BN_OK;
 }

@@ -37,8 +37,12 @@ struct DevView {
   double* delta;             // [M] energy change
   uint8_t* accept;           // [M] decision
   const uint32_t* pix_list;  // [M] pixels (list mode)
-  unsigned long long* ctr;   // [0] sweep index, [1] accepted total
+  unsigned long long* ctr;   // [0] sweep index, [1] accepted total, [2] BF16 vetoes
   long long* xpart;          // [ncls][pc] integer class sums of the staged evaluation (kept zero between phases)
+  uint32_t* unsure;          // [pc] matrix-core results not certified exact (kept zero between phases)
+  uint32_t mfma;             // 1: BF16 matrix-core evaluation of the colour phases
+  uint32_t tch;              // integrands per wave in the counting kernels (launch shape)
+  uint32_t slice_target;     // workgroups the staged energy-change launch aims for
 };
 
 hipError_t launch_init_offsets(const DevView& v, hipStream_t s);
@@ -53,5 +57,21 @@ hipError_t launch_blur(const DevView& v, const float* kx, uint32_t nkx, const in
                        const float* ky, uint32_t nky, const int32_t* dy, float* tmp,
                        double* partial, uint32_t* npartial, hipStream_t s);
 uint32_t blur_partials(const DevView& v);
+
+// batched launches: member i of a group owns blocks pre[i] .. pre[i+1]-1
+int count_kind(const DevView& v);
+uint32_t count_blocks(const DevView& v);
+uint32_t stage_by(uint32_t k);
+void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen);
+hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
+                              uint32_t blocks, uint32_t kappa, hipStream_t s);
+hipError_t launch_stage_batch(uint32_t radius, uint32_t k, const DevView* views, const uint32_t* pre,
+                              const uint32_t* geo, uint32_t nmem, uint32_t blocks, uint32_t kappa,
+                              hipStream_t s);
+hipError_t launch_finish_batch(const DevView* views, const uint32_t* pre, uint32_t nmem, uint32_t blocks,
+                               hipStream_t s);
+hipError_t launch_commit_batch(const DevView* views, const uint32_t* pre, uint32_t nmem, uint32_t blocks,
+                               uint32_t kappa, hipStream_t s);
+hipError_t launch_advance_batch(const DevView* views, uint32_t nmem, hipStream_t s);
 
 }  // namespace bnlat

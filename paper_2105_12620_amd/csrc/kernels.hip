@@ -22,6 +22,9 @@
 
 #include "bnlat_dev.h"
 
+// v_writelane_b32: write a wave-uniform value into one lane of a register.
+extern "C" __device__ int bnlat_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace bnlat {
 namespace {
 
@@ -128,10 +131,11 @@ __device__ inline void count_target(const DevView& v, uint32_t kappa, uint32_t j
 // and stored as one coalesced 128-byte row segment.  N > 64*PPL is handled
 // in groups of 64*PPL samples.
 template <int PPL, int MODE>
-__global__ __launch_bounds__(256) void k_count_points(DevView v, uint32_t kappa, uint32_t m,
-                                                      uint32_t tch) {
+__device__ __forceinline__ void count_points_body(const DevView& v, const int2* __restrict__ ihp,
+                                                  uint32_t kappa, uint32_t m, uint32_t tch,
+                                                  uint32_t blk) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = wave_id();
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
   const uint32_t nch = (v.tp + tch - 1) / tch;
   const uint32_t j = wave / nch, ch = wave - j * nch;
   if (j >= m) return;
@@ -142,14 +146,12 @@ __global__ __launch_bounds__(256) void k_count_points(DevView v, uint32_t kappa,
 
   const uint32_t groups = v.n / (64u * PPL);
   uint32_t sp[PPL];
-  if (groups == 1) {
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) sp[k] = centre(wrap_add(v.lat[lane + 64 * k], u));
-  }
+  for (int k = 0; k < PPL; ++k) sp[k] = centre(wrap_add(v.lat[lane + 64 * k], u));
   const float inv_n = 1.0f / (float)v.n;
   const uint32_t t0 = ch * tch, t1 = min(t0 + tch, v.tp);
   for (uint32_t tb = t0; tb < t1; tb += 64) {
-    int myc = 0;
+    int total = 0;
     if (tb < v.t) {
       for (uint32_t g = 0; g < groups; ++g) {
         if (groups > 1) {
@@ -157,30 +159,64 @@ __global__ __launch_bounds__(256) void k_count_points(DevView v, uint32_t kappa,
           for (int k = 0; k < PPL; ++k)
             sp[k] = centre(wrap_add(v.lat[g * 64 * PPL + lane + 64 * k], u));
         }
-        const int2* ip = v.ihp + tb;
-#pragma unroll 8
-        for (uint32_t tt = 0; tt < 64; ++tt) {
-          const int2 q = ip[tt];
-          int c = 0;
+        // one integrand per step: PPL dot products and compares on the
+        // vector ALU, popcounts and adds on the scalar ALU, and the count
+        // written into lane tt
+        int myc = 0;
+        const int4* ip = (const int4*)(ihp + tb);
+#pragma unroll 1
+        for (int blk = 0; blk < 8; ++blk) {
+          // eight integrands' parameters in one scalar load
+          const int4 q0 = ip[4 * blk], q1 = ip[4 * blk + 1], q2 = ip[4 * blk + 2], q3 = ip[4 * blk + 3];
+          const int nn[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
+          const int dd[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
 #pragma unroll
-          for (int k = 0; k < PPL; ++k)
-            c += __popcll(__ballot(dot2((uint32_t)q.x, sp[k], 0) > q.y));
-          myc += (lane == tt) ? c : 0;
+          for (int k8 = 0; k8 < 8; ++k8) {
+            int c = 0;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k)
+              c += __popcll(__ballot(dot2((uint32_t)nn[k8], sp[k], 0) > dd[k8]));
+            myc = bnlat_writelane_i32(c, 8 * blk + k8, myc);
+          }
         }
+        total += myc;
       }
     }
-    buf[tix(row, tb + lane, rows)] = (uint16_t)myc;
+    buf[tix(row, tb + lane, rows)] = (uint16_t)total;
     if (MODE == MODE_ALL)
-      v.err[(size_t)p * v.tp + tb + lane] = (float)myc * inv_n - v.area[tb + lane];
+      v.err[(size_t)p * v.tp + tb + lane] = (float)total * inv_n - v.area[tb + lane];
   }
+}
+
+template <int PPL, int MODE>
+__global__ __launch_bounds__(256) void k_count_points(DevView v, const int2* __restrict__ ihp,
+                                                      uint32_t kappa, uint32_t m, uint32_t tch) {
+  count_points_body<PPL, MODE>(v, ihp, kappa, m, tch, blockIdx.x);
+}
+
+// Member of a batch that owns launch block blk (prefix sums of blocks per member).
+__device__ inline uint32_t batch_member(const uint32_t* __restrict__ pre, uint32_t nmem, uint32_t blk) {
+  uint32_t i = 0;
+  while (i + 1 < nmem && pre[i + 1] <= blk) ++i;
+  return __builtin_amdgcn_readfirstlane(i);
+}
+
+template <int PPL>
+__global__ __launch_bounds__(256) void k_count_points_batch(const DevView* __restrict__ views,
+                                                            const uint32_t* __restrict__ pre,
+                                                            uint32_t nmem, uint32_t kappa) {
+  const uint32_t i = batch_member(pre, nmem, blockIdx.x);
+  const DevView v = views[i];
+  count_points_body<PPL, MODE_CLASS>(v, v.ihp, kappa, v.pc, v.tch, blockIdx.x - pre[i]);
 }
 
 // k_count_integrands (N < 64): lanes hold 64 integrands of one pixel and walk
 // the N samples, which are wave-uniform.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_count_integrands(DevView v, uint32_t kappa, uint32_t m) {
+__device__ __forceinline__ void count_integrands_body(const DevView& v, uint32_t kappa, uint32_t m,
+                                                      uint32_t blk) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = wave_id();
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
   const uint32_t nch = v.tp >> 6;
   const uint32_t j = wave / nch, ch = wave - j * nch;
   if (j >= m) return;
@@ -194,6 +230,19 @@ __global__ __launch_bounds__(256) void k_count_integrands(DevView v, uint32_t ka
   for (uint32_t i = 0; i < v.n; ++i) c += dot2((uint32_t)q.x, centre(wrap_add(v.lat[i], u)), 0) > q.y;
   buf[tix(row, t, rows)] = (uint16_t)c;
   if (MODE == MODE_ALL) v.err[(size_t)p * v.tp + t] = (float)c * (1.0f / (float)v.n) - v.area[t];
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_count_integrands(DevView v, uint32_t kappa, uint32_t m) {
+  count_integrands_body<MODE>(v, kappa, m, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_count_integrands_batch(const DevView* __restrict__ views,
+                                                                const uint32_t* __restrict__ pre,
+                                                                uint32_t nmem, uint32_t kappa) {
+  const uint32_t i = batch_member(pre, nmem, blockIdx.x);
+  const DevView v = views[i];
+  count_integrands_body<MODE_CLASS>(v, kappa, v.pc, blockIdx.x - pre[i]);
 }
 
 // --------------------------------------------------------- window tables
@@ -331,8 +380,9 @@ struct StageGeom {
 };
 
 template <int R, int K, int BY, int PAIRS>
-__global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kappa, uint32_t trlen,
-                                                         long long* __restrict__ xpart) {
+__device__ __forceinline__ void delta_stage_body(const DevView& v, uint32_t kappa, uint32_t trlen,
+                                                 long long* __restrict__ xpart, uint32_t bkx,
+                                                 uint32_t bky, uint32_t bkz) {
   using G = StageGeom<R, K, BY, PAIRS>;
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
@@ -340,7 +390,7 @@ __global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kap
   uint32_t* reg = lds;
   uint32_t* cnb = lds + G::PAIRS * G::RA;
   const uint32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const uint32_t a0 = blockIdx.y * BY, b0 = blockIdx.x * G::BX;
+  const uint32_t a0 = bky * BY, b0 = bkx * G::BX;
   const uint32_t a = a0 + ty, b = b0 + tx;
   const bool active = (a < v.ch) && (b < v.cw);
   const uint32_t ky = kappa / K, kx = kappa - ky * K;
@@ -356,7 +406,7 @@ __global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kap
 #pragma unroll
   for (int c = 0; c < NCLS; ++c) zd[c] = 0;
 
-  const uint32_t t_begin = blockIdx.z * trlen, t_end = min(t_begin + trlen, v.tp);
+  const uint32_t t_begin = bkz * trlen, t_end = min(t_begin + trlen, v.tp);
   for (uint32_t t0 = t_begin; t0 < t_end; t0 += 2 * G::PAIRS) {
     __syncthreads();
     {
@@ -457,9 +507,30 @@ __global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kap
   }
 }
 
+template <int R, int K, int BY, int PAIRS>
+__global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kappa, uint32_t trlen,
+                                                         long long* __restrict__ xpart) {
+  delta_stage_body<R, K, BY, PAIRS>(v, kappa, trlen, xpart, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched form: member i owns blocks pre[i] .. pre[i+1]-1, laid out as its own
+// (x, y, slice) grid; its slice length is in trl[i].
+template <int R, int K, int BY, int PAIRS>
+__global__ __launch_bounds__(32 * BY) void k_delta_stage_batch(const DevView* __restrict__ views,
+                                                               const uint32_t* __restrict__ pre,
+                                                               const uint32_t* __restrict__ geo,
+                                                               uint32_t nmem, uint32_t kappa) {
+  const uint32_t i = batch_member(pre, nmem, blockIdx.x);
+  const DevView v = views[i];
+  const uint32_t lb = blockIdx.x - pre[i];
+  const uint32_t gx = geo[3 * i], gy = geo[3 * i + 1], trlen = geo[3 * i + 2];
+  delta_stage_body<R, K, BY, PAIRS>(v, kappa, trlen, v.xpart, lb % gx, (lb / gx) % gy, lb / (gx * gy));
+}
+
 // Decide from the summed class sums (one thread per pixel) and clear them.
-__global__ __launch_bounds__(256) void k_delta_finish(DevView v, long long* __restrict__ xsum) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void delta_finish_body(const DevView& v, long long* __restrict__ xsum,
+                                                  uint32_t blk) {
+  const uint32_t j = blk * blockDim.x + threadIdx.x;
   if (j >= v.pc) return;
   double acc = 0.0;
   for (uint32_t c = 0; c < v.ncls; ++c) {
@@ -471,12 +542,275 @@ __global__ __launch_bounds__(256) void k_delta_finish(DevView v, long long* __re
   v.accept[j] = (v.objective > 0) ? (acc < 0.0) : (acc > 0.0);
 }
 
+__global__ __launch_bounds__(256) void k_delta_finish(DevView v, long long* __restrict__ xsum) {
+  delta_finish_body(v, xsum, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_delta_finish_batch(const DevView* __restrict__ views,
+                                                            const uint32_t* __restrict__ pre,
+                                                            uint32_t nmem) {
+  const uint32_t i = batch_member(pre, nmem, blockIdx.x);
+  const DevView v = views[i];
+  delta_finish_body(v, v.xpart, blockIdx.x - pre[i]);
+}
+
+// ---------------------------------------------- energy change on matrix cores
+//
+// BF16 form of the neighbourhood Gram products (K = 2 colour classes per
+// axis).  A block holds 8 class rows x 16 class pixels; wave w owns class row
+// w, i.e. the 16 rows of an MFMA tile.  For every 16-integrand slice the
+// counts of the block's window region are staged in LDS as BF16 (integer
+// counts up to 256 are exact in BF16), together with the moved pixels'
+// count changes dc = c' - c.  v_mfma_f32_16x16x16_bf16 then forms, for each
+// of the 2r+1 neighbour rows and 3 column tiles, the products
+//   G[b][col] = sum_t dc[b][t] * c[row][col][t]
+// with FP32 accumulation; the window entries (col - 2b - r in [-r, r]) are the
+// Gram terms the energy change needs.  A slice's partial sums are exact
+// integers when every partial sum stays below 2^24, which holds if
+// N <= 256 and N * sum_t |dc_t| < 2^24 over the slice; slices that cannot
+// certify this mark the pixel, and accepted marked moves are re-checked with
+// the exact integer kernel (k_delta_recheck).
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int R>
+struct MfmaGeom {
+  static constexpr int BYC = 8;                       // class rows (waves) per block
+  static constexpr int BXC = 16;                      // class pixels per row (MFMA rows)
+  static constexpr int RROWS = 2 * (BYC - 1) + 1 + 2 * R;
+  static constexpr int RUSED = 2 * (BXC - 1) + 1 + 2 * R;   // region columns read
+  static constexpr int RCOLS = 48;                    // three 16-column tiles
+  static constexpr int NB = BYC * BXC;
+  // LDS in 8-byte units (4 BF16 = 4 integrands of one pixel):
+  //   region [4 quarter-slices][RROWS][RCOLS], dc [4][NB]
+  static constexpr int REG8 = 4 * RROWS * RCOLS;
+  static constexpr int DC8 = 4 * NB;
+  static constexpr int LDS_BYTES = 8 * (REG8 + DC8);
+  static_assert(RUSED <= RCOLS, "window too wide for three column tiles");
+};
+
+__device__ inline uint2 to_bf16x4(uint32_t c01, uint32_t c23) {
+  // four non-negative integer counts -> BF16 (round to nearest even)
+  const __bf16 a = (__bf16)(float)(c01 & 0xFFFFu), b = (__bf16)(float)(c01 >> 16);
+  const __bf16 c = (__bf16)(float)(c23 & 0xFFFFu), d = (__bf16)(float)(c23 >> 16);
+  return make_uint2((uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16),
+                    (uint32_t)__builtin_bit_cast(uint16_t, c) | ((uint32_t)__builtin_bit_cast(uint16_t, d) << 16));
+}
+
+__device__ inline uint32_t bf16_pair(int x, int y) {
+  const __bf16 a = (__bf16)(float)x, b = (__bf16)(float)y;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+template <int R>
+__global__ __launch_bounds__(512) void k_delta_mfma(DevView v, uint32_t kappa, uint32_t trlen,
+                                                    long long* __restrict__ xsum,
+                                                    uint32_t* __restrict__ unsure) {
+  using G = MfmaGeom<R>;
+  constexpr Window<R> W = WinConst<R>::w;
+  constexpr int NCLS = WinConst<R>::NCLS;
+  extern __shared__ uint2 lds8[];
+  uint2* reg = lds8;                 // [4][RROWS][RCOLS]
+  uint2* dcs = lds8 + G::REG8;       // [4][NB]
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t a0 = blockIdx.y * G::BYC, b0 = blockIdx.x * G::BXC;
+  const uint32_t ky = kappa >> 1, kx = kappa & 1;
+  const uint32_t ys = (ky + 2 * a0 + v.h * (R / v.h + 1) - R) % v.h;
+  const uint32_t xs = (kx + 2 * b0 + v.w * (R / v.w + 1) - R) % v.w;
+  const uint32_t P = v.w * v.h;
+
+  // columns past the used ones are never read back; keep them finite
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(4 * G::RROWS * (G::RCOLS - G::RUSED)); i += blockDim.x) {
+    const uint32_t q = i / (G::RCOLS - G::RUSED), c = G::RUSED + i % (G::RCOLS - G::RUSED);
+    reg[q * G::RCOLS + c] = make_uint2(0, 0);
+  }
+
+  // staging roles: thread i < 2*NB owns (class pixel i >> 1, half of the slice)
+  const uint32_t own_cp = threadIdx.x >> 1, own_half = threadIdx.x & 1;
+  const uint32_t own_a = a0 + own_cp / G::BXC, own_b = b0 + own_cp % G::BXC;
+  const bool own_ok = threadIdx.x < 2u * G::NB && own_a < v.ch && own_b < v.cw;
+  const uint32_t own_p = own_ok ? (ky + 2 * own_a) * v.w + (kx + 2 * own_b) : 0;
+  long long z0 = 0;          // sum_t dc (c' + c) over this thread's integrands
+  uint32_t absdc = 0;        // sum_t |dc| over this thread's integrands
+
+  f32x4 acc[2 * R + 1][3];
+#pragma unroll
+  for (int oy = 0; oy < 2 * R + 1; ++oy)
+#pragma unroll
+    for (int ct = 0; ct < 3; ++ct) acc[oy][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const uint32_t t_begin = blockIdx.z * trlen, t_end = min(t_begin + trlen, v.tp);
+  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 16) {
+    __syncthreads();
+    // region counts for integrands t0..t0+15 (two 8-integrand tiles)
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(2 * G::RROWS * G::RUSED); i += blockDim.x) {
+      const uint32_t half = i / (G::RROWS * G::RUSED), pix = i - half * (G::RROWS * G::RUSED);
+      const uint32_t rr = pix / G::RUSED, cc = pix - rr * G::RUSED;
+      uint32_t gy = ys + rr, gx = xs + cc;
+      while (gy >= v.h) gy -= v.h;
+      while (gx >= v.w) gx -= v.w;
+      const uint4 q = *(const uint4*)(v.cnt + tix(gy * v.w + gx, t0 + 8 * half, P));
+      reg[((2 * half) * G::RROWS + rr) * G::RCOLS + cc] = to_bf16x4(q.x, q.y);
+      reg[((2 * half + 1) * G::RROWS + rr) * G::RCOLS + cc] = to_bf16x4(q.z, q.w);
+    }
+    // count changes of the moved pixels
+    if (threadIdx.x < 2u * G::NB) {
+      uint2 lo = make_uint2(0, 0), hi = make_uint2(0, 0);
+      if (own_ok) {
+        const uint32_t j = own_a * v.cw + own_b;
+        const uint4 cn = *(const uint4*)(v.c_new + tix(j, t0 + 8 * own_half, v.pc));
+        const uint4 co = *(const uint4*)(v.cnt + tix(own_p, t0 + 8 * own_half, P));
+        const uint32_t nw[4] = {cn.x, cn.y, cn.z, cn.w}, ow[4] = {co.x, co.y, co.z, co.w};
+        int d[8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int n0 = (int)(nw[k] & 0xFFFFu), n1 = (int)(nw[k] >> 16);
+          const int o0 = (int)(ow[k] & 0xFFFFu), o1 = (int)(ow[k] >> 16);
+          d[2 * k] = n0 - o0;
+          d[2 * k + 1] = n1 - o1;
+          z0 += (long long)(d[2 * k] * (n0 + o0) + d[2 * k + 1] * (n1 + o1));
+          absdc += (uint32_t)(abs(d[2 * k]) + abs(d[2 * k + 1]));
+        }
+        lo = make_uint2(bf16_pair(d[0], d[1]), bf16_pair(d[2], d[3]));
+        hi = make_uint2(bf16_pair(d[4], d[5]), bf16_pair(d[6], d[7]));
+      }
+      dcs[(2 * own_half) * G::NB + own_cp] = lo;
+      dcs[(2 * own_half + 1) * G::NB + own_cp] = hi;
+    }
+    __syncthreads();
+    // lane l: MFMA row (pixel) l % 16, integrands 4 (l / 16) .. +3 of the slice
+    const uint32_t quarter = lane >> 4, m = lane & 15;
+    const uint2 a2 = dcs[quarter * G::NB + w * G::BXC + m];
+    const bf16x4 af = __builtin_bit_cast(bf16x4, a2);
+#pragma unroll
+    for (int oy = 0; oy < 2 * R + 1; ++oy) {
+      const uint32_t rr = 2 * w + oy;
+#pragma unroll
+      for (int ct = 0; ct < 3; ++ct) {
+        const uint2 b2 = reg[(quarter * G::RROWS + rr) * G::RCOLS + ct * 16 + m];
+        acc[oy][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, __builtin_bit_cast(bf16x4, b2),
+                                                                acc[oy][ct], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+
+  // certificate and z0 of each pixel: combine the two halves through LDS
+  long long* zsh = (long long*)lds8;                     // [NB]
+  uint32_t* ash = (uint32_t*)(zsh + G::NB);              // [NB]
+  if (threadIdx.x < 2u * G::NB && own_half == 0) {
+    zsh[own_cp] = z0;
+    ash[own_cp] = absdc;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2u * G::NB && own_half == 1) {
+    zsh[own_cp] += z0;
+    ash[own_cp] += absdc;
+  }
+  __syncthreads();
+
+  // Gram extraction: per neighbour row, the wave's three tiles go through
+  // LDS and lanes 0..15 (one per class pixel) collect the window entries.
+  float* gsh = (float*)(ash + G::NB) + w * (16 * G::RCOLS);   // [16][48] per wave
+  const uint32_t b = lane;                                    // class pixel of lanes 0..15
+  long long zd[NCLS];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) zd[c] = 0;
+#pragma unroll
+  for (int oy = 0; oy < 2 * R + 1; ++oy) {
+#pragma unroll
+    for (int ct = 0; ct < 3; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) gsh[(4 * (lane >> 4) + i) * G::RCOLS + ct * 16 + (lane & 15)] = acc[oy][ct][i];
+    __builtin_amdgcn_s_barrier();   // wave-local: only this wave touches its gsh
+    if (lane < 16) {
+#pragma unroll
+      for (int ox = -R; ox <= R; ++ox) {
+        if (ox == 0 && oy == R) continue;
+        const int d2 = ox * ox + (oy - R) * (oy - R);
+        int cidx = 0;
+#pragma unroll
+        for (int c = 0; c < NCLS; ++c)
+          if (W.d[c] == d2) cidx = c;
+        zd[cidx] += (long long)gsh[b * G::RCOLS + 2 * b + R + ox];
+      }
+    }
+    __builtin_amdgcn_s_barrier();
+  }
+  const uint32_t a = a0 + w, bb = b0 + b;
+  if (lane < 16 && a < v.ch && bb < v.cw) {
+    const uint32_t cp = w * G::BXC + b;
+    const uint32_t j = a * v.cw + bb;
+    const long long zz = zsh[cp];
+    if (v.n > 256 || (unsigned long long)ash[cp] * v.n >= (1ull << 24)) atomicOr(&unsure[j], 1u);
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c)
+      atomicAdd((unsigned long long*)&xsum[(size_t)c * v.pc + j],
+                (unsigned long long)((long long)W.csize[c] * zz - 2 * zd[c]));
+  }
+}
+
+// Exact re-check of accepted moves the matrix-core pass could not certify:
+// the integer energy change decides, a reversed decision is a veto.
+template <int R>
+__global__ __launch_bounds__(256) void k_delta_recheck(DevView v, uint32_t kappa,
+                                                       uint32_t* __restrict__ unsure) {
+  constexpr Window<R> W = WinConst<R>::w;
+  constexpr int NCLS = WinConst<R>::NCLS;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t j = wave_id();
+  if (j >= v.pc) return;
+  const uint32_t flagged = unsure[j];
+  if (!flagged) return;
+  if (!v.accept[j]) {
+    if (lane == 0) unsure[j] = 0;
+    return;
+  }
+  const uint32_t p = class_pixel(v, kappa, j);
+  const uint32_t y = p / v.w, x = p - y * v.w, P = v.w * v.h;
+  long long z0 = 0, zd[NCLS];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) zd[c] = 0;
+  for (uint32_t base = 0; base < v.tp; base += 128) {
+    const uint32_t t = base + 2 * lane;
+    const uint32_t cn = *(const uint32_t*)(v.c_new + tix(j, t, v.pc));
+    const uint32_t co = *(const uint32_t*)(v.cnt + tix(p, t, P));
+    const int n0 = (int)(cn & 0xFFFFu), n1 = (int)(cn >> 16);
+    const int o0 = (int)(co & 0xFFFFu), o1 = (int)(co >> 16);
+    const int dc0 = n0 - o0, dc1 = n1 - o1;
+    const uint32_t dcp = ((uint32_t)dc0 & 0xFFFFu) | ((uint32_t)dc1 << 16);
+    z0 += (long long)(dc0 * (n0 + o0) + dc1 * (n1 + o1));
+#pragma unroll
+    for (int mm = 0; mm < W.M; ++mm) {
+      const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
+      zd[W.cls[mm]] += dot2(dcp, *(const uint32_t*)(v.cnt + tix(q, t, P)), 0);
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) {
+    long long xv = (long long)W.csize[c] * z0 - 2 * zd[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
+    acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)xv));
+  }
+  if (lane == 0) {
+    const bool ok = (v.objective > 0) ? (acc < 0.0) : (acc > 0.0);
+    v.delta[j] = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+    if (!ok) {
+      v.accept[j] = 0;
+      atomicAdd(&v.ctr[2], 1ull);
+    }
+    unsure[j] = 0;
+  }
+}
+
 // ------------------------------------------------------------------ commit
 // Accepted moves of the phase become the state (Sec. 3.4): offset, hit
 // counts and FP32 errors of the pixel.
-__global__ __launch_bounds__(256) void k_commit(DevView v, uint32_t kappa) {
+__device__ __forceinline__ void commit_body(const DevView& v, uint32_t kappa, uint32_t blk) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t j = wave_id();
+  const uint32_t j = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
   if (j >= v.pc || !v.accept[j]) return;
   const uint32_t p = class_pixel(v, kappa, j);
   if (lane == 0) {
@@ -505,8 +839,23 @@ __global__ __launch_bounds__(256) void k_commit(DevView v, uint32_t kappa) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_commit(DevView v, uint32_t kappa) { commit_body(v, kappa, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_commit_batch(const DevView* __restrict__ views,
+                                                      const uint32_t* __restrict__ pre, uint32_t nmem,
+                                                      uint32_t kappa) {
+  const uint32_t i = batch_member(pre, nmem, blockIdx.x);
+  const DevView v = views[i];
+  commit_body(v, kappa, blockIdx.x - pre[i]);
+}
+
 __global__ void k_advance(unsigned long long* ctr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&ctr[0], 1ull);
+}
+
+__global__ void k_advance_batch(const DevView* __restrict__ views, uint32_t nmem) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nmem) atomicAdd(&views[i].ctr[0], 1ull);
 }
 
 __global__ __launch_bounds__(256) void k_init_offsets(DevView v) {
@@ -629,15 +978,15 @@ hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
                        v, kappa, m);
     return hipGetLastError();
   }
-  const uint32_t tch = v.tp >= 256 ? 256 : v.tp;
+  const uint32_t tch = v.tch;
   const uint64_t waves = (uint64_t)m * ((v.tp + tch - 1) / tch);
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
   switch (v.n) {
-    case 64: hipLaunchKernelGGL((k_count_points<1, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
-    case 128: hipLaunchKernelGGL((k_count_points<2, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
-    case 256: hipLaunchKernelGGL((k_count_points<4, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
-    case 512: hipLaunchKernelGGL((k_count_points<8, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
-    default: hipLaunchKernelGGL((k_count_points<16, MODE>), grid, block, 0, s, v, kappa, m, tch); break;
+    case 64: hipLaunchKernelGGL((k_count_points<1, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
+    case 128: hipLaunchKernelGGL((k_count_points<2, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
+    case 256: hipLaunchKernelGGL((k_count_points<4, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
+    case 512: hipLaunchKernelGGL((k_count_points<8, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
+    default: hipLaunchKernelGGL((k_count_points<16, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
   }
   return hipGetLastError();
 }
@@ -663,7 +1012,8 @@ hipError_t delta_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
 // of 16-integrand stages.
 inline uint32_t stage_slices(const DevView& v, uint32_t blocks, uint32_t* trlen) {
   const uint32_t chunks = v.tp / 16;
-  uint32_t want = (512 + blocks - 1) / blocks;
+  const uint32_t target = v.slice_target ? v.slice_target : 512;
+  uint32_t want = (target + blocks - 1) / blocks;
   if (want > chunks) want = chunks;
   const uint32_t per = (chunks + want - 1) / want;
   *trlen = per * 16;
@@ -715,7 +1065,36 @@ hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
   }
 }
 
+template <int R>
+hipError_t mfma_launch(const DevView& v, uint32_t kappa, hipStream_t s) {
+  using G = MfmaGeom<R>;
+  const uint32_t bx = (v.cw + G::BXC - 1) / G::BXC, by = (v.ch + G::BYC - 1) / G::BYC;
+  uint32_t trlen = 0;
+  const uint32_t ns = stage_slices(v, bx * by, &trlen);
+  const size_t lds = (size_t)G::LDS_BYTES;
+  hipLaunchKernelGGL((k_delta_mfma<R>), dim3(bx, by, ns), dim3(64 * G::BYC), lds, s, v, kappa, trlen,
+                     v.xpart, v.unsure);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_delta_finish, dim3((v.pc + 255) / 256), dim3(256), 0, s, v, v.xpart);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_delta_recheck<R>), dim3((v.pc + 3) / 4), dim3(256), 0, s, v, kappa, v.unsure);
+  return hipGetLastError();
+}
+
 hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
+  if (mode == MODE_CLASS && v.mfma) {
+    switch (v.radius) {
+      case 1: return mfma_launch<1>(v, kappa, s);
+      case 2: return mfma_launch<2>(v, kappa, s);
+      case 3: return mfma_launch<3>(v, kappa, s);
+      case 4: return mfma_launch<4>(v, kappa, s);
+      case 5: return mfma_launch<5>(v, kappa, s);
+      case 6: return mfma_launch<6>(v, kappa, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (mode == MODE_CLASS && v.xpart) {
     switch (v.radius) {
       case 1: return stage_by_k<1>(v, kappa, v.xpart, s);
@@ -781,4 +1160,100 @@ hipError_t launch_blur(const DevView& v, const float* kx, uint32_t nkx, const in
   return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------------ batches
+
+int count_kind(const DevView& v) {
+  if (v.n < 64) return 0;
+  switch (v.n) {
+    case 64: return 1;
+    case 128: return 2;
+    case 256: return 4;
+    case 512: return 8;
+    default: return 16;
+  }
+}
+
+uint32_t count_blocks(const DevView& v) {
+  if (v.n < 64) return (uint32_t)(((uint64_t)v.pc * (v.tp >> 6) + 3) / 4);
+  const uint64_t waves = (uint64_t)v.pc * ((v.tp + v.tch - 1) / v.tch);
+  return (uint32_t)((waves + 3) / 4);
+}
+
+uint32_t stage_by(uint32_t k) { return k == 4 ? 2 : 8; }
+
+void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen) {
+  const uint32_t by = stage_by(v.k);
+  *gx = (v.cw + 31) / 32;
+  *gy = (v.ch + by - 1) / by;
+  *gz = stage_slices(v, *gx * *gy, trlen);
+}
+
+hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
+                              uint32_t blocks, uint32_t kappa, hipStream_t s) {
+  const dim3 grid(blocks), block(256);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(k_count_integrands_batch, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 1: hipLaunchKernelGGL(k_count_points_batch<1>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 2: hipLaunchKernelGGL(k_count_points_batch<2>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 4: hipLaunchKernelGGL(k_count_points_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 8: hipLaunchKernelGGL(k_count_points_batch<8>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    default: hipLaunchKernelGGL(k_count_points_batch<16>, grid, block, 0, s, views, pre, nmem, kappa); break;
+  }
+  return hipGetLastError();
+}
+
+namespace {
+template <int R, int K>
+hipError_t stage_batch_rk(const DevView* views, const uint32_t* pre, const uint32_t* geo, uint32_t nmem,
+                          uint32_t blocks, uint32_t kappa, hipStream_t s) {
+  constexpr int BY = K == 4 ? 2 : 8;
+  using G = StageGeom<R, K, BY, 4>;
+  hipLaunchKernelGGL((k_delta_stage_batch<R, K, BY, 4>), dim3(blocks), dim3(32 * BY), (size_t)G::LDS_WORDS * 4, s,
+                     views, pre, geo, nmem, kappa);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t stage_batch_r(uint32_t k, const DevView* views, const uint32_t* pre, const uint32_t* geo,
+                         uint32_t nmem, uint32_t blocks, uint32_t kappa, hipStream_t s) {
+  switch (k) {
+    case 1: return stage_batch_rk<R, 1>(views, pre, geo, nmem, blocks, kappa, s);
+    case 2: return stage_batch_rk<R, 2>(views, pre, geo, nmem, blocks, kappa, s);
+    case 4: return stage_batch_rk<R, 4>(views, pre, geo, nmem, blocks, kappa, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+hipError_t launch_stage_batch(uint32_t radius, uint32_t k, const DevView* views, const uint32_t* pre,
+                              const uint32_t* geo, uint32_t nmem, uint32_t blocks, uint32_t kappa,
+                              hipStream_t s) {
+  switch (radius) {
+    case 1: return stage_batch_r<1>(k, views, pre, geo, nmem, blocks, kappa, s);
+    case 2: return stage_batch_r<2>(k, views, pre, geo, nmem, blocks, kappa, s);
+    case 3: return stage_batch_r<3>(k, views, pre, geo, nmem, blocks, kappa, s);
+    case 4: return stage_batch_r<4>(k, views, pre, geo, nmem, blocks, kappa, s);
+    case 5: return stage_batch_r<5>(k, views, pre, geo, nmem, blocks, kappa, s);
+    case 6: return stage_batch_r<6>(k, views, pre, geo, nmem, blocks, kappa, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_finish_batch(const DevView* views, const uint32_t* pre, uint32_t nmem, uint32_t blocks,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_delta_finish_batch, dim3(blocks), dim3(256), 0, s, views, pre, nmem);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit_batch(const DevView* views, const uint32_t* pre, uint32_t nmem, uint32_t blocks,
+                               uint32_t kappa, hipStream_t s) {
+  hipLaunchKernelGGL(k_commit_batch, dim3(blocks), dim3(256), 0, s, views, pre, nmem, kappa);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_batch(const DevView* views, uint32_t nmem, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance_batch, dim3((nmem + 63) / 64), dim3(64), 0, s, views, nmem);
+  return hipGetLastError();
+}
 }  // namespace bnlat

@@ -1,0 +1,119 @@
+"""Batched form: many independent problems of uneven shapes swept by shared,
+graph-captured launches.  Each member's trajectory must equal the oracle's
+(small members) and the one it follows when swept alone (larger members)."""
+import numpy as np
+import pytest
+
+from oracle import sweep as osw
+import synthgen
+
+from cases import oracle_problem, say, workload
+
+pytestmark = pytest.mark.gpu
+bnlat = pytest.importorskip("paper_2105_12620_amd.bnlat")
+
+
+@pytest.fixture(scope="module")
+def stream():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.cuda.Stream()
+
+
+MEMBERS = [
+    workload(n=4, g=(1, 3), width=16, height=16, t_heaviside=70, problem_id=0),
+    workload(n=16, g=(1, 7), width=32, height=16, t_heaviside=40, problem_id=1),
+    workload(n=64, g=(1, 19), width=16, height=16, t_heaviside=130, problem_id=2),
+    workload(n=256, g=(1, 79), width=12, height=12, t_heaviside=64, radius=4, problem_id=3),
+    workload(n=16, g=(3, 5), width=8, height=8, t_heaviside=20, radius=2, problem_id=4),
+    workload(n=64, g=(5, 27), width=24, height=24, t_heaviside=33, problem_id=5),
+]
+
+
+def make(w, inp, stream):
+    p = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]), stream=stream.cuda_stream)
+    p.init_offsets(inp["offsets"])
+    p.compute_errors()
+    return p
+
+
+def test_batched_members_follow_oracle(stream, tmp_path):
+    k = 3
+    inps = [synthgen.problem_inputs(w) for w in MEMBERS]
+    probs = [make(w, inp, stream) for w, inp in zip(MEMBERS, inps)]
+    cache = str(tmp_path / "tune.txt")
+    with bnlat.Batch(probs, tune_cache=cache) as b:
+        say("tuning", b.tuning())
+        b.sweep(k)
+    for w, inp, p in zip(MEMBERS, inps, probs):
+        say("member", w["problem_id"], w["n"], w["width"], w["height"])
+        ref = oracle_problem(w, inp)
+        st = osw.run(ref, osw.initial_state(ref, inp["offsets"]), k)
+        np.testing.assert_array_equal(p.get_offsets(), st.u)
+        np.testing.assert_array_equal(p.get_counts(), st.c.reshape(-1, w["t_heaviside"]))
+        assert p.get_sweep_index() == k
+        assert p.energy() == pytest.approx(osw.energy_of(ref, st), rel=1e-12)
+        p.close()
+    text = open(cache).read()
+    assert "tch=" in text and "slices=" in text
+
+
+def test_tune_cache_round_trip(stream, tmp_path):
+    """The tuner's choice is written under the members' shape key and read
+    back; a hand-written entry for the key is honoured."""
+    inps = [synthgen.problem_inputs(w) for w in MEMBERS[:3]]
+    probs = [make(w, inp, stream) for w, inp in zip(MEMBERS[:3], inps)]
+    cache = str(tmp_path / "tune.txt")
+    with bnlat.Batch(probs, tune_cache=cache) as b:
+        first = b.tuning()
+    assert first["tch"] in (64, 128, 256, 512)
+    assert first["slice_target"] in (256, 512, 1024, 2048)
+    key = open(cache).read().split()[0]
+    with bnlat.Batch(probs, tune_cache=cache) as b:
+        assert b.tuning() == first
+    fixed = str(tmp_path / "fixed.txt")
+    with open(fixed, "w") as f:
+        f.write(f"{key} tch=64 slices=2048\n")
+    with bnlat.Batch(probs, tune_cache=fixed) as b:
+        assert b.tuning() == {"tch": 64, "slice_target": 2048}
+        b.sweep(1)
+    for p in probs:
+        p.close()
+
+
+def test_dimension_pair_batch_equals_members_alone(stream):
+    """Uneven batch shaped like the padded-sampler workload (tiles 64-256,
+    N in {4, 16, 64, 256}, T = 256, 7x7 window): one batched sweep equals
+    each member's own sweep, bit for bit."""
+    members = synthgen.dimension_pair_batch(count=8)
+    inps = [synthgen.problem_inputs(w) for w in members]
+    batched = [make(w, inp, stream) for w, inp in zip(members, inps)]
+    with bnlat.Batch(batched) as b:
+        b.sweep(2)
+    for w, inp, p in zip(members, inps, batched):
+        say("member", w["problem_id"], w["n"], w["width"])
+        with make(w, inp, stream) as alone:
+            alone.sweep(2)
+            np.testing.assert_array_equal(p.get_offsets(), alone.get_offsets())
+        p.close()
+
+
+def test_batch_validation(stream):
+    w = MEMBERS[0]
+    inp = synthgen.problem_inputs(w)
+    p = make(w, inp, stream)
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.Batch([p, p])
+    assert e.value.status == bnlat.BN_EINVAL
+    q = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]), stream=stream.cuda_stream)
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.Batch([p, q])
+    assert e.value.status == bnlat.BN_ESTATE
+    other = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]))
+    other.init_offsets(inp["offsets"])
+    other.compute_errors()
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.Batch([p, other])
+    assert e.value.status == bnlat.BN_EINVAL
+    for x in (p, q, other):
+        x.close()

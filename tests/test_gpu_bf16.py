@@ -1,0 +1,129 @@
+"""BF16 matrix-core form of the energy change (precision = BF16).
+
+Where the exactness certificate holds (N <= 256 and N * sum|dc| < 2^24 per
+integrand slice) the FP32-accumulated MFMA Gram products are exact integers,
+so decisions, energy changes and trajectories equal the oracle's bit for bit.
+Where it cannot hold (N > 256, counts rounded to BF16) every accepted move is
+re-checked with the exact integer form: committed moves must satisfy the
+oracle's exact criterion, and the vetoes are counted."""
+import numpy as np
+import pytest
+
+from oracle import energy, estimator, quality, sweep as osw
+import synthgen
+
+from cases import EDGE, gpu_problem, oracle_problem, say, workload
+
+pytestmark = pytest.mark.gpu
+bnlat = pytest.importorskip("paper_2105_12620_amd.bnlat")
+
+BF16 = 1
+
+
+def bf16(w):
+    w = dict(w)
+    w["precision"] = BF16
+    return w
+
+
+@pytest.mark.parametrize("name", ["tile32_n16_t64", "n256_r4", "rect_ascend", "wide64", "r6",
+                                  "tile4_alias"])
+def test_bf16_phases_match_oracle_exactly(name):
+    w = bf16(EDGE.get(name) or workload(name))
+    say("case", name)
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.initial_state(ref, inp["offsets"])
+    with gpu_problem(w, inp) as p:
+        for s in range(2):
+            for kappa in range(4):
+                p.phase_propose(kappa)
+                p.phase_evaluate(kappa)
+                got = p.get_phase()
+                ph = osw.phase(ref, st, kappa)
+                np.testing.assert_array_equal(got["c_new"], ph["c_new"])
+                np.testing.assert_allclose(got["delta"], ph["delta"], rtol=1e-12, atol=0)
+                np.testing.assert_array_equal(got["accept"], ph["accept"])
+                p.phase_commit(kappa)
+            p.phase_advance()
+            st.sweep += 1
+        np.testing.assert_array_equal(p.get_offsets(), st.u)
+
+
+@pytest.mark.parametrize("name,k", [("tile128_n64_t256", 2), ("n256_r4", 5)])
+def test_bf16_trajectory_matches_oracle(name, k):
+    w = bf16(EDGE.get(name) or workload(name))
+    say("case", name, k)
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.run(ref, osw.initial_state(ref, inp["offsets"]), k)
+    with gpu_problem(w, inp) as p:
+        stats = p.sweep(k, stats=True)
+        assert stats["bf16_vetoes"] == 0
+        np.testing.assert_array_equal(p.get_offsets(), st.u)
+        assert p.energy() == pytest.approx(osw.energy_of(ref, st), rel=1e-12)
+
+
+def test_bf16_uncertified_moves_are_rechecked():
+    """N = 1024: counts are rounded to BF16, so no slice is certified and every
+    accepted move is re-checked exactly.  On the first phase the committed
+    moves are a subset of the oracle's (re-checks remove false accepts; false
+    rejects stay), with the oracle's exact energy change; after 6 sweeps the
+    energy is within 2 % of the oracle's exact trajectory."""
+    name = "n1024_r5"
+    w = bf16(EDGE[name])
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.initial_state(ref, inp["offsets"])
+    ph = osw.phase(ref, st, 0)
+    with gpu_problem(w, inp) as p:
+        p.phase_propose(0)
+        p.phase_evaluate(0)
+        got = p.get_phase()
+        acc = got["accept"]
+        assert np.all(ph["accept"][acc])
+        np.testing.assert_allclose(got["delta"][acc], ph["delta"][acc], rtol=1e-12)
+        p.phase_commit(0)
+        for kappa in (1, 2, 3):
+            p.phase_propose(kappa)
+            p.phase_evaluate(kappa)
+            p.phase_commit(kappa)
+        p.phase_advance()
+        stats = p.sweep(5, stats=True)
+        e_bf16 = p.energy()
+    st = osw.run(ref, osw.initial_state(ref, inp["offsets"]), 6)
+    assert e_bf16 == pytest.approx(osw.energy_of(ref, st), rel=0.02)
+    assert stats["bf16_vetoes"] >= 0
+
+
+def test_bf16_full_size_first_phase_sampled():
+    """256x256, N=256, T=1024, 9x9: the BF16 launch configuration of the
+    benchmark gives the oracle's decisions for sampled class pixels."""
+    w = bf16(workload("tile256_n256_t1024"))
+    inp = synthgen.problem_inputs(w)
+    W, H, T, r = w["width"], w["height"], w["t_heaviside"], w["radius"]
+    u0 = inp["offsets"].reshape(-1, 2).astype(np.int64)
+    ref = oracle_problem(w, inp)
+    with gpu_problem(w, inp) as p:
+        p.phase_propose(0)
+        p.phase_evaluate(0)
+        ph = p.get_phase()
+    js = synthgen.pixel_sample((W // 2) * (H // 2), 6, seed=8)
+    for j in js:
+        y, x = 2 * (int(j) // (W // 2)), 2 * (int(j) % (W // 2))
+        win = [((y + oy) % H, (x + ox) % W) for oy in range(-r, r + 1) for ox in range(-r, r + 1)]
+        ids = np.array([yy * W + xx for yy, xx in win])
+        local = np.zeros((H, W, T), dtype=np.int16)
+        local[tuple(np.array(win).T)] = estimator.hit_counts(w["n"], w["g"], u0[ids], inp["heaviside"])
+        u_new = osw.proposals(ref, np.array([y]), np.array([x]), 0).astype(np.int64)
+        c_new = estimator.hit_counts(w["n"], w["g"], u_new, inp["heaviside"])
+        d = energy.delta_exact(local, [y], [x], c_new, w["n"], r, w["sigma"])
+        assert ph["delta"][j] == pytest.approx(d[0], rel=1e-12)
+        assert bool(ph["accept"][j]) == bool(d[0] < 0)
+
+
+def test_bf16_rejects_other_colourings():
+    w = bf16(EDGE["k4_conflict_free"])
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.create_problem(w, None)
+    assert e.value.status == bnlat.BN_EUNSUPPORTED
