@@ -81,65 +81,102 @@ def main() -> int:
     w = dict(synthgen.WORKLOADS[args.workload])
     inp = synthgen.problem_inputs(w)
     stream = torch.cuda.Stream()
-    prob = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]), stream=stream.cuda_stream)
-    prob.init_offsets(inp["offsets"])
-    prob.compute_errors()
     K2 = w["colour_k"] ** 2
-    P, T, N, M = w["width"] * w["height"], w["t_heaviside"], w["n"], prob.M
+    P, T, N = w["width"] * w["height"], w["t_heaviside"], w["n"]
 
-    def staged_sweep(events):
-        for kappa in range(K2):
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if events is not None else None
-            if e: e[0].record(stream)
-            prob.phase_propose(kappa)
-            if e: e[1].record(stream)
-            prob.phase_evaluate(kappa)
-            if e: e[2].record(stream)
-            prob.phase_commit(kappa)
-            if e:
-                e[3].record(stream)
-                events.append(e)
-        prob.phase_advance()
+    def timed_form(precision: int) -> dict:
+        """K staged sweeps with events around every launch, then K graph-replayed sweeps."""
+        prob = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]), stream=stream.cuda_stream,
+                                    precision=precision)
+        prob.init_offsets(inp["offsets"])
+        prob.compute_errors()
 
-    for _ in range(args.warmup):
-        staged_sweep(None)
-    torch.cuda.synchronize()
+        def staged_sweep(events):
+            for kappa in range(K2):
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if events is not None else None
+                if e: e[0].record(stream)
+                prob.phase_propose(kappa)
+                if e: e[1].record(stream)
+                prob.phase_evaluate(kappa)
+                if e: e[2].record(stream)
+                prob.phase_commit(kappa)
+                if e:
+                    e[3].record(stream)
+                    events.append(e)
+            prob.phase_advance()
 
-    # timed region: K sweeps, every launch bracketed by events on the problem stream
-    events = []
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(args.steps):
-        staged_sweep(events)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    k_ms = {"count": [], "delta": [], "commit": []}
-    for e in events:
-        k_ms["count"].append(e[0].elapsed_time(e[1]))
-        k_ms["delta"].append(e[1].elapsed_time(e[2]))
-        k_ms["commit"].append(e[2].elapsed_time(e[3]))
-    avg = {k: float(np.mean(v)) for k, v in k_ms.items()}
+        for _ in range(args.warmup):
+            staged_sweep(None)
+        torch.cuda.synchronize()
+        events = []
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(args.steps):
+            staged_sweep(events)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(stop)
+        k_ms = {"count": [], "delta": [], "commit": []}
+        for e in events:
+            k_ms["count"].append(e[0].elapsed_time(e[1]))
+            k_ms["delta"].append(e[1].elapsed_time(e[2]))
+            k_ms["commit"].append(e[2].elapsed_time(e[3]))
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        prob.sweep(1)
+        torch.cuda.synchronize()
+        g0.record(stream)
+        stats = prob.sweep(args.steps, stats=False)
+        g1.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1)
+        energy = prob.energy()
+        quality = prob.quality_metric([1.0, 4.0, 16.0]).tolist()
+        prob.close()
+        return {"total_ms": total_ms, "kernels_ms": {k: float(np.mean(v)) for k, v in k_ms.items()},
+                "graph_ms": graph_ms, "energy": energy, "quality_sigma_1_4_16": quality}
 
-    # graph-replayed sweeps (bn_sweep) over the same number of steps
-    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    prob.sweep(1)
-    torch.cuda.synchronize()
-    g0.record(stream)
-    prob.sweep(args.steps)
-    g1.record(stream)
-    torch.cuda.synchronize()
-    graph_ms = g0.elapsed_time(g1)
+    fp32 = timed_form(bnlat.BN_FP32)
+    bf16 = timed_form(bnlat.BN_BF16)
+    avg, total_ms = fp32["kernels_ms"], fp32["total_ms"]
+    M = P // K2
+
+    def batched() -> dict:
+        members = synthgen.dimension_pair_batch()
+        probs = []
+        for mw in members:
+            mi = synthgen.problem_inputs(mw)
+            q = bnlat.create_problem(mw, bnlat.heaviside_array(mi["heaviside"]), stream=stream.cuda_stream)
+            q.init_offsets(mi["offsets"])
+            q.compute_errors()
+            probs.append(q)
+        b = bnlat.Batch(probs)
+        b.sweep(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps = max(1, args.steps // 2)
+        e0.record(stream)
+        b.sweep(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        pix = sum(mw["width"] * mw["height"] for mw in members)
+        out = {"value": pix * steps / (ms * 1e-3), "unit": "pixel-updates/s", "members": len(members),
+               "pixels": pix, "sweeps": steps, "ms_per_sweep": ms / steps, "tuning": b.tuning(),
+               "shapes": [f"{mw['width']}^2/N{mw['n']}" for mw in members]}
+        b.close()
+        for q in probs:
+            q.close()
+        return out
+
+    batch = batched()
 
     # algorithmic work per launch
     count_ops = 2.0 * M * N * T                       # v_dot2 + compare per (sample, integrand)
     count_tops = count_ops / (avg["count"] * 1e-3) / 1e12
     win = (2 * w["radius"] + 1) ** 2 - 1
-    # energy change: read the moved pixel's old and new rows and its window
-    # once per phase (the tile, 2 B per count), write M decisions
+    # energy change: the tile's counts once per phase (2 B each) plus the moved
+    # pixels' proposal rows, and the decisions
     delta_bytes = 2.0 * T * (P + M) + 9.0 * M
-    commit_bytes = 0.0
     value = P * args.steps / (total_ms * 1e-3)
     out = {
         "metric": METRIC, "value": value, "unit": "pixel-updates/s", "n_gpus": 1,
@@ -156,10 +193,17 @@ def main() -> int:
         "kernels_ms": avg,
         "delta_hbm_gbs": delta_bytes / (avg["delta"] * 1e-3) / 1e9,
         "delta_hbm_frac": delta_bytes / (avg["delta"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "graph_value": P * args.steps / (graph_ms * 1e-3),
+        "graph_value": P * args.steps / (fp32["graph_ms"] * 1e-3),
+        "bf16": {"value": P * args.steps / (bf16["total_ms"] * 1e-3),
+                 "graph_value": P * args.steps / (bf16["graph_ms"] * 1e-3),
+                 "kernels_ms": bf16["kernels_ms"],
+                 "delta_hbm_gbs": delta_bytes / (bf16["kernels_ms"]["delta"] * 1e-3) / 1e9,
+                 "energy_rel_diff_vs_fp32": abs(bf16["energy"] - fp32["energy"]) / abs(fp32["energy"]),
+                 "quality_rel_diff_vs_fp32": max(abs(a - b) / b for a, b in zip(bf16["quality_sigma_1_4_16"],
+                                                                                 fp32["quality_sigma_1_4_16"]))},
+        "batched": batch,
         "window_offsets": win,
     }
-    prob.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, inp)
     print(json.dumps(out), flush=True)

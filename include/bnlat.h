@@ -75,7 +75,7 @@ typedef struct {
   uint32_t width;        /* toroidal tile width W  (multiple of colour_k)        */
   uint32_t height;       /* toroidal tile height H (multiple of colour_k)        */
   uint32_t t_heaviside;  /* number T of Heaviside test integrands, >= 1          */
-  uint32_t t_gauss;      /* number of Gaussian integrands (must be 0 here)       */
+  uint32_t t_gauss;      /* number of Gaussian integrands (Sec. 3.5), >= 0      */
   double sigma;          /* energy weight w_o = exp(-|o|^2 / sigma^2), > 0       */
   uint32_t radius;       /* window offsets o in [-r, r]^2 \ {0}; 1 <= r < min(W,H), r <= 8 */
   uint32_t colour_k;     /* colour modulus K: K*K classes (y mod K) K + (x mod K) */
@@ -94,6 +94,12 @@ typedef struct {
   uint16_t cx, cy;
 } bn_heaviside;
 
+/* One isotropic Gaussian test integrand (Sec. 3.5 low-frequency family):
+ * f(x) = exp(-|x - (mx, my)|^2 / (2 s^2)), s > 0, no wrap. */
+typedef struct {
+  double mx, my, s;
+} bn_gaussian;
+
 typedef struct {
   uint64_t proposals;    /* pixel proposals evaluated                          */
   uint64_t accepts;      /* proposals committed                                */
@@ -107,12 +113,16 @@ typedef struct {
  * heavisides: host array [cfg->t_heaviside], or NULL to draw them from the
  *   Philox stream (counter (t, 0, problem_id, 0xB): angle 2 pi w0 2^-32,
  *   normal = round-half-even(2^14 (cos, sin)), edge point (w1>>16, w2>>16)).
+ * gaussians: host array [cfg->t_gauss], or NULL to draw them (counter
+ *   (t, 1, problem_id, 0xB): centre (w0, w1) 2^-32, s = 0.05 + 0.25 w2 2^-32).
  * stream: hipStream_t to order all work on, or NULL to let the library create
  *   (and later destroy) a non-blocking stream.
- * The exact integral of each Heaviside (area of the unit square on the hit
- * side) is computed on the host in FP64.  *out receives the handle. */
+ * Exact integrals are computed on the host in FP64: the area of the unit
+ * square on a Heaviside's hit side, and the erf product for a Gaussian.
+ * Gaussian rows enter the energy in the plain form (FP32 estimates, FP64
+ * arithmetic); Heaviside rows stay exact.  *out receives the handle. */
 bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides,
-                            void* stream, bn_problem* out);
+                            const bn_gaussian* gaussians, void* stream, bn_problem* out);
 bn_status bn_destroy_problem(bn_problem p);
 
 /* Set the offset tile U = {u_p} (Sec. 2).  host_u: uint16 [H][W][2] (x then y), or
@@ -140,7 +150,7 @@ bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats);
 bn_status bn_energy(bn_problem p, double* out);
 
 /* Blur criterion of Sec. 3.3 / Fig. 1c: for each sigmas[i] > 0,
- * out[i] = sqrt(mean_{p,t} ((k_sigma * e_t)(p))^2) with k_sigma the
+ * out[i] = sqrt(mean_{p,t} ((k_sigma * e_t)(p))^2) over all T + T_G rows, with k_sigma the
  * normalised Gaussian of standard deviation sigma periodised on the torus,
  * applied separably.  n <= 64.  Synchronises. */
 bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, double* out);
@@ -152,11 +162,13 @@ bn_status bn_get_offsets(bn_problem p, uint16_t* host_u);
 
 /* host: uint16 [H*W][T] hit counts.  Requires bn_compute_errors. */
 bn_status bn_get_counts(bn_problem p, uint16_t* host);
-/* host: float [H*W][T] error vectors.  Requires bn_compute_errors. */
+/* host: float [H*W][T + T_G] error vectors (Heaviside rows, then Gaussian
+ * rows).  Requires bn_compute_errors. */
 bn_status bn_get_errors(bn_problem p, float* host);
-/* Integrand table as used (heavisides [T], nullable) and the FP64 exact
- * integrals (areas [T], nullable). */
-bn_status bn_get_integrands(bn_problem p, bn_heaviside* heavisides, double* areas);
+/* Integrand tables as used and their FP64 exact integrals; every pointer is
+ * nullable: heavisides [T], areas [T], gaussians [T_G], gauss_integrals [T_G]. */
+bn_status bn_get_integrands(bn_problem p, bn_heaviside* heavisides, double* areas,
+                            bn_gaussian* gaussians, double* gauss_integrals);
 /* The N scrambled samples of one pixel in van der Corput order k = 0..N-1,
  * computed on the device: host uint16 [N][2].  Synchronises. */
 bn_status bn_get_points(bn_problem p, uint32_t pixel, uint16_t* host);
@@ -217,6 +229,10 @@ bn_status bn_window_classes(const bn_config* cfg, uint32_t* n_classes, uint32_t*
 bn_status bn_heaviside_area(const bn_heaviside* h, double* out);
 /* The Philox-drawn Heavisides bn_create_problem uses when given NULL. */
 bn_status bn_draw_heavisides(uint64_t seed, uint32_t problem_id, uint32_t t, bn_heaviside* out);
+/* The Philox-drawn Gaussians bn_create_problem uses when given NULL. */
+bn_status bn_draw_gaussians(uint64_t seed, uint32_t problem_id, uint32_t t, bn_gaussian* out);
+/* Exact integral (FP64) of one Gaussian over the unit square (erf product). */
+bn_status bn_gaussian_integral(const bn_gaussian* g, double* out);
 
 const char* bn_status_string(bn_status s);
 const char* bn_last_error(void);

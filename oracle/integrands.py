@@ -105,3 +105,10 @@ def heaviside_table_philox(t: int, seed: int, problem: int = 0) -> dict:
     return {"nx": nx, "ny": ny,
             "cx": (w[:, 1] >> np.uint32(16)).astype(np.uint16),
             "cy": (w[:, 2] >> np.uint32(16)).astype(np.uint16)}
+
+
+def gaussian_table_philox(t: int, seed: int, problem: int = 0) -> dict:
+    """Gaussians drawn from counters (t, 1, problem, S_INTEG): centre
+    (w0, w1) 2**-32, standard deviation 0.05 + 0.25 w2 2**-32."""
+    w = philox.draw(np.arange(t), 1, problem, philox.S_INTEG, seed).astype(np.float64)
+    return {"mx": w[:, 0] * 2.0 ** -32, "my": w[:, 1] * 2.0 ** -32, "s": 0.05 + 0.25 * (w[:, 2] * 2.0 ** -32)}

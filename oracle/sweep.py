@@ -19,7 +19,9 @@ quarter of the pixels move concurrently.  Readings used here:
     raise the sum instead (ascend), the only sign under which swapping pixels
     lowers the blurred error.
 
-Decisions use the exact integer form of the energy change (energy module).
+Decisions use the exact integer form of the energy change for Heaviside rows
+(energy module); Gaussian rows (Sec. 3.5's low-frequency integrands) add their
+FP64 plain-form change, and the decision is taken on the sum.
 
 Test infrastructure: this file is part of the CPU oracle.
 """
@@ -45,10 +47,14 @@ class Problem:
     problem_id: int
     table: dict                       # Heaviside table (synthgen format)
     objective: int = 1                # +1: accept dE < 0 (descend); -1: accept dE > 0
+    gauss: dict | None = None         # Gaussian table (synthgen format), optional
 
     def __post_init__(self):
         validate(self)
         self.areas = integrands.heaviside_areas(self.table)
+        tg = 0 if self.gauss is None else len(self.gauss["mx"])
+        self.gauss_integrals = (integrands.gaussian_integrals(self.gauss) if tg
+                                else np.zeros(0, dtype=np.float64))
 
 
 def validate(p) -> None:
@@ -72,6 +78,7 @@ def validate(p) -> None:
 class State:
     u: np.ndarray            # int64 [H, W, 2]  (Q0.16 offsets)
     c: np.ndarray            # int64 [H, W, T]  (hit counts)
+    g: np.ndarray | None = None   # float64 [H, W, T_G] Gaussian estimates
     sweep: int = 0
     accepts: list = field(default_factory=list)   # per phase
 
@@ -79,7 +86,11 @@ class State:
 def initial_state(prob: Problem, u0: np.ndarray) -> State:
     u = np.asarray(u0, dtype=np.int64).reshape(prob.height, prob.width, 2).copy()
     c = estimator.hit_counts(prob.n, prob.g, u.reshape(-1, 2), prob.table)
-    return State(u=u, c=c.reshape(prob.height, prob.width, -1))
+    g = None
+    if prob.gauss is not None and len(prob.gauss["mx"]):
+        g = estimator.gauss_estimates(prob.n, prob.g, u.reshape(-1, 2), prob.gauss).reshape(
+            prob.height, prob.width, -1)
+    return State(u=u, c=c.reshape(prob.height, prob.width, -1), g=g)
 
 
 def philox_offsets(prob: Problem) -> np.ndarray:
@@ -108,11 +119,19 @@ def phase(prob: Problem, st: State, kappa: int) -> dict:
     c_new = estimator.hit_counts(prob.n, prob.g, u_new, prob.table)
     xd = energy.delta_class_sums(st.c, ys, xs, c_new, prob.radius)
     acc = energy.weighted_class_sum(xd, prob.radius, prob.sigma)
-    accept = (acc < 0.0) if prob.objective == 1 else (acc > 0.0)
+    delta = acc * (2.0 / (prob.n * prob.n))
+    g_new = None
+    if st.g is not None:
+        g_new = estimator.gauss_estimates(prob.n, prob.g, u_new, prob.gauss)
+        delta = delta + np.array([energy.delta_plain(st.g, y, x, g_new[j], prob.radius, prob.sigma)
+                                  for j, (y, x) in enumerate(zip(ys, xs))])
+    accept = (delta < 0.0) if prob.objective == 1 else (delta > 0.0)
     st.u[ys[accept], xs[accept]] = u_new[accept]
     st.c[ys[accept], xs[accept]] = c_new[accept]
-    return {"ys": ys, "xs": xs, "u_new": u_new, "c_new": c_new, "xd": xd,
-            "delta": acc * (2.0 / (prob.n * prob.n)), "accept": accept}
+    if st.g is not None:
+        st.g[ys[accept], xs[accept]] = g_new[accept]
+    return {"ys": ys, "xs": xs, "u_new": u_new, "c_new": c_new, "g_new": g_new, "xd": xd,
+            "delta": delta, "accept": accept}
 
 
 def sweep(prob: Problem, st: State) -> None:
@@ -129,8 +148,15 @@ def run(prob: Problem, st: State, k: int) -> State:
 
 
 def errors(prob: Problem, st: State) -> np.ndarray:
-    return estimator.errors_from_counts(st.c, prob.n, prob.areas)
+    """Error vectors [H, W, T + T_G]: Heaviside rows then Gaussian rows."""
+    e = estimator.errors_from_counts(st.c, prob.n, prob.areas)
+    if st.g is not None:
+        e = np.concatenate([e, st.g - prob.gauss_integrals], axis=-1)
+    return e
 
 
 def energy_of(prob: Problem, st: State) -> float:
-    return energy.energy_exact(st.c, prob.n, prob.radius, prob.sigma)
+    e = energy.energy_exact(st.c, prob.n, prob.radius, prob.sigma)
+    if st.g is not None:
+        e += energy.energy_plain(st.g, prob.radius, prob.sigma)
+    return e

@@ -45,10 +45,15 @@ class SweepStats(C.Structure):
 
 
 HEAVISIDE_DTYPE = np.dtype([("nx", "<i2"), ("ny", "<i2"), ("cx", "<u2"), ("cy", "<u2")])
+GAUSSIAN_DTYPE = np.dtype([("mx", "<f8"), ("my", "<f8"), ("s", "<f8")])
+
+
+class Gaussian(C.Structure):
+    _fields_ = [("mx", C.c_double), ("my", C.c_double), ("s", C.c_double)]
 
 _P = C.c_void_p
 _SIGNATURES = {
-    "bn_create_problem": [C.POINTER(Config), _P, _P, C.POINTER(_P)],
+    "bn_create_problem": [C.POINTER(Config), _P, _P, _P, C.POINTER(_P)],
     "bn_destroy_problem": [_P],
     "bn_init_offsets": [_P, _P],
     "bn_compute_errors": [_P],
@@ -58,7 +63,7 @@ _SIGNATURES = {
     "bn_get_offsets": [_P, _P],
     "bn_get_counts": [_P, _P],
     "bn_get_errors": [_P, _P],
-    "bn_get_integrands": [_P, _P, _P],
+    "bn_get_integrands": [_P, _P, _P, _P, _P],
     "bn_get_points": [_P, C.c_uint32, _P],
     "bn_delta_energy": [_P, _P, _P, C.c_uint32, _P, _P],
     "bn_get_sweep_index": [_P, C.POINTER(C.c_uint64)],
@@ -76,6 +81,8 @@ _SIGNATURES = {
     "bn_window_classes": [C.POINTER(Config), C.POINTER(C.c_uint32), _P, _P],
     "bn_heaviside_area": [C.POINTER(Heaviside), C.POINTER(C.c_double)],
     "bn_draw_heavisides": [C.c_uint64, C.c_uint32, C.c_uint32, _P],
+    "bn_draw_gaussians": [C.c_uint64, C.c_uint32, C.c_uint32, _P],
+    "bn_gaussian_integral": [C.POINTER(Gaussian), C.POINTER(C.c_double)],
 }
 
 _lib = None
@@ -156,20 +163,46 @@ def draw_heavisides(seed: int, problem_id: int, t: int) -> np.ndarray:
     return out
 
 
+def gaussian_array(table: dict) -> np.ndarray:
+    """synthgen Gaussian table -> packed bn_gaussian array."""
+    out = np.empty(len(table["mx"]), dtype=GAUSSIAN_DTYPE)
+    for k in ("mx", "my", "s"):
+        out[k] = table[k]
+    return out
+
+
+def draw_gaussians(seed: int, problem_id: int, t: int) -> np.ndarray:
+    out = np.zeros(t, dtype=GAUSSIAN_DTYPE)
+    _call("bn_draw_gaussians", seed, problem_id, t, _ptr(out))
+    return out
+
+
+def gaussian_integral(mx, my, s) -> float:
+    g = Gaussian(float(mx), float(my), float(s))
+    out = C.c_double()
+    _call("bn_gaussian_integral", C.byref(g), C.byref(out))
+    return out.value
+
+
 # ------------------------------------------------------------------- problems
 class Problem:
     """Owns one ``bn_problem`` handle."""
 
-    def __init__(self, cfg: Config, heavisides: np.ndarray | None = None, stream: int | None = None):
+    def __init__(self, cfg: Config, heavisides: np.ndarray | None = None, stream: int | None = None,
+                 gaussians: np.ndarray | None = None):
         self.cfg = cfg
         self.P = cfg.width * cfg.height
         self.T = cfg.t_heaviside
+        self.TG = cfg.t_gauss
         self.M = self.P // (cfg.colour_k * cfg.colour_k)
         h = None if heavisides is None else np.ascontiguousarray(heavisides, dtype=HEAVISIDE_DTYPE)
         if h is not None and h.shape[0] != cfg.t_heaviside:
             raise ValueError("heaviside table length differs from t_heaviside")
+        g = None if gaussians is None else np.ascontiguousarray(gaussians, dtype=GAUSSIAN_DTYPE)
+        if g is not None and g.shape[0] != cfg.t_gauss:
+            raise ValueError("gaussian table length differs from t_gauss")
         handle = C.c_void_p()
-        _call("bn_create_problem", C.byref(cfg), _ptr(h), C.c_void_p(stream or 0), C.byref(handle))
+        _call("bn_create_problem", C.byref(cfg), _ptr(h), _ptr(g), C.c_void_p(stream or 0), C.byref(handle))
         self.handle = handle
 
     def close(self):
@@ -228,15 +261,18 @@ class Problem:
         return out
 
     def get_errors(self) -> np.ndarray:
-        out = np.zeros((self.P, self.T), dtype=np.float32)
+        """float32 [P, T + T_G]: Heaviside rows, then Gaussian rows."""
+        out = np.zeros((self.P, self.T + self.TG), dtype=np.float32)
         _call("bn_get_errors", self.handle, _ptr(out))
         return out
 
-    def get_integrands(self):
+    def get_integrands(self, gaussians: bool = False):
         h = np.zeros(self.T, dtype=HEAVISIDE_DTYPE)
         a = np.zeros(self.T, dtype=np.float64)
-        _call("bn_get_integrands", self.handle, _ptr(h), _ptr(a))
-        return h, a
+        g = np.zeros(self.TG, dtype=GAUSSIAN_DTYPE)
+        gi = np.zeros(self.TG, dtype=np.float64)
+        _call("bn_get_integrands", self.handle, _ptr(h), _ptr(a), _ptr(g), _ptr(gi))
+        return (h, a, g, gi) if gaussians else (h, a)
 
     def get_points(self, pixel: int) -> np.ndarray:
         out = np.zeros((self.cfg.n, 2), dtype=np.uint16)
@@ -319,8 +355,8 @@ class Batch:
         self.close()
 
 
-def create_problem(workload: dict, heavisides=None, stream=None, **overrides) -> Problem:
+def create_problem(workload: dict, heavisides=None, stream=None, gaussians=None, **overrides) -> Problem:
     """Create a problem from a workload description (synthgen format)."""
     w = dict(workload)
     w.update(overrides)
-    return Problem(make_config(**w), heavisides, stream)
+    return Problem(make_config(**w), heavisides, stream, gaussians)

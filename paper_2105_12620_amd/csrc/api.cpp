@@ -101,6 +101,19 @@ bn_status heaviside_area_checked(const bn_heaviside& h, double* out) {
   return BN_OK;
 }
 
+// Integral of exp(-|x - mu|^2 / (2 s^2)) over [0,1]^2 (separable, erf).
+double gaussian_integral(double mx, double my, double sd) {
+  const double c = sd * std::sqrt(M_PI / 2.0), r = sd * std::sqrt(2.0);
+  return c * (std::erf((1.0 - mx) / r) + std::erf(mx / r)) * c * (std::erf((1.0 - my) / r) + std::erf(my / r));
+}
+
+bn_status gaussian_checked(const bn_gaussian& g, double* out) {
+  if (!(g.s > 0.0) || !std::isfinite(g.s) || !std::isfinite(g.mx) || !std::isfinite(g.my))
+    return fail(BN_EINVAL, "Gaussian needs finite centre and s > 0");
+  *out = gaussian_integral(g.mx, g.my, g.s);
+  return BN_OK;
+}
+
 // ---------------------------------------------------------------- windows
 void window_classes(uint32_t r, double sigma, std::vector<uint32_t>& d, std::vector<double>& w) {
   d.clear();
@@ -150,6 +163,11 @@ struct bn_problem_s {
   DevView v{};
   std::vector<bn_heaviside> heav;
   std::vector<double> area64;
+  std::vector<bn_gaussian> gauss;
+  std::vector<double> gint64;
+  double* gsum = nullptr;
+  float* list_g = nullptr;
+  double* list_gdelta = nullptr;
   std::vector<uint32_t> cls_d;
   std::vector<double> cls_w;
   std::vector<void*> allocs;
@@ -163,6 +181,7 @@ struct bn_problem_s {
   uint64_t sweep = 0;
   bool have_offsets = false;
   bool have_counts = false;
+  bool errors_valid = false;   // FP32 error vectors match the counts
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool graph_failed = false;
@@ -243,7 +262,8 @@ bn_status validate(const bn_config* c) {
 bn_status supported(const bn_config* c) {
   if (c->n > MAX_N) return fail(BN_EUNSUPPORTED, "N > %u is not supported by this build", MAX_N);
   if (c->radius > 6) return fail(BN_EUNSUPPORTED, "radius > 6 is not supported by this build");
-  if (c->t_gauss) return fail(BN_EUNSUPPORTED, "Gaussian integrands are not supported by this build");
+  if (c->t_heaviside == 0) return fail(BN_EUNSUPPORTED, "at least one Heaviside integrand is required");
+  if (c->t_gauss > (1u << 16)) return fail(BN_EINVAL, "more than 65536 Gaussian integrands");
   if (c->precision == BN_BF16 && c->colour_k != 2)
     return fail(BN_EUNSUPPORTED, "the BF16 matrix-core form needs colour_k = 2");
   if (c->move != BN_REDRAW) return fail(BN_EUNSUPPORTED, "swap moves are not supported by this build");
@@ -292,15 +312,29 @@ bn_status ensure_list(bn_problem p, uint32_t m) {
   if ((s = p->alloc(&p->list_pix, m)) != BN_OK) return s;
   if ((s = p->alloc(&p->list_delta, m)) != BN_OK) return s;
   if ((s = p->alloc(&p->list_accept, m)) != BN_OK) return s;
+  if ((s = p->alloc(&p->list_g, (size_t)m * std::max<uint32_t>(p->v.tgp, 1))) != BN_OK) return s;
+  if ((s = p->alloc(&p->list_gdelta, m)) != BN_OK) return s;
   p->list_cap = m;
+  return BN_OK;
+}
+
+// Bring the FP32 error vectors up to date with the counts.
+bn_status refresh_errors(bn_problem p) {
+  if (p->errors_valid) return BN_OK;
+  HIPCHK(launch_errors(p->v, p->stream));
+  HIPCHK(launch_gauss_errors(p->v, p->stream));
+  p->errors_valid = true;
   return BN_OK;
 }
 
 bn_status record_sweep(bn_problem p) {
   for (uint32_t kappa = 0; kappa < p->cfg.colour_k * p->cfg.colour_k; ++kappa) {
     HIPCHK(launch_count(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
+    HIPCHK(launch_gauss_est(p->v, MODE_CLASS, p->v.pc, p->stream));
+    HIPCHK(launch_gauss_delta(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
     HIPCHK(launch_delta(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
     HIPCHK(launch_commit(p->v, kappa, p->stream));
+    HIPCHK(launch_gauss_commit(p->v, kappa, p->stream));
   }
   HIPCHK(launch_advance(p->v, p->stream));
   return BN_OK;
@@ -536,8 +570,26 @@ bn_status bn_draw_heavisides(uint64_t seed, uint32_t problem_id, uint32_t t, bn_
   return BN_OK;
 }
 
-bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides, void* stream,
-                            bn_problem* out) {
+bn_status bn_draw_gaussians(uint64_t seed, uint32_t problem_id, uint32_t t, bn_gaussian* out) {
+  if (!out && t) return fail(BN_EINVAL, "out is NULL");
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (uint32_t i = 0; i < t; ++i) {
+    uint32_t c[4] = {i, 1u, problem_id, S_INTEG};
+    philox10(c, k0, k1);
+    out[i].mx = (double)c[0] * 0x1p-32;
+    out[i].my = (double)c[1] * 0x1p-32;
+    out[i].s = 0.05 + 0.25 * ((double)c[2] * 0x1p-32);
+  }
+  return BN_OK;
+}
+
+bn_status bn_gaussian_integral(const bn_gaussian* g, double* out) {
+  if (!g || !out) return fail(BN_EINVAL, "NULL argument");
+  return gaussian_checked(*g, out);
+}
+
+bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides, const bn_gaussian* gaussians,
+                            void* stream, bn_problem* out) {
   bn_status s = validate(cfg);
   if (s != BN_OK) return s;
   if (!out) return fail(BN_EINVAL, "out is NULL");
@@ -554,6 +606,15 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   for (uint32_t t = 0; t < cfg->t_heaviside; ++t)
     if ((s = heaviside_area_checked(heav[t], &area[t])) != BN_OK)
       return fail(s, "integrand %u: %s", t, g_last_error.c_str());
+  std::vector<bn_gaussian> gauss(cfg->t_gauss);
+  if (gaussians)
+    std::copy(gaussians, gaussians + cfg->t_gauss, gauss.begin());
+  else if ((s = bn_draw_gaussians(cfg->seed, cfg->problem_id, cfg->t_gauss, gauss.data())) != BN_OK)
+    return s;
+  std::vector<double> gint(cfg->t_gauss);
+  for (uint32_t t = 0; t < cfg->t_gauss; ++t)
+    if ((s = gaussian_checked(gauss[t], &gint[t])) != BN_OK)
+      return fail(s, "Gaussian %u: %s", t, g_last_error.c_str());
 
   if ((s = check_device()) != BN_OK) return s;
 
@@ -561,6 +622,8 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   p->cfg = *cfg;
   p->heav = heav;
   p->area64 = area;
+  p->gauss = gauss;
+  p->gint64 = gint;
   window_classes(cfg->radius, cfg->sigma, p->cls_d, p->cls_w);
   if (stream) {
     p->stream = (hipStream_t)stream;
@@ -594,6 +657,8 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   v.ncls = (uint32_t)p->cls_d.size();
   v.tch = std::min<uint32_t>(256, v.tp);
   v.slice_target = 512;
+  v.tg = cfg->t_gauss;
+  v.tgp = round_up(v.tg, 64);
   const size_t P = (size_t)v.w * v.h;
 
   std::vector<uint32_t> lat(v.n);
@@ -631,6 +696,34 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   v.ihp = ihp_d;
   v.area = area_d;
   v.wd = wd_d;
+  std::vector<double2> gmu(v.tgp, make_double2(0.0, 0.0));
+  std::vector<double> gscale(v.tgp, 0.0), gintp(v.tgp, 0.0);
+  for (uint32_t t = 0; t < v.tg; ++t) {
+    gmu[t] = make_double2(gauss[t].mx, gauss[t].my);
+    gscale[t] = M_LOG2E / (2.0 * gauss[t].s * gauss[t].s);
+    gintp[t] = gint[t];
+  }
+  if (v.tgp) {
+    double2* gmu_d;
+    double *gscale_d, *gint_d;
+    if ((s = p->alloc(&gmu_d, v.tgp)) != BN_OK || (s = p->alloc(&gscale_d, v.tgp)) != BN_OK ||
+        (s = p->alloc(&gint_d, v.tgp)) != BN_OK || (s = p->alloc(&v.gest, P * v.tgp)) != BN_OK ||
+        (s = p->alloc(&v.gerr, P * v.tgp)) != BN_OK || (s = p->alloc(&v.g_new, (size_t)v.pc * v.tgp)) != BN_OK ||
+        (s = p->alloc(&v.gdelta, v.pc)) != BN_OK || (s = p->alloc(&p->gsum, v.ncls)) != BN_OK) {
+      delete p;
+      return s;
+    }
+    v.gmu = gmu_d;
+    v.gscale = gscale_d;
+    v.gint = gint_d;
+    hipError_t ge = hipMemcpyAsync(gmu_d, gmu.data(), v.tgp * sizeof(double2), hipMemcpyHostToDevice, p->stream);
+    if (ge == hipSuccess) ge = hipMemcpyAsync(gscale_d, gscale.data(), v.tgp * 8, hipMemcpyHostToDevice, p->stream);
+    if (ge == hipSuccess) ge = hipMemcpyAsync(gint_d, gintp.data(), v.tgp * 8, hipMemcpyHostToDevice, p->stream);
+    if (ge != hipSuccess) {
+      delete p;
+      return fail(BN_EHIP, "uploading Gaussian tables: %s", hipGetErrorString(ge));
+    }
+  }
   v.pix_list = nullptr;
   const unsigned long long zero[4] = {0ull, 0ull, 0ull, 0ull};
   v.mfma = cfg->precision == BN_BF16 ? 1u : 0u;
@@ -676,7 +769,10 @@ bn_status bn_compute_errors(bn_problem p) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   if (!p->have_offsets) return fail(BN_ESTATE, "offsets are not initialised");
   HIPCHK(launch_count(p->v, MODE_ALL, 0, p->v.w * p->v.h, p->stream));
+  HIPCHK(launch_gauss_est(p->v, MODE_ALL, p->v.w * p->v.h, p->stream));
+  HIPCHK(launch_gauss_errors(p->v, p->stream));
   p->have_counts = true;
+  p->errors_valid = true;
   return BN_OK;
 }
 
@@ -699,6 +795,7 @@ bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats) {
     }
   }
   p->sweep += k;
+  if (k) p->errors_valid = false;
   if (stats) {
     HIPCHK(hipMemcpyAsync(after, p->v.ctr, sizeof after, hipMemcpyDeviceToHost, p->stream));
     if ((s = sync(p)) != BN_OK) return s;
@@ -723,6 +820,16 @@ bn_status bn_energy(bn_problem p, double* out) {
   double acc = 0.0;
   for (uint32_t c = 0; c < p->v.ncls; ++c) acc = acc + p->cls_w[c] * (double)(long long)(2 * y[c]);
   *out = acc / ((double)p->v.n * (double)p->v.n);
+  if (p->v.tgp) {
+    std::vector<double> g(p->v.ncls);
+    HIPCHK(hipMemsetAsync(p->gsum, 0, p->v.ncls * sizeof(double), p->stream));
+    HIPCHK(launch_gauss_energy(p->v, p->gsum, p->stream));
+    HIPCHK(hipMemcpyAsync(g.data(), p->gsum, g.size() * 8, hipMemcpyDeviceToHost, p->stream));
+    if ((s = sync(p)) != BN_OK) return s;
+    double ga = 0.0;
+    for (uint32_t c = 0; c < p->v.ncls; ++c) ga = ga + p->cls_w[c] * (2.0 * g[c]);
+    *out = *out + ga;
+  }
   if (!std::isfinite(*out)) return fail(BN_ENUMERIC, "energy is not finite");
   return BN_OK;
 }
@@ -733,8 +840,13 @@ bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, doub
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
   for (uint32_t i = 0; i < n; ++i)
     if (!(sigmas[i] > 0.0) || !std::isfinite(sigmas[i])) return fail(BN_EINVAL, "blur sizes must be > 0");
+  {
+    bn_status rs = refresh_errors(p);
+    if (rs != BN_OK) return rs;
+  }
   const size_t P = (size_t)p->v.w * p->v.h;
-  const uint32_t nparts = blur_partials(p->v);
+  const uint32_t pitch_max = std::max(p->v.tp, p->v.tgp);
+  const uint32_t nparts = blur_partials(p->v, pitch_max);
   float *tmp = nullptr, *kx = nullptr, *ky = nullptr;
   int32_t *dx = nullptr, *dy = nullptr;
   double* part = nullptr;
@@ -743,7 +855,7 @@ bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, doub
     for (void* q : {(void*)tmp, (void*)kx, (void*)ky, (void*)dx, (void*)dy, (void*)part})
       if (q) (void)hipFree(q);
   };
-  hipError_t e = hipMalloc((void**)&tmp, P * p->v.tp * sizeof(float));
+  hipError_t e = hipMalloc((void**)&tmp, P * pitch_max * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void**)&kx, p->v.w * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void**)&ky, p->v.h * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void**)&dx, p->v.w * sizeof(int32_t));
@@ -760,23 +872,27 @@ bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, doub
     std::vector<int32_t> hdx, hdy;
     blur_taps(p->v.w, sigmas[i], hkx, hdx);
     blur_taps(p->v.h, sigmas[i], hky, hdy);
-    uint32_t np = 0;
     e = hipMemcpyAsync(kx, hkx.data(), hkx.size() * 4, hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dx, hdx.data(), hdx.size() * 4, hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(ky, hky.data(), hky.size() * 4, hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dy, hdy.data(), hdy.size() * 4, hipMemcpyHostToDevice, p->stream);
-    if (e == hipSuccess)
-      e = launch_blur(p->v, kx, (uint32_t)hkx.size(), dx, ky, (uint32_t)hky.size(), dy, tmp, part, &np,
-                      p->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, (size_t)np * 8, hipMemcpyDeviceToHost, p->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    double acc = 0.0;
+    const float* fields[2] = {p->v.err, p->v.gerr};
+    const uint32_t pitches[2] = {p->v.tp, p->v.tgp}, valids[2] = {p->v.t, p->v.tg};
+    for (int f = 0; f < 2 && e == hipSuccess; ++f) {
+      if (!pitches[f]) continue;
+      uint32_t np = 0;
+      e = launch_blur(p->v, fields[f], pitches[f], valids[f], kx, (uint32_t)hkx.size(), dx, ky,
+                      (uint32_t)hky.size(), dy, tmp, part, &np, p->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, (size_t)np * 8, hipMemcpyDeviceToHost, p->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+      for (uint32_t b = 0; b < np && e == hipSuccess; ++b) acc += hp[b];
+    }
     if (e != hipSuccess) {
       release();
       return fail(BN_EHIP, "quality metric: %s", hipGetErrorString(e));
     }
-    double acc = 0.0;
-    for (uint32_t b = 0; b < np; ++b) acc += hp[b];
-    out[i] = std::sqrt(acc / ((double)P * p->v.t));
+    out[i] = std::sqrt(acc / ((double)P * (p->v.t + p->v.tg)));
   }
   release();
   return BN_OK;
@@ -798,15 +914,23 @@ bn_status bn_get_counts(bn_problem p, uint16_t* host) {
 bn_status bn_get_errors(bn_problem p, float* host) {
   if (!p || !host) return fail(BN_EINVAL, "NULL argument");
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
-  HIPCHK(hipMemcpy2DAsync(host, p->v.t * 4, p->v.err, p->v.tp * 4, p->v.t * 4, (size_t)p->v.w * p->v.h,
-                          hipMemcpyDeviceToHost, p->stream));
+  bn_status rs = refresh_errors(p);
+  if (rs != BN_OK) return rs;
+  const size_t P = (size_t)p->v.w * p->v.h, row = (size_t)(p->v.t + p->v.tg) * 4;
+  HIPCHK(hipMemcpy2DAsync(host, row, p->v.err, p->v.tp * 4, p->v.t * 4, P, hipMemcpyDeviceToHost, p->stream));
+  if (p->v.tg)
+    HIPCHK(hipMemcpy2DAsync(host + p->v.t, row, p->v.gerr, p->v.tgp * 4, p->v.tg * 4, P, hipMemcpyDeviceToHost,
+                            p->stream));
   return sync(p);
 }
 
-bn_status bn_get_integrands(bn_problem p, bn_heaviside* heavisides, double* areas) {
+bn_status bn_get_integrands(bn_problem p, bn_heaviside* heavisides, double* areas, bn_gaussian* gaussians,
+                            double* gauss_integrals) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   if (heavisides) std::copy(p->heav.begin(), p->heav.end(), heavisides);
   if (areas) std::copy(p->area64.begin(), p->area64.end(), areas);
+  if (gaussians) std::copy(p->gauss.begin(), p->gauss.end(), gaussians);
+  if (gauss_integrals) std::copy(p->gint64.begin(), p->gint64.end(), gauss_integrals);
   return BN_OK;
 }
 
@@ -840,9 +964,13 @@ bn_status bn_delta_energy(bn_problem p, const uint32_t* pixels, const uint16_t* 
   lv.pix_list = p->list_pix;
   lv.delta = p->list_delta;
   lv.accept = p->list_accept;
+  lv.g_new = p->list_g;
+  lv.gdelta = p->list_gdelta;
   HIPCHK(hipMemcpyAsync(p->list_pix, pixels, (size_t)m * 4, hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipMemcpyAsync(p->list_u, proposals, (size_t)m * 4, hipMemcpyHostToDevice, p->stream));
   HIPCHK(launch_count(lv, MODE_LIST, 0, m, p->stream));
+  HIPCHK(launch_gauss_est(lv, MODE_LIST, m, p->stream));
+  HIPCHK(launch_gauss_delta(lv, MODE_LIST, 0, m, p->stream));
   HIPCHK(launch_delta(lv, MODE_LIST, 0, m, p->stream));
   HIPCHK(hipMemcpyAsync(out_de, p->list_delta, (size_t)m * 8, hipMemcpyDeviceToHost, p->stream));
   if (out_counts) return untile_counts(p, p->list_cnt, m, out_counts);
@@ -875,6 +1003,7 @@ bn_status bn_phase_propose(bn_problem p, uint32_t kappa) {
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
   if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
   HIPCHK(launch_count(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
+  HIPCHK(launch_gauss_est(p->v, MODE_CLASS, p->v.pc, p->stream));
   return BN_OK;
 }
 
@@ -882,6 +1011,7 @@ bn_status bn_phase_evaluate(bn_problem p, uint32_t kappa) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
   if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
+  HIPCHK(launch_gauss_delta(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
   HIPCHK(launch_delta(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
   return BN_OK;
 }
@@ -891,6 +1021,8 @@ bn_status bn_phase_commit(bn_problem p, uint32_t kappa) {
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
   if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
   HIPCHK(launch_commit(p->v, kappa, p->stream));
+  HIPCHK(launch_gauss_commit(p->v, kappa, p->stream));
+  p->errors_valid = false;
   return BN_OK;
 }
 
@@ -924,6 +1056,7 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
     if (p->stream != members[0]->stream) return fail(BN_EINVAL, "members must share one stream");
     if (p->cfg.colour_k != members[0]->cfg.colour_k) return fail(BN_EINVAL, "members must share colour_k");
     if (p->cfg.precision != BN_FP32) return fail(BN_EUNSUPPORTED, "batched members must use FP32 precision");
+    if (p->cfg.t_gauss) return fail(BN_EUNSUPPORTED, "batched members must have Heaviside integrands only");
     for (uint32_t j = 0; j < i; ++j)
       if (members[j] == p) return fail(BN_EINVAL, "member %u appears twice", i);
   }
@@ -1008,7 +1141,10 @@ bn_status bn_batch_sweep(bn_batch b, uint32_t k) {
     b->graph = g;
   }
   for (uint32_t i = 0; i < k; ++i) HIPCHK(hipGraphLaunch(b->graph_exec, b->stream));
-  for (bn_problem p : b->members) p->sweep += k;
+  for (bn_problem p : b->members) {
+    p->sweep += k;
+    if (k) p->errors_valid = false;
+  }
   return BN_OK;
 }
 

@@ -43,6 +43,15 @@ struct DevView {
   uint32_t mfma;             // 1: BF16 matrix-core evaluation of the colour phases
   uint32_t tch;              // integrands per wave in the counting kernels (launch shape)
   uint32_t slice_target;     // workgroups the staged energy-change launch aims for
+  // Gaussian integrands (tgp = 0 when there are none)
+  uint32_t tg, tgp;          // count, padded to 64
+  const double2* gmu;        // [tgp] centres
+  const double* gscale;      // [tgp] log2(e) / (2 s^2)  (0 for padding)
+  const double* gint;        // [tgp] exact integrals
+  float* gest;               // [P][tgp] estimates
+  float* gerr;               // [P][tgp] errors g - I (refreshed on demand)
+  float* g_new;              // [M][tgp] estimates of the proposals
+  double* gdelta;            // [M] Gaussian part of the energy change
 };
 
 hipError_t launch_init_offsets(const DevView& v, hipStream_t s);
@@ -50,13 +59,19 @@ hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
 hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s);
 uint32_t xpart_words(const DevView& v);
 hipError_t launch_commit(const DevView& v, uint32_t kappa, hipStream_t s);
+hipError_t launch_errors(const DevView& v, hipStream_t s);
 hipError_t launch_advance(const DevView& v, hipStream_t s);
 hipError_t launch_points(const DevView& v, uint32_t pixel, uint32_t* out, hipStream_t s);
 hipError_t launch_energy(const DevView& v, unsigned long long* y, hipStream_t s);
-hipError_t launch_blur(const DevView& v, const float* kx, uint32_t nkx, const int32_t* dx,
-                       const float* ky, uint32_t nky, const int32_t* dy, float* tmp,
-                       double* partial, uint32_t* npartial, hipStream_t s);
-uint32_t blur_partials(const DevView& v);
+hipError_t launch_blur(const DevView& v, const float* field, uint32_t pitch, uint32_t valid, const float* kx,
+                       uint32_t nkx, const int32_t* dx, const float* ky, uint32_t nky, const int32_t* dy,
+                       float* tmp, double* partial, uint32_t* npartial, hipStream_t s);
+uint32_t blur_partials(const DevView& v, uint32_t pitch);
+hipError_t launch_gauss_est(const DevView& v, int mode, uint32_t m, hipStream_t s);
+hipError_t launch_gauss_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s);
+hipError_t launch_gauss_commit(const DevView& v, uint32_t kappa, hipStream_t s);
+hipError_t launch_gauss_errors(const DevView& v, hipStream_t s);
+hipError_t launch_gauss_energy(const DevView& v, double* gsum, hipStream_t s);
 
 // batched launches: member i of a group owns blocks pre[i] .. pre[i+1]-1
 int count_kind(const DevView& v);

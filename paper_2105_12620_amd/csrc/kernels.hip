@@ -7,9 +7,12 @@
 //                          contiguous and neighbouring pixels' tiles are
 //                          adjacent, so a row of pixels for 8 integrands is
 //                          one contiguous run
-//   err  float  [P][Tp]    error vectors c/N - A_t
+//   err  float  [P][Tp]    error vectors c/N - A_t (refreshed from the counts
+//                          when read)
 //   lat  uint32 [N]        rank-1 lattice points (Sec. 3.2), x | y << 16
 //   ihp  int2   [Tp]       Heaviside (n packed as two int16, D' = n.(C - 2^15))
+//   gest float  [P][TGp]   Gaussian estimates (TGp = Gaussian count rounded
+//                          up to 64; padded rows evaluate exp(0) = 1)
 // Side buffers of one colour phase (M class pixels): u_new [M],
 // c_new [Tp/8][M][8] (same tiling), delta [M], accept [M].
 //
@@ -345,8 +348,10 @@ __global__ __launch_bounds__(256) void k_delta(DevView v, uint32_t kappa, uint32
     acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)xv));
   }
   if (lane == 0) {
-    v.delta[j] = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
-    v.accept[j] = (v.objective > 0) ? (acc < 0.0) : (acc > 0.0);
+    double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+    if (v.tgp) total = __dadd_rn(total, v.gdelta[j]);
+    v.delta[j] = total;
+    v.accept[j] = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
   }
 }
 
@@ -538,8 +543,10 @@ __device__ __forceinline__ void delta_finish_body(const DevView& v, long long* _
     xsum[(size_t)c * v.pc + j] = 0;
     acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)x));
   }
-  v.delta[j] = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
-  v.accept[j] = (v.objective > 0) ? (acc < 0.0) : (acc > 0.0);
+  double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+  if (v.tgp) total = __dadd_rn(total, v.gdelta[j]);
+  v.delta[j] = total;
+  v.accept[j] = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
 }
 
 __global__ __launch_bounds__(256) void k_delta_finish(DevView v, long long* __restrict__ xsum) {
@@ -795,8 +802,10 @@ __global__ __launch_bounds__(256) void k_delta_recheck(DevView v, uint32_t kappa
     acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)xv));
   }
   if (lane == 0) {
-    const bool ok = (v.objective > 0) ? (acc < 0.0) : (acc > 0.0);
-    v.delta[j] = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+    double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+    if (v.tgp) total = __dadd_rn(total, v.gdelta[j]);
+    const bool ok = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
+    v.delta[j] = total;
     if (!ok) {
       v.accept[j] = 0;
       atomicAdd(&v.ctr[2], 1ull);
@@ -818,25 +827,33 @@ __device__ __forceinline__ void commit_body(const DevView& v, uint32_t kappa, ui
     atomicAdd(&v.ctr[1], 1ull);
   }
   const uint32_t P = v.w * v.h;
-  float* e = v.err + (size_t)p * v.tp;
+  for (uint32_t tt = lane; tt < (v.tp >> 3); tt += 64)
+    *(uint4*)(v.cnt + ((size_t)tt * P + p) * 8) = *(const uint4*)(v.c_new + ((size_t)tt * v.pc + j) * 8);
+}
+
+// FP32 error vectors e = c/N - A_t of every pixel from the exact counts
+// (refreshed on demand; thread per (integrand tile, pixel), pixels fastest).
+__global__ __launch_bounds__(256) void k_errors(DevView v) {
+  const uint32_t P = v.w * v.h;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)P * (v.tp >> 3)) return;
+  const uint32_t tt = (uint32_t)(i / P), p = (uint32_t)(i - (size_t)tt * P);
+  const uint4 c8 = *(const uint4*)(v.cnt + i * 8);
+  const uint32_t t = tt * 8;
   const float inv_n = 1.0f / (float)v.n;
-  for (uint32_t tt = lane; tt < (v.tp >> 3); tt += 64) {
-    const uint4 c8 = *(const uint4*)(v.c_new + ((size_t)tt * v.pc + j) * 8);
-    *(uint4*)(v.cnt + ((size_t)tt * P + p) * 8) = c8;
-    const uint32_t t = tt * 8;
-    const float4 a = *(const float4*)(v.area + t), b = *(const float4*)(v.area + t + 4);
-    float4 lo, hi;
-    lo.x = (float)(c8.x & 0xFFFFu) * inv_n - a.x;
-    lo.y = (float)(c8.x >> 16) * inv_n - a.y;
-    lo.z = (float)(c8.y & 0xFFFFu) * inv_n - a.z;
-    lo.w = (float)(c8.y >> 16) * inv_n - a.w;
-    hi.x = (float)(c8.z & 0xFFFFu) * inv_n - b.x;
-    hi.y = (float)(c8.z >> 16) * inv_n - b.y;
-    hi.z = (float)(c8.w & 0xFFFFu) * inv_n - b.z;
-    hi.w = (float)(c8.w >> 16) * inv_n - b.w;
-    *(float4*)(e + t) = lo;
-    *(float4*)(e + t + 4) = hi;
-  }
+  const float4 a = *(const float4*)(v.area + t), b = *(const float4*)(v.area + t + 4);
+  float4 lo, hi;
+  lo.x = (float)(c8.x & 0xFFFFu) * inv_n - a.x;
+  lo.y = (float)(c8.x >> 16) * inv_n - a.y;
+  lo.z = (float)(c8.y & 0xFFFFu) * inv_n - a.z;
+  lo.w = (float)(c8.y >> 16) * inv_n - a.w;
+  hi.x = (float)(c8.z & 0xFFFFu) * inv_n - b.x;
+  hi.y = (float)(c8.z >> 16) * inv_n - b.y;
+  hi.z = (float)(c8.w & 0xFFFFu) * inv_n - b.z;
+  hi.w = (float)(c8.w >> 16) * inv_n - b.w;
+  float* e = v.err + (size_t)p * v.tp + t;
+  *(float4*)e = lo;
+  *(float4*)(e + 4) = hi;
 }
 
 __global__ __launch_bounds__(256) void k_commit(DevView v, uint32_t kappa) { commit_body(v, kappa, blockIdx.x); }
@@ -919,36 +936,38 @@ __global__ __launch_bounds__(256) void k_energy(DevView v, unsigned long long* y
 }
 
 // ------------------------------------------------------------ blur criterion
-// Separable periodised Gaussian blur of the error tile (Sec. 3.3): taps
-// (d_i, k_i) with d_i in [0, W); b(x) = sum_i k_i e((x - d_i) mod W).
-__global__ __launch_bounds__(256) void k_blur_x(DevView v, const float* __restrict__ kx,
-                                                const int32_t* __restrict__ dx, uint32_t nk,
-                                                float* __restrict__ out) {
+// Separable periodised Gaussian blur of an error tile (Sec. 3.3): taps
+// (d_i, k_i) with d_i in [0, W); b(x) = sum_i k_i e((x - d_i) mod W).  The
+// field is float [P][pitch] with `valid` meaningful columns.
+__global__ __launch_bounds__(256) void k_blur_x(DevView v, const float* __restrict__ field, uint32_t pitch,
+                                                const float* __restrict__ kx, const int32_t* __restrict__ dx,
+                                                uint32_t nk, float* __restrict__ out) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = wave_id();
-  const uint32_t nch = v.tp >> 6;
+  const uint32_t nch = pitch >> 6;
   const uint32_t p = wave / nch, ch = wave - p * nch;
   if (p >= v.w * v.h) return;
   const uint32_t y = p / v.w, x = p - y * v.w;
   const uint32_t t = ch * 64 + lane;
-  const float* rowbase = v.err + (size_t)y * v.w * v.tp + t;
+  const float* rowbase = field + (size_t)y * v.w * pitch + t;
   float acc = 0.0f;
   for (uint32_t i = 0; i < nk; ++i) {
     uint32_t xs = x + v.w - (uint32_t)dx[i];
     if (xs >= v.w) xs -= v.w;
-    acc = fmaf(kx[i], rowbase[(size_t)xs * v.tp], acc);
+    acc = fmaf(kx[i], rowbase[(size_t)xs * pitch], acc);
   }
-  out[(size_t)p * v.tp + t] = acc;
+  out[(size_t)p * pitch + t] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_blur_y_sq(DevView v, const float* __restrict__ ky,
+__global__ __launch_bounds__(256) void k_blur_y_sq(DevView v, uint32_t pitch, uint32_t valid,
+                                                   const float* __restrict__ ky,
                                                    const int32_t* __restrict__ dy, uint32_t nk,
                                                    const float* __restrict__ in,
                                                    double* __restrict__ partial) {
   __shared__ double red[4];
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = wave_id();
-  const uint32_t nch = v.tp >> 6;
+  const uint32_t nch = pitch >> 6;
   const uint32_t p = wave / nch, ch = wave - p * nch;
   double sq = 0.0;
   if (p < v.w * v.h) {
@@ -958,15 +977,138 @@ __global__ __launch_bounds__(256) void k_blur_y_sq(DevView v, const float* __res
     for (uint32_t i = 0; i < nk; ++i) {
       uint32_t ys = y + v.h - (uint32_t)dy[i];
       if (ys >= v.h) ys -= v.h;
-      acc = fmaf(ky[i], in[((size_t)ys * v.w + x) * v.tp + t], acc);
+      acc = fmaf(ky[i], in[((size_t)ys * v.w + x) * pitch + t], acc);
     }
-    if (t < v.t) sq = (double)acc * (double)acc;
+    if (t < valid) sq = (double)acc * (double)acc;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
   if (lane == 0) red[threadIdx.x >> 6] = sq;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ----------------------------------------------------- Gaussian integrands
+// Low-frequency test integrands (Sec. 3.5): f_t(x) = exp(-|x - mu_t|^2 / (2 s_t^2)).
+// Estimates g = (1/N) sum_k f_t(s_p^k) per pixel, lanes over integrands and
+// wave-uniform samples.  The exponent is formed in FP64 from the exact Q0.16
+// sample (the centres are FP64), exp2 runs in FP32 and the sum accumulates in
+// FP64; the estimate is stored in FP32.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, uint32_t m) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = wave_id();
+  const uint32_t nch = v.tgp >> 6;
+  const uint32_t j = wave / nch, ch = wave - j * nch;
+  if (j >= m) return;
+  uint32_t u;
+  float* out;
+  if (MODE == MODE_ALL) {
+    u = v.U[j];
+    out = v.gest + (size_t)j * v.tgp;
+  } else {
+    u = v.u_new[j];
+    out = v.g_new + (size_t)j * v.tgp;
+  }
+  const uint32_t t = ch * 64 + lane;
+  const double2 mu = v.gmu[t];
+  const double a = v.gscale[t];
+  double acc = 0.0;
+  for (uint32_t i = 0; i < v.n; ++i) {
+    const uint32_t sv = wrap_add(v.lat[i], u);
+    const double dx = (double)(sv & 0xFFFFu) * 0x1p-16 - mu.x;
+    const double dy = (double)(sv >> 16) * 0x1p-16 - mu.y;
+    acc += (double)exp2f((float)(-(dx * dx + dy * dy) * a));
+  }
+  out[t] = (float)(acc / (double)v.n);
+}
+
+// Gaussian rows' part of a move's energy change (plain form of Eq. (1) over
+// the window, FP64 arithmetic on the FP32 estimates); one wave per moved
+// pixel, lanes over integrands.  Written to gdelta[j]; the decision adds it to
+// the exact Heaviside part.
+template <int R, int MODE>
+__global__ __launch_bounds__(256) void k_delta_gauss(DevView v, uint32_t kappa, uint32_t m) {
+  constexpr Window<R> W = WinConst<R>::w;
+  constexpr int NCLS = WinConst<R>::NCLS;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t j = wave_id();
+  if (j >= m) return;
+  const uint32_t p = (MODE == MODE_CLASS) ? class_pixel(v, kappa, j) : v.pix_list[j];
+  const uint32_t y = p / v.w, x = p - y * v.w;
+  double cs[NCLS];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) cs[c] = 0.0;
+  for (uint32_t base = 0; base < v.tgp; base += 64) {
+    const uint32_t t = base + lane;
+    const double gn = v.g_new[(size_t)j * v.tgp + t], go = v.gest[(size_t)p * v.tgp + t];
+    const double d = gn - go, sm = gn + go;
+#pragma unroll
+    for (int mm = 0; mm < W.M; ++mm) {
+      const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
+      cs[W.cls[mm]] += d * (sm - 2.0 * (double)v.gest[(size_t)q * v.tgp + t]);
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) {
+    double xv = cs[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
+    acc += v.wd[c] * xv;
+  }
+  if (lane == 0) v.gdelta[j] = 2.0 * acc;
+}
+
+// Gaussian rows' part of the energy: per distance class, sum over the half
+// window of |g_p - g_q|^2 (FP64 atomics; doubled by the host).
+template <int R>
+__global__ __launch_bounds__(256) void k_energy_gauss(DevView v, double* gsum) {
+  constexpr Window<R> W = WinConst<R>::w;
+  constexpr int NCLS = WinConst<R>::NCLS;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t p = wave_id();
+  if (p >= v.w * v.h) return;
+  const uint32_t y = p / v.w, x = p - y * v.w;
+  double cs[NCLS];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) cs[c] = 0.0;
+  for (uint32_t base = 0; base < v.tgp; base += 64) {
+    const uint32_t t = base + lane;
+    const double gp = v.gest[(size_t)p * v.tgp + t];
+#pragma unroll
+    for (int mm = 0; mm < W.M; ++mm) {
+      if (W.oy[mm] > 0 || (W.oy[mm] == 0 && W.ox[mm] > 0)) {
+        const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
+        const double d = gp - (double)v.gest[(size_t)q * v.tgp + t];
+        cs[W.cls[mm]] += d * d;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) {
+    double xv = cs[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
+    if (lane == 0 && xv != 0.0) atomicAdd(&gsum[c], xv);
+  }
+}
+
+// Commit of accepted moves' Gaussian estimate rows.
+__global__ __launch_bounds__(256) void k_commit_gauss(DevView v, uint32_t kappa) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t j = wave_id();
+  if (j >= v.pc || !v.accept[j]) return;
+  const uint32_t p = class_pixel(v, kappa, j);
+  for (uint32_t t = lane; t < v.tgp; t += 64) v.gest[(size_t)p * v.tgp + t] = v.g_new[(size_t)j * v.tgp + t];
+}
+
+// Gaussian error rows g - I (refreshed on demand).
+__global__ __launch_bounds__(256) void k_gauss_errors(DevView v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)v.w * v.h * v.tgp) return;
+  const uint32_t t = (uint32_t)(i % v.tgp);
+  v.gerr[i] = (float)((double)v.gest[i] - v.gint[t]);
 }
 
 template <int MODE>
@@ -1117,6 +1259,12 @@ hipError_t launch_commit(const DevView& v, uint32_t kappa, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_errors(const DevView& v, hipStream_t s) {
+  const size_t n = (size_t)v.w * v.h * (v.tp >> 3);
+  hipLaunchKernelGGL(k_errors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_advance(const DevView& v, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, v.ctr);
   return hipGetLastError();
@@ -1142,21 +1290,82 @@ hipError_t launch_energy(const DevView& v, unsigned long long* y, hipStream_t s)
   return hipGetLastError();
 }
 
-uint32_t blur_partials(const DevView& v) {
-  const uint64_t waves = (uint64_t)v.w * v.h * (v.tp >> 6);
+uint32_t blur_partials(const DevView& v, uint32_t pitch) {
+  const uint64_t waves = (uint64_t)v.w * v.h * (pitch >> 6);
   return (uint32_t)((waves + 3) / 4);
 }
 
-hipError_t launch_blur(const DevView& v, const float* kx, uint32_t nkx, const int32_t* dx,
-                       const float* ky, uint32_t nky, const int32_t* dy, float* tmp,
-                       double* partial, uint32_t* npartial, hipStream_t s) {
-  const uint32_t blocks = blur_partials(v);
-  hipLaunchKernelGGL(k_blur_x, dim3(blocks), dim3(256), 0, s, v, kx, dx, nkx, tmp);
+hipError_t launch_blur(const DevView& v, const float* field, uint32_t pitch, uint32_t valid, const float* kx,
+                       uint32_t nkx, const int32_t* dx, const float* ky, uint32_t nky, const int32_t* dy,
+                       float* tmp, double* partial, uint32_t* npartial, hipStream_t s) {
+  const uint32_t blocks = blur_partials(v, pitch);
+  hipLaunchKernelGGL(k_blur_x, dim3(blocks), dim3(256), 0, s, v, field, pitch, kx, dx, nkx, tmp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_blur_y_sq, dim3(blocks), dim3(256), 0, s, v, ky, dy, nky, (const float*)tmp,
-                     partial);
+  hipLaunchKernelGGL(k_blur_y_sq, dim3(blocks), dim3(256), 0, s, v, pitch, valid, ky, dy, nky,
+                     (const float*)tmp, partial);
   *npartial = blocks;
+  return hipGetLastError();
+}
+
+hipError_t launch_gauss_est(const DevView& v, int mode, uint32_t m, hipStream_t s) {
+  if (!v.tgp || m == 0) return hipSuccess;
+  const uint64_t waves = (uint64_t)m * (v.tgp >> 6);
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+  if (mode == MODE_ALL) hipLaunchKernelGGL(k_gauss_est<MODE_ALL>, grid, block, 0, s, v, 0u, m);
+  else hipLaunchKernelGGL(k_gauss_est<MODE_CLASS>, grid, block, 0, s, v, 0u, m);
+  return hipGetLastError();
+}
+
+namespace {
+template <int MODE>
+hipError_t gauss_delta_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStream_t s) {
+  const dim3 grid((m + 3) / 4), block(256);
+  switch (v.radius) {
+    case 1: hipLaunchKernelGGL((k_delta_gauss<1, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 2: hipLaunchKernelGGL((k_delta_gauss<2, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 3: hipLaunchKernelGGL((k_delta_gauss<3, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 4: hipLaunchKernelGGL((k_delta_gauss<4, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 5: hipLaunchKernelGGL((k_delta_gauss<5, MODE>), grid, block, 0, s, v, kappa, m); break;
+    case 6: hipLaunchKernelGGL((k_delta_gauss<6, MODE>), grid, block, 0, s, v, kappa, m); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_gauss_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
+  if (!v.tgp || m == 0) return hipSuccess;
+  return mode == MODE_CLASS ? gauss_delta_dispatch<MODE_CLASS>(v, kappa, m, s)
+                            : gauss_delta_dispatch<MODE_LIST>(v, kappa, m, s);
+}
+
+hipError_t launch_gauss_commit(const DevView& v, uint32_t kappa, hipStream_t s) {
+  if (!v.tgp) return hipSuccess;
+  hipLaunchKernelGGL(k_commit_gauss, dim3((v.pc + 3) / 4), dim3(256), 0, s, v, kappa);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauss_errors(const DevView& v, hipStream_t s) {
+  if (!v.tgp) return hipSuccess;
+  const size_t n = (size_t)v.w * v.h * v.tgp;
+  hipLaunchKernelGGL(k_gauss_errors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauss_energy(const DevView& v, double* gsum, hipStream_t s) {
+  if (!v.tgp) return hipSuccess;
+  const uint32_t P = v.w * v.h;
+  const dim3 grid((P + 3) / 4), block(256);
+  switch (v.radius) {
+    case 1: hipLaunchKernelGGL(k_energy_gauss<1>, grid, block, 0, s, v, gsum); break;
+    case 2: hipLaunchKernelGGL(k_energy_gauss<2>, grid, block, 0, s, v, gsum); break;
+    case 3: hipLaunchKernelGGL(k_energy_gauss<3>, grid, block, 0, s, v, gsum); break;
+    case 4: hipLaunchKernelGGL(k_energy_gauss<4>, grid, block, 0, s, v, gsum); break;
+    case 5: hipLaunchKernelGGL(k_energy_gauss<5>, grid, block, 0, s, v, gsum); break;
+    case 6: hipLaunchKernelGGL(k_energy_gauss<6>, grid, block, 0, s, v, gsum); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -41,11 +41,14 @@ def oracle_problem(w, inp):
     return osw.Problem(n=w["n"], g=w["g"], width=w["width"], height=w["height"], radius=w["radius"],
                        sigma=w["sigma"], colour_k=w["colour_k"], seed=w["seed"],
                        problem_id=w.get("problem_id", 0), table=inp["heaviside"],
-                       objective=w.get("objective", 1))
+                       objective=w.get("objective", 1),
+                       gauss=inp["gauss"] if w.get("t_gauss", 0) else None)
 
 
 def gpu_problem(w, inp):
-    p = _bnlat().create_problem(w, bnlat.heaviside_array(inp["heaviside"]))
+    b = _bnlat()
+    g = b.gaussian_array(inp["gauss"]) if w.get("t_gauss", 0) else None
+    p = b.create_problem(w, b.heaviside_array(inp["heaviside"]), gaussians=g)
     p.init_offsets(inp["offsets"])
     p.compute_errors()
     return p

@@ -62,7 +62,7 @@ def test_create_rejects_bad_config_before_device(L):
         bnlat.Problem(cfg(n=12))
     assert e.value.status == bnlat.BN_EINVAL
     with pytest.raises(bnlat.BnlatError) as e:
-        bnlat.Problem(cfg(t_gauss=4))
+        bnlat.Problem(cfg(t_heaviside=0, t_gauss=4))
     assert e.value.status == bnlat.BN_EUNSUPPORTED
 
 
@@ -95,6 +95,18 @@ def test_drawn_heavisides_match_oracle_draw(L):
     want = integrands.heaviside_table_philox(2000, seed=5, problem=3)
     for k in ("nx", "ny", "cx", "cy"):
         np.testing.assert_array_equal(got[k], want[k])
+
+
+def test_gaussians_match_oracle(L):
+    got = bnlat.draw_gaussians(seed=7, problem_id=2, t=500)
+    want = integrands.gaussian_table_philox(500, seed=7, problem=2)
+    for k in ("mx", "my", "s"):
+        np.testing.assert_array_equal(got[k], want[k])
+    for mx, my, s in zip(got["mx"][:100], got["my"][:100], got["s"][:100]):
+        assert bnlat.gaussian_integral(mx, my, s) == pytest.approx(integrands.gaussian_integral(mx, my, s),
+                                                                   rel=1e-14, abs=1e-16)
+    with pytest.raises(bnlat.BnlatError):
+        bnlat.gaussian_integral(0.5, 0.5, 0.0)
 
 
 def test_device_calls_fail_loudly_without_gpu(L):

@@ -98,6 +98,7 @@ def test_sweep_trajectory_matches_oracle(name, k):
         assert stats["accepts"] == sum(st.accepts)
         np.testing.assert_array_equal(p.get_offsets(), st.u)
         np.testing.assert_array_equal(p.get_counts(), st.c.reshape(-1, w["t_heaviside"]))
+        check_errors(p.get_errors(), st.c.reshape(-1, w["t_heaviside"]), w["n"], ref.areas)
         e_ref = osw.energy_of(ref, st)
         assert p.energy() == pytest.approx(e_ref, rel=1e-12)
         assert p.energy() == pytest.approx(energy.energy_plain(osw.errors(ref, st), w["radius"], w["sigma"]),

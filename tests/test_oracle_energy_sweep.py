@@ -217,3 +217,23 @@ def test_quality_limits_and_white_noise():
     for s in (1.0, 2.0):
         k2 = np.sum(quality.periodic_kernel(64, s) ** 2) ** 2
         assert quality.quality(e, (s,))[0] ** 2 == pytest.approx(rmse ** 2 * k2, rel=0.05)
+
+
+def test_mixed_integrands_phase_consistent():
+    """Heaviside + Gaussian rows: the phase's energy change equals the
+    brute-force change of the full error field (both parts), and accepted
+    moves are exactly the ones with a negative change."""
+    prob = small_problem(w=12, h=12, t=6)
+    prob.gauss = synthgen.gaussian_table(4, seed=5)
+    prob.__post_init__()
+    st = osw_initial = sweep.initial_state(prob, synthgen.offsets(12, 12, seed=6))
+    e_before = sweep.errors(prob, st).copy()
+    ph = sweep.phase(prob, sweep.initial_state(prob, st.u), 0)
+    for j in range(0, len(ph["ys"]), 5):
+        y, x = ph["ys"][j], ph["xs"][j]
+        new = np.concatenate([ph["c_new"][j] / prob.n - prob.areas, ph["g_new"][j] - prob.gauss_integrals])
+        want = energy.delta_plain(e_before, y, x, new, prob.radius, prob.sigma)
+        assert ph["delta"][j] == pytest.approx(want, rel=1e-9, abs=1e-12)
+        assert ph["accept"][j] == (ph["delta"][j] < 0)
+    assert sweep.energy_of(prob, osw_initial) == pytest.approx(
+        energy.energy_plain(e_before, prob.radius, prob.sigma), rel=1e-12)
