@@ -30,6 +30,27 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile256_n256_t1024_fp32.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the counting kernel from the committed counter
+    summary, or None when the kernels changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    src = os.path.join(ROOT, "paper_2105_12620_amd", "csrc", "kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if f"kernels.hip sha256: {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("count_kernel_traffic_bytes:"):
+            return float(line.split(":")[1])
+    return None
+
+
 def cpu_baseline(w: dict, inp: dict, sweeps: int = 16, row_pixels: int = 128) -> dict:
     """The oracle timed on a band of class-0 pixels (one class row) of the same
     workload: proposals, recount, energy change and commit, repeated over
@@ -68,7 +89,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="tile256_n256_t1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp32,bf16,batched",
+                    help="comma list of forms to run: fp32 (headline), bf16, batched")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    forms = set(args.forms.split(","))
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the optimiser's batched "
                                    "and multi-tile sharding is not built for several GPUs", "n_gpus": args.gpus}))
@@ -135,8 +161,16 @@ def main() -> int:
         return {"total_ms": total_ms, "kernels_ms": {k: float(np.mean(v)) for k, v in k_ms.items()},
                 "graph_ms": graph_ms, "energy": energy, "quality_sigma_1_4_16": quality}
 
+    if args.copy_calibration:
+        # a plain copy kernel of known size: 1 GiB read, 1 GiB written
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     fp32 = timed_form(bnlat.BN_FP32)
-    bf16 = timed_form(bnlat.BN_BF16)
+    bf16 = timed_form(bnlat.BN_BF16) if "bf16" in forms else None
     avg, total_ms = fp32["kernels_ms"], fp32["total_ms"]
     M = P // K2
 
@@ -168,7 +202,7 @@ def main() -> int:
             q.close()
         return out
 
-    batch = batched()
+    batch = batched() if "batched" in forms else None
 
     # algorithmic work per launch
     count_ops = 2.0 * M * N * T                       # v_dot2 + compare per (sample, integrand)
@@ -188,19 +222,20 @@ def main() -> int:
                    "precision": "fp32", "mutation": "redraw"},
         "roofline": {"bound": "alu", "kernel": "k_count_points (proposal recount)",
                      "achieved": count_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": count_tops / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": count_tops / VALU_PEAK_TOPS, "traffic": measured_traffic(),
                      "work_per_launch": f"{M} pixels x {N} samples x {T} integrands x 2 lane-ops"},
         "kernels_ms": avg,
         "delta_hbm_gbs": delta_bytes / (avg["delta"] * 1e-3) / 1e9,
         "delta_hbm_frac": delta_bytes / (avg["delta"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "graph_value": P * args.steps / (fp32["graph_ms"] * 1e-3),
-        "bf16": {"value": P * args.steps / (bf16["total_ms"] * 1e-3),
-                 "graph_value": P * args.steps / (bf16["graph_ms"] * 1e-3),
-                 "kernels_ms": bf16["kernels_ms"],
-                 "delta_hbm_gbs": delta_bytes / (bf16["kernels_ms"]["delta"] * 1e-3) / 1e9,
-                 "energy_rel_diff_vs_fp32": abs(bf16["energy"] - fp32["energy"]) / abs(fp32["energy"]),
-                 "quality_rel_diff_vs_fp32": max(abs(a - b) / b for a, b in zip(bf16["quality_sigma_1_4_16"],
-                                                                                 fp32["quality_sigma_1_4_16"]))},
+        "bf16": None if bf16 is None else {
+            "value": P * args.steps / (bf16["total_ms"] * 1e-3),
+            "graph_value": P * args.steps / (bf16["graph_ms"] * 1e-3),
+            "kernels_ms": bf16["kernels_ms"],
+            "delta_hbm_gbs": delta_bytes / (bf16["kernels_ms"]["delta"] * 1e-3) / 1e9,
+            "energy_rel_diff_vs_fp32": abs(bf16["energy"] - fp32["energy"]) / abs(fp32["energy"]),
+            "quality_rel_diff_vs_fp32": max(abs(a - b) / b for a, b in zip(bf16["quality_sigma_1_4_16"],
+                                                                            fp32["quality_sigma_1_4_16"]))},
         "batched": batch,
         "window_offsets": win,
     }
