@@ -1,12 +1,15 @@
 """Benchmark: pixel-updates/s of the lattice-offset optimiser sweep.
 
-One step = one sweep of the whole hot path (for every colour class:
-proposals + recount, energy change, commit) over a 256x256 tile with
-N = 256 samples per pixel, T = 1024 Heaviside integrands and a 9x9 window.
-Inputs are synthetic (seeded) and resident in HBM before the timed region.
+One step = one sweep of the whole hot path (proposals and their recount for
+every pixel, then for every colour class: energy change and commit) over a
+256x256 tile with N = 256 samples per pixel, T = 1024 Heaviside integrands
+and a 9x9 window.  Inputs are synthetic (seeded) and resident in HBM before
+the timed region.
 
-Prints one JSON line.  Per-kernel durations come from HIP events recorded on
-the problem's stream around every launch of the timed region.
+Prints one JSON line.  The timed region runs bn_sweep's overlapped schedule
+with HIP events recorded on each launch's own stream (the recount on the
+library's auxiliary stream, evaluation and commit on the problem stream);
+the graph-replayed rate of the same schedule is reported beside it.
 """
 from __future__ import annotations
 
@@ -111,55 +114,40 @@ def main() -> int:
     P, T, N = w["width"] * w["height"], w["t_heaviside"], w["n"]
 
     def timed_form(precision: int) -> dict:
-        """K staged sweeps with events around every launch, then K graph-replayed sweeps."""
+        """K sweeps of the overlapped schedule with HIP events around every
+        launch (the timed region), then K graph-replayed sweeps."""
         prob = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]), stream=stream.cuda_stream,
                                     precision=precision)
         prob.init_offsets(inp["offsets"])
         prob.compute_errors()
-
-        def staged_sweep(events):
-            for kappa in range(K2):
-                e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if events is not None else None
-                if e: e[0].record(stream)
-                prob.phase_propose(kappa)
-                if e: e[1].record(stream)
-                prob.phase_evaluate(kappa)
-                if e: e[2].record(stream)
-                prob.phase_commit(kappa)
-                if e:
-                    e[3].record(stream)
-                    events.append(e)
-            prob.phase_advance()
-
-        for _ in range(args.warmup):
-            staged_sweep(None)
-        torch.cuda.synchronize()
-        events = []
+        prob.sweep(args.warmup)
+        prob.set_profiling(True)
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
         start.record(stream)
-        for _ in range(args.steps):
-            staged_sweep(events)
+        prob.sweep(args.steps)
         stop.record(stream)
         torch.cuda.synchronize()
         total_ms = start.elapsed_time(stop)
-        k_ms = {"count": [], "delta": [], "commit": []}
-        for e in events:
-            k_ms["count"].append(e[0].elapsed_time(e[1]))
-            k_ms["delta"].append(e[1].elapsed_time(e[2]))
-            k_ms["commit"].append(e[2].elapsed_time(e[3]))
-        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        prob.sweep(1)
+        prof = prob.get_profile()
+        prob.set_profiling(False)
+        prob.sweep(2)
         torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         g0.record(stream)
-        stats = prob.sweep(args.steps, stats=False)
+        prob.sweep(args.steps)
         g1.record(stream)
         torch.cuda.synchronize()
         graph_ms = g0.elapsed_time(g1)
         energy = prob.energy()
         quality = prob.quality_metric([1.0, 4.0, 16.0]).tolist()
         prob.close()
-        return {"total_ms": total_ms, "kernels_ms": {k: float(np.mean(v)) for k, v in k_ms.items()},
-                "graph_ms": graph_ms, "energy": energy, "quality_sigma_1_4_16": quality}
+        kernels = {"recount_per_sweep": prof["recount_ms"] / max(1, prof["recount_launches"]),
+                   "evaluate_per_phase": prof["evaluate_ms"] / max(1, prof["phases"]),
+                   "commit_per_phase": prof["commit_ms"] / max(1, prof["phases"]),
+                   "recount_launches": prof["recount_launches"], "phases": prof["phases"]}
+        return {"total_ms": total_ms, "kernels_ms": kernels, "graph_ms": graph_ms, "energy": energy,
+                "quality_sigma_1_4_16": quality}
 
     if args.copy_calibration:
         # a plain copy kernel of known size: 1 GiB read, 1 GiB written
@@ -204,11 +192,11 @@ def main() -> int:
 
     batch = batched() if "batched" in forms else None
 
-    # algorithmic work per launch
-    count_ops = 2.0 * M * N * T                       # v_dot2 + compare per (sample, integrand)
-    count_tops = count_ops / (avg["count"] * 1e-3) / 1e12
+    # algorithmic work per launch of the counting kernel: one sweep-wide recount
+    count_ops = 2.0 * P * N * T                       # v_dot2 + compare per (sample, integrand)
+    count_tops = count_ops / (avg["recount_per_sweep"] * 1e-3) / 1e12
     win = (2 * w["radius"] + 1) ** 2 - 1
-    # energy change: the tile's counts once per phase (2 B each) plus the moved
+    # evaluation of a phase: the tile's counts once (2 B each) plus the moved
     # pixels' proposal rows, and the decisions
     delta_bytes = 2.0 * T * (P + M) + 9.0 * M
     value = P * args.steps / (total_ms * 1e-3)
@@ -220,19 +208,19 @@ def main() -> int:
         "config": {"workload": args.workload, "tile": f"{w['width']}x{w['height']}", "n": N, "t": T,
                    "window": f"{2 * w['radius'] + 1}x{2 * w['radius'] + 1}", "colour_classes": K2,
                    "precision": "fp32", "mutation": "redraw"},
-        "roofline": {"bound": "alu", "kernel": "k_count_points (proposal recount)",
+        "roofline": {"bound": "alu", "kernel": "k_count_points<4, 3> (sweep-wide proposal recount)",
                      "achieved": count_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": count_tops / VALU_PEAK_TOPS, "traffic": measured_traffic(),
-                     "work_per_launch": f"{M} pixels x {N} samples x {T} integrands x 2 lane-ops"},
+                     "work_per_launch": f"{P} pixels x {N} samples x {T} integrands x 2 lane-ops"},
         "kernels_ms": avg,
-        "delta_hbm_gbs": delta_bytes / (avg["delta"] * 1e-3) / 1e9,
-        "delta_hbm_frac": delta_bytes / (avg["delta"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "evaluate_hbm_gbs": delta_bytes / (avg["evaluate_per_phase"] * 1e-3) / 1e9,
+        "evaluate_hbm_frac": delta_bytes / (avg["evaluate_per_phase"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "graph_value": P * args.steps / (fp32["graph_ms"] * 1e-3),
         "bf16": None if bf16 is None else {
             "value": P * args.steps / (bf16["total_ms"] * 1e-3),
             "graph_value": P * args.steps / (bf16["graph_ms"] * 1e-3),
             "kernels_ms": bf16["kernels_ms"],
-            "delta_hbm_gbs": delta_bytes / (bf16["kernels_ms"]["delta"] * 1e-3) / 1e9,
+            "evaluate_hbm_gbs": delta_bytes / (bf16["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9,
             "energy_rel_diff_vs_fp32": abs(bf16["energy"] - fp32["energy"]) / abs(fp32["energy"]),
             "quality_rel_diff_vs_fp32": max(abs(a - b) / b for a, b in zip(bf16["quality_sigma_1_4_16"],
                                                                             fp32["quality_sigma_1_4_16"]))},

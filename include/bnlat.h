@@ -140,6 +140,10 @@ bn_status bn_compute_errors(bn_problem p);
  * draws a proposal (counter (p, sweep, problem_id, 0xC)), recounts its hits,
  * evaluates the energy change of Eq. (1) against the state at the start of
  * the phase and commits the accepted moves; then the sweep index advances.
+ * A proposal and its recount depend only on (pixel, sweep), never on the
+ * state, so the recount of sweep s+1 runs on an auxiliary stream while sweep
+ * s is evaluated and committed (two sweeps per replay of a captured graph);
+ * the result equals the plain sequential schedule bit for bit.
  * stats (nullable) receives totals over the k sweeps (synchronises).
  * Returns BN_ESTATE before bn_compute_errors. */
 bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats);
@@ -180,6 +184,23 @@ bn_status bn_delta_energy(bn_problem p, const uint32_t* pixels, const uint16_t* 
                           uint32_t m, double* out_de, uint16_t* out_counts);
 bn_status bn_get_sweep_index(bn_problem p, uint64_t* out);
 bn_status bn_set_sweep_index(bn_problem p, uint64_t sweep);
+
+/* Kernel timing of bn_sweep.  While profiling is on, bn_sweep runs the same
+ * overlapped schedule eagerly (no graph replay) and records HIP events on
+ * each launch's own stream: around the sweep-wide recount (the counting
+ * kernel, on the library's auxiliary stream), around each colour phase's
+ * evaluation and around its commit (problem stream).  bn_set_profiling
+ * synchronises and clears the record; bn_get_profile synchronises and sums
+ * the event intervals. */
+typedef struct {
+  uint64_t recount_launches;  /* sweep-wide counting launches recorded          */
+  double recount_ms;          /* their total duration                           */
+  uint64_t phases;            /* colour phases recorded                         */
+  double evaluate_ms;         /* total duration of the phases' evaluations      */
+  double commit_ms;           /* total duration of the phases' commits          */
+} bn_profile_stats;
+bn_status bn_set_profiling(bn_problem p, int enable);
+bn_status bn_get_profile(bn_problem p, bn_profile_stats* out);
 
 /* The three steps of one colour phase kappa < K*K at the current sweep
  * index, as bn_sweep runs them: propose + recount, evaluate, commit.

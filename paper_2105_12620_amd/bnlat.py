@@ -44,6 +44,11 @@ class SweepStats(C.Structure):
                 ("sweep_index", C.c_uint64)]
 
 
+class ProfileStats(C.Structure):
+    _fields_ = [("recount_launches", C.c_uint64), ("recount_ms", C.c_double), ("phases", C.c_uint64),
+                ("evaluate_ms", C.c_double), ("commit_ms", C.c_double)]
+
+
 HEAVISIDE_DTYPE = np.dtype([("nx", "<i2"), ("ny", "<i2"), ("cx", "<u2"), ("cy", "<u2")])
 GAUSSIAN_DTYPE = np.dtype([("mx", "<f8"), ("my", "<f8"), ("s", "<f8")])
 
@@ -68,6 +73,8 @@ _SIGNATURES = {
     "bn_delta_energy": [_P, _P, _P, C.c_uint32, _P, _P],
     "bn_get_sweep_index": [_P, C.POINTER(C.c_uint64)],
     "bn_set_sweep_index": [_P, C.c_uint64],
+    "bn_set_profiling": [_P, C.c_int],
+    "bn_get_profile": [_P, C.POINTER(ProfileStats)],
     "bn_phase_propose": [_P, C.c_uint32],
     "bn_phase_evaluate": [_P, C.c_uint32],
     "bn_phase_commit": [_P, C.c_uint32],
@@ -295,6 +302,14 @@ class Problem:
 
     def set_sweep_index(self, s: int):
         _call("bn_set_sweep_index", self.handle, s)
+
+    def set_profiling(self, enable: bool):
+        _call("bn_set_profiling", self.handle, 1 if enable else 0)
+
+    def get_profile(self) -> dict:
+        st = ProfileStats()
+        _call("bn_get_profile", self.handle, C.byref(st))
+        return {k: getattr(st, k) for k, _ in ProfileStats._fields_}
 
     # phase steps
     def phase_propose(self, kappa: int):

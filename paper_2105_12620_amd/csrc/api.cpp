@@ -185,6 +185,24 @@ struct bn_problem_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool graph_failed = false;
+  // Overlapped sweeps: proposals of a whole sweep, rows grouped by colour
+  // class, in two buffer sets; set 0 always holds the proposals of the
+  // current sweep index `prefetched` when that equals `sweep`.
+  struct SweepSet {
+    uint16_t* cn = nullptr;
+    uint32_t* un = nullptr;
+    float* gn = nullptr;
+  } sets[2];
+  bool sets_ready = false;
+  uint64_t prefetched = ~0ull;
+  hipStream_t aux = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraph_t pair_graph = nullptr;
+  hipGraphExec_t pair_exec = nullptr;
+  bool pair_failed = false;
+  // profiling: eager overlapped sweeps with events around the launches
+  bool profiling = false;
+  std::vector<hipEvent_t> prof_recount, prof_eval, prof_commit;   // start/stop pairs
 
   template <class T>
   bn_status alloc(T** ptr, size_t count) {
@@ -201,8 +219,16 @@ struct bn_problem_s {
   ~bn_problem_s() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (pair_exec) (void)hipGraphExecDestroy(pair_exec);
+    if (pair_graph) (void)hipGraphDestroy(pair_graph);
     if (stream) (void)hipStreamSynchronize(stream);
+    if (aux) (void)hipStreamSynchronize(aux);
     for (void* p : allocs) (void)hipFree(p);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto* vec : {&prof_recount, &prof_eval, &prof_commit})
+      for (hipEvent_t e : *vec) (void)hipEventDestroy(e);
+    if (aux) (void)hipStreamDestroy(aux);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -337,6 +363,167 @@ bn_status record_sweep(bn_problem p) {
     HIPCHK(launch_gauss_commit(p->v, kappa, p->stream));
   }
   HIPCHK(launch_advance(p->v, p->stream));
+  return BN_OK;
+}
+
+// The view of colour phase kappa reading proposals from sweep buffer set b.
+DevView phase_view(bn_problem p, int b, uint32_t kappa) {
+  DevView v = p->v;
+  v.c_new = p->sets[b].cn + (size_t)kappa * v.pc * v.tp;
+  v.u_new = p->sets[b].un + (size_t)kappa * v.pc;
+  if (v.tgp) v.g_new = p->sets[b].gn + (size_t)kappa * v.pc * v.tgp;
+  return v;
+}
+
+DevView sweep_view(bn_problem p, int b) {
+  DevView v = p->v;
+  v.c_new = p->sets[b].cn;
+  v.u_new = p->sets[b].un;
+  if (v.tgp) v.g_new = p->sets[b].gn;
+  return v;
+}
+
+bn_status ensure_sweep_sets(bn_problem p) {
+  if (p->sets_ready) return BN_OK;
+  const size_t P = (size_t)p->v.w * p->v.h;
+  bn_status s;
+  for (int b = 0; b < 2; ++b) {
+    if ((s = p->alloc(&p->sets[b].cn, P * p->v.tp)) != BN_OK) return s;
+    if ((s = p->alloc(&p->sets[b].un, P)) != BN_OK) return s;
+    if (p->v.tgp && (s = p->alloc(&p->sets[b].gn, P * p->v.tgp)) != BN_OK) return s;
+  }
+  HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
+  for (hipEvent_t& e : p->ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  p->sets_ready = true;
+  return BN_OK;
+}
+
+// Proposals (offsets, recounts, Gaussian estimates) of every pixel for the
+// sweep `ahead` steps after the device sweep counter, into buffer set b.
+// Event pair recorded around a launch when profiling (eager mode only).
+struct ProfMark {
+  bn_problem p;
+  std::vector<hipEvent_t>* vec;
+  hipStream_t st;
+  hipEvent_t stop = nullptr;
+  bn_status s = BN_OK;
+  ProfMark(bn_problem p_, std::vector<hipEvent_t>* v_, hipStream_t st_) : p(p_), vec(v_), st(st_) {
+    if (!p->profiling) return;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess || hipEventRecord(a, st) != hipSuccess) {
+      s = fail(BN_EHIP, "profiling events");
+      return;
+    }
+    vec->push_back(a);
+    vec->push_back(b);
+    stop = b;
+  }
+  bn_status end() {
+    if (stop && hipEventRecord(stop, st) != hipSuccess) return fail(BN_EHIP, "profiling event record");
+    return s;
+  }
+};
+
+bn_status record_proposals(bn_problem p, int b, uint32_t ahead, hipStream_t st) {
+  const DevView v = sweep_view(p, b);
+  const uint32_t P = v.w * v.h;
+  ProfMark m(p, &p->prof_recount, st);
+  HIPCHK(launch_count(v, MODE_SWEEP, ahead, P, st));
+  bn_status s = m.end();
+  if (s != BN_OK) return s;
+  HIPCHK(launch_gauss_est(v, MODE_SWEEP, P, st));
+  return BN_OK;
+}
+
+bn_status record_phases(bn_problem p, int b) {
+  for (uint32_t kappa = 0; kappa < p->cfg.colour_k * p->cfg.colour_k; ++kappa) {
+    const DevView v = phase_view(p, b, kappa);
+    ProfMark me(p, &p->prof_eval, p->stream);
+    HIPCHK(launch_gauss_delta(v, MODE_CLASS, kappa, v.pc, p->stream));
+    HIPCHK(launch_delta(v, MODE_CLASS, kappa, v.pc, p->stream));
+    bn_status s = me.end();
+    if (s != BN_OK) return s;
+    ProfMark mc(p, &p->prof_commit, p->stream);
+    HIPCHK(launch_commit(v, kappa, p->stream));
+    HIPCHK(launch_gauss_commit(v, kappa, p->stream));
+    if ((s = mc.end()) != BN_OK) return s;
+  }
+  return BN_OK;
+}
+
+// Two sweeps with the recount of the next sweep overlapping the evaluation of
+// the current one: [recount(s+1) -> set 1 || phases(s) from set 0], join,
+// advance, [recount(s+2) -> set 0 || phases(s+1) from set 1], join, advance.
+// The sweep counter only moves after a join, so every recount reads a stable
+// index.  Set 0 holds the current sweep's proposals before and after.
+bn_status record_pair(bn_problem p) {
+  bn_status s;
+  for (int half = 0; half < 2; ++half) {
+    const int cur = half, nxt = 1 - half;
+    HIPCHK(hipEventRecord(p->ev[2 * half], p->stream));
+    HIPCHK(hipStreamWaitEvent(p->aux, p->ev[2 * half], 0));
+    if ((s = record_proposals(p, nxt, 1, p->aux)) != BN_OK) return s;
+    HIPCHK(hipEventRecord(p->ev[2 * half + 1], p->aux));
+    if ((s = record_phases(p, cur)) != BN_OK) return s;
+    HIPCHK(hipStreamWaitEvent(p->stream, p->ev[2 * half + 1], 0));
+    HIPCHK(launch_advance(p->v, p->stream));
+  }
+  return BN_OK;
+}
+
+bn_status build_pair_graph(bn_problem p) {
+  if (p->pair_exec || p->pair_failed) return BN_OK;
+  HIPCHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+  bn_status s = record_pair(p);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->stream, &g);
+  if (s != BN_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p->pair_failed = true;
+    return BN_OK;
+  }
+  e = hipGraphInstantiate(&p->pair_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g);
+    p->pair_exec = nullptr;
+    p->pair_failed = true;
+    return BN_OK;
+  }
+  p->pair_graph = g;
+  return BN_OK;
+}
+
+// k sweeps through the overlapped path.
+bn_status overlapped_sweeps(bn_problem p, uint32_t k) {
+  bn_status s;
+  if ((s = ensure_sweep_sets(p)) != BN_OK) return s;
+  if (p->prefetched != p->sweep) {
+    if ((s = record_proposals(p, 0, 0, p->stream)) != BN_OK) return s;
+    p->prefetched = p->sweep;
+  }
+  if (k >= 2 && !p->profiling && (s = build_pair_graph(p)) != BN_OK) return s;
+  uint32_t done = 0;
+  while (k - done >= 2) {
+    if (p->pair_exec && !p->profiling) {
+      HIPCHK(hipGraphLaunch(p->pair_exec, p->stream));
+    } else if ((s = record_pair(p)) != BN_OK) {
+      return s;
+    }
+    done += 2;
+  }
+  if (done < k) {
+    // one more sweep, then the next sweep's proposals into set 0
+    if ((s = record_phases(p, 0)) != BN_OK) return s;
+    HIPCHK(launch_advance(p->v, p->stream));
+    if ((s = record_proposals(p, 0, 0, p->stream)) != BN_OK) return s;
+    done += 1;
+  }
+  p->prefetched = p->sweep + k;
   return BN_OK;
 }
 
@@ -785,15 +972,8 @@ bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats) {
     bn_status s = sync(p);
     if (s != BN_OK) return s;
   }
-  bn_status s = build_graph(p);
+  bn_status s = overlapped_sweeps(p, k);
   if (s != BN_OK) return s;
-  for (uint32_t i = 0; i < k; ++i) {
-    if (p->graph_exec) {
-      HIPCHK(hipGraphLaunch(p->graph_exec, p->stream));
-    } else if ((s = record_sweep(p)) != BN_OK) {
-      return s;
-    }
-  }
   p->sweep += k;
   if (k) p->errors_valid = false;
   if (stats) {
@@ -975,6 +1155,42 @@ bn_status bn_delta_energy(bn_problem p, const uint32_t* pixels, const uint16_t* 
   HIPCHK(hipMemcpyAsync(out_de, p->list_delta, (size_t)m * 8, hipMemcpyDeviceToHost, p->stream));
   if (out_counts) return untile_counts(p, p->list_cnt, m, out_counts);
   return sync(p);
+}
+
+bn_status bn_set_profiling(bn_problem p, int enable) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  bn_status s = sync(p);
+  if (s != BN_OK) return s;
+  if (p->aux) HIPCHK(hipStreamSynchronize(p->aux));
+  for (auto* vec : {&p->prof_recount, &p->prof_eval, &p->prof_commit}) {
+    for (hipEvent_t e : *vec) (void)hipEventDestroy(e);
+    vec->clear();
+  }
+  p->profiling = enable != 0;
+  return BN_OK;
+}
+
+bn_status bn_get_profile(bn_problem p, bn_profile_stats* out) {
+  if (!p || !out) return fail(BN_EINVAL, "NULL argument");
+  bn_status s = sync(p);
+  if (s != BN_OK) return s;
+  if (p->aux) HIPCHK(hipStreamSynchronize(p->aux));
+  auto total = [](const std::vector<hipEvent_t>& v, double* ms) -> hipError_t {
+    *ms = 0.0;
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+      float t = 0.f;
+      hipError_t e = hipEventElapsedTime(&t, v[i], v[i + 1]);
+      if (e != hipSuccess) return e;
+      *ms += t;
+    }
+    return hipSuccess;
+  };
+  HIPCHK(total(p->prof_recount, &out->recount_ms));
+  HIPCHK(total(p->prof_eval, &out->evaluate_ms));
+  HIPCHK(total(p->prof_commit, &out->commit_ms));
+  out->recount_launches = p->prof_recount.size() / 2;
+  out->phases = p->prof_eval.size() / 2;
+  return BN_OK;
 }
 
 bn_status bn_get_sweep_index(bn_problem p, uint64_t* out) {

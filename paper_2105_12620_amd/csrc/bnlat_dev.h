@@ -17,7 +17,10 @@ constexpr uint32_t T_ALIGN = 128;
 constexpr uint32_t MAX_RADIUS = 8;
 constexpr uint32_t MAX_N = 4096;
 
-enum CountMode : int { MODE_ALL = 0, MODE_CLASS = 1, MODE_LIST = 2 };
+// MODE_SWEEP: proposals of every pixel of a sweep, rows grouped by colour
+// class ([class][class pixel]); the kernel argument kappa is then the sweep
+// look-ahead added to the device sweep counter.
+enum CountMode : int { MODE_ALL = 0, MODE_CLASS = 1, MODE_LIST = 2, MODE_SWEEP = 3 };
 
 // Everything a kernel needs to know about one problem, passed by value.
 struct DevView {

@@ -112,6 +112,13 @@ __device__ inline void count_target(const DevView& v, uint32_t kappa, uint32_t j
     buf = v.c_new;
     row = j;
     rows = v.pc;
+  } else if (MODE == MODE_SWEEP) {
+    const uint32_t cls = j / v.pc, jj = j - cls * v.pc;
+    p = class_pixel(v, cls, jj);
+    u = proposal(v, p, (uint32_t)v.ctr[0] + kappa);
+    buf = v.c_new + (size_t)cls * v.pc * v.tp;
+    row = jj;
+    rows = v.pc;
   } else {
     p = v.pix_list[j];
     u = v.u_new[j];
@@ -145,7 +152,7 @@ __device__ __forceinline__ void count_points_body(const DevView& v, const int2* 
   uint32_t p, u, row, rows;
   uint16_t* buf;
   count_target<MODE>(v, kappa, j, m, p, u, buf, row, rows);
-  if (MODE == MODE_CLASS && ch == 0 && lane == 0) v.u_new[j] = u;
+  if ((MODE == MODE_CLASS || MODE == MODE_SWEEP) && ch == 0 && lane == 0) v.u_new[j] = u;
 
   const uint32_t groups = v.n / (64u * PPL);
   uint32_t sp[PPL];
@@ -226,7 +233,7 @@ __device__ __forceinline__ void count_integrands_body(const DevView& v, uint32_t
   uint32_t p, u, row, rows;
   uint16_t* buf;
   count_target<MODE>(v, kappa, j, m, p, u, buf, row, rows);
-  if (MODE == MODE_CLASS && ch == 0 && lane == 0) v.u_new[j] = u;
+  if ((MODE == MODE_CLASS || MODE == MODE_SWEEP) && ch == 0 && lane == 0) v.u_new[j] = u;
   const uint32_t t = ch * 64 + lane;
   const int2 q = v.ihp[t];
   int c = 0;
@@ -1203,6 +1210,7 @@ hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
   switch (mode) {
     case MODE_ALL: return count_dispatch<MODE_ALL>(v, kappa, m, s);
     case MODE_CLASS: return count_dispatch<MODE_CLASS>(v, kappa, m, s);
+    case MODE_SWEEP: return count_dispatch<MODE_SWEEP>(v, kappa, m, s);
     default: return count_dispatch<MODE_LIST>(v, kappa, m, s);
   }
 }

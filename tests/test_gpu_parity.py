@@ -205,3 +205,28 @@ def test_call_order_is_enforced():
         with pytest.raises(bnlat.BnlatError) as e:
             p.phase_propose(4)
         assert e.value.status == bnlat.BN_EINVAL
+
+
+def test_profiled_and_mixed_schedules_agree():
+    """bn_sweep with kernel profiling (eager overlapped launches) gives the
+    graph-replayed trajectory; mixing phase steps and bn_sweep keeps the
+    proposal prefetch consistent with the sweep index."""
+    w = EDGE["n256_r4"]
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.run(ref, osw.initial_state(ref, inp["offsets"]), 5)
+    with gpu_problem(w, inp) as p:
+        p.set_profiling(True)
+        p.sweep(3)
+        prof = p.get_profile()
+        assert prof["recount_launches"] >= 3 and prof["phases"] == 12
+        assert prof["recount_ms"] > 0 and prof["evaluate_ms"] > 0
+        p.set_profiling(False)
+        for kappa in range(4):
+            p.phase_propose(kappa)
+            p.phase_evaluate(kappa)
+            p.phase_commit(kappa)
+        p.phase_advance()
+        p.sweep(1)
+        np.testing.assert_array_equal(p.get_offsets(), st.u)
+        assert p.get_sweep_index() == 5
