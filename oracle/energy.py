@@ -138,3 +138,38 @@ def energy_class_sums(c: np.ndarray, r: int) -> np.ndarray:
 def energy_exact(c: np.ndarray, n: int, r: int, sigma: float) -> float:
     """E from integer hit counts: (1/N^2) sum_d w(d) Y_d, added in increasing d."""
     return float(weighted_class_sum(energy_class_sums(c, r), r, sigma)) / (n * n)
+
+
+def swap_class_sums(c: np.ndarray, ay, ax, by, bx, r: int) -> np.ndarray:
+    """Integer X_d of exchanging the vectors of pixels a and b (Sec. 3.4).
+
+    The swap is the two moves c_a -> c_b and c_b -> c_a evaluated on the
+    unmodified state, plus a correction for the pair itself: for every window
+    offset o with a + o = b on the torus, each single move counted the pair
+    term (c_a - c_b)^2 once with the partner's old vector, while the true
+    pair term does not change.  Per such offset, X_{|o|^2} gains
+    2 sum_t (c_a,t - c_b,t)^2.  Returns int64 [M, n_classes]."""
+    h, w, _ = c.shape
+    ay, ax, by, bx = (np.asarray(v, dtype=np.int64) for v in (ay, ax, by, bx))
+    ca = c[ay, ax].astype(np.int64)
+    cb = c[by, bx].astype(np.int64)
+    out = delta_class_sums(c, ay, ax, cb, r) + delta_class_sums(c, by, bx, ca, r)
+    d2 = np.sum((ca - cb) ** 2, axis=1)
+    classes = distance_classes(r)
+    for ox, oy in window_offsets(r):
+        linked = ((ay + oy) % h == by) & ((ax + ox) % w == bx)
+        out[linked, classes.index(ox * ox + oy * oy)] += 2 * d2[linked]
+    return out
+
+
+def swap_delta_plain(e: np.ndarray, ay: int, ax: int, by: int, bx: int, r: int, sigma: float) -> float:
+    """dE of exchanging e[ay, ax] and e[by, bx], plain FP64 form with the
+    pair correction of ``swap_class_sums``."""
+    h, w, _ = e.shape
+    ea = np.asarray(e[ay, ax], dtype=np.float64)
+    eb = np.asarray(e[by, bx], dtype=np.float64)
+    total = delta_plain(e, ay, ax, eb, r, sigma) + delta_plain(e, by, bx, ea, r, sigma)
+    for ox, oy in window_offsets(r):
+        if (ay + oy) % h == by and (ax + ox) % w == bx:
+            total += 4.0 * weight(ox * ox + oy * oy, sigma) * float(np.sum((ea - eb) ** 2))
+    return total

@@ -27,6 +27,8 @@ _MASK = np.uint64(0xFFFFFFFF)
 S_INIT = 0xA    # initial offsets
 S_INTEG = 0xB   # integrand parameters
 S_PROP = 0xC    # offset proposals of the optimiser
+S_PERM = 0xE    # sort keys of the pixel permutation (swap mutation)
+S_SWAP = 0xF    # XOR masks of the swap passes
 
 
 def philox4x32_10(counter, key) -> np.ndarray:

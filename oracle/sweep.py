@@ -19,6 +19,20 @@ quarter of the pixels move concurrently.  Readings used here:
     raise the sum instead (ascend), the only sign under which swapping pixels
     lowers the blurred error.
 
+The paper's own mutation (Sec. 3.4, and the pixel permutation of Sec. 2)
+exchanges the offsets of two pixels; ``move = 1`` selects it.  Readings:
+  * the precomputed permutation pi lists the pixels sorted by 64-bit Philox
+    keys drawn at counters (p, 0, problem, S_PERM) (ties by pixel index);
+  * pass kappa of sweep s scrambles the listed indices with the XOR mask
+    x = word 0 of Philox((kappa, s, problem, S_SWAP)) mod P (P a power of two,
+    so the scrambled list is again a permutation);
+  * pass kappa takes list positions [kappa M, (kappa + 1) M), M = P / K^2
+    (K = 2: a quarter of the pixels), and couples positions 2i and 2i + 1;
+  * each couple is evaluated on the pass-start state (the two exchanged
+    vectors plus the pair correction, energy module) and accepted by the same
+    strict sign rule; accepted couples exchange offsets, counts and
+    estimates, so no recount happens.
+
 Decisions use the exact integer form of the energy change for Heaviside rows
 (energy module); Gaussian rows (Sec. 3.5's low-frequency integrands) add their
 FP64 plain-form change, and the decision is taken on the sum.
@@ -48,9 +62,11 @@ class Problem:
     table: dict                       # Heaviside table (synthgen format)
     objective: int = 1                # +1: accept dE < 0 (descend); -1: accept dE > 0
     gauss: dict | None = None         # Gaussian table (synthgen format), optional
+    move: int = 0                     # 0: redraw offsets; 1: swap couples of pixels
 
     def __post_init__(self):
         validate(self)
+        self.perm = swap_permutation(self) if self.move == 1 else None
         self.areas = integrands.heaviside_areas(self.table)
         tg = 0 if self.gauss is None else len(self.gauss["mx"])
         self.gauss_integrals = (integrands.gaussian_integrals(self.gauss) if tg
@@ -72,6 +88,14 @@ def validate(p) -> None:
         raise ValueError("objective must be +1 (descend) or -1 (ascend)")
     if len(p.table["nx"]) < 1:
         raise ValueError("at least one integrand is required")
+    if getattr(p, "move", 0) not in (0, 1):
+        raise ValueError("move must be 0 (redraw) or 1 (swap)")
+    if getattr(p, "move", 0) == 1:
+        npix = p.width * p.height
+        if npix & (npix - 1) or npix < 2 * p.colour_k ** 2:
+            raise ValueError("swap mutation: W*H must be a power of two and at least 2 K^2")
+        if p.gauss is not None and len(p.gauss["mx"]):
+            raise ValueError("swap mutation: Heaviside integrands only")
 
 
 @dataclass
@@ -134,10 +158,48 @@ def phase(prob: Problem, st: State, kappa: int) -> dict:
             "delta": delta, "accept": accept}
 
 
+def swap_permutation(prob: Problem) -> np.ndarray:
+    """pi: pixel indices sorted by the keys (w0 << 32) | w1 of
+    Philox((p, 0, problem, S_PERM)), ties by pixel index."""
+    npix = prob.width * prob.height
+    w = philox.draw(np.arange(npix), 0, prob.problem_id, philox.S_PERM, prob.seed)
+    key = (w[:, 0].astype(np.uint64) << np.uint64(32)) | w[:, 1].astype(np.uint64)
+    return np.argsort(key, kind="stable").astype(np.int64)
+
+
+def swap_mask(prob: Problem, sweep: int, kappa: int) -> int:
+    """XOR mask of pass kappa of a sweep: word 0 of Philox((kappa, sweep,
+    problem, S_SWAP)) modulo the (power-of-two) pixel count."""
+    w = philox.draw(np.array([kappa]), sweep, prob.problem_id, philox.S_SWAP, prob.seed)
+    return int(w[0, 0]) & (prob.width * prob.height - 1)
+
+
+def swap_couples(prob: Problem, sweep: int, kappa: int):
+    """Pixel indices (a, b) of the couples of pass kappa, in list order."""
+    m = prob.width * prob.height // prob.colour_k ** 2
+    pix = prob.perm[kappa * m:(kappa + 1) * m] ^ swap_mask(prob, sweep, kappa)
+    return pix[0::2], pix[1::2]
+
+
+def swap_pass(prob: Problem, st: State, kappa: int) -> dict:
+    """One swap pass at sweep st.sweep; commits accepted exchanges into st."""
+    a, b = swap_couples(prob, st.sweep, kappa)
+    ay, ax = np.divmod(a, prob.width)
+    by, bx = np.divmod(b, prob.width)
+    xd = energy.swap_class_sums(st.c, ay, ax, by, bx, prob.radius)
+    delta = energy.weighted_class_sum(xd, prob.radius, prob.sigma) * (2.0 / (prob.n * prob.n))
+    accept = (delta < 0.0) if prob.objective == 1 else (delta > 0.0)
+    sa, sb = (ay[accept], ax[accept]), (by[accept], bx[accept])
+    st.u[sa], st.u[sb] = st.u[sb].copy(), st.u[sa].copy()
+    st.c[sa], st.c[sb] = st.c[sb].copy(), st.c[sa].copy()
+    return {"a": a, "b": b, "xd": xd, "delta": delta, "accept": accept}
+
+
 def sweep(prob: Problem, st: State) -> None:
-    """All K^2 phases of one sweep, then advance the sweep index."""
+    """All K^2 phases (or swap passes) of one sweep, then advance the sweep index."""
+    step = swap_pass if prob.move == 1 else phase
     for kappa in range(prob.colour_k ** 2):
-        st.accepts.append(int(phase(prob, st, kappa)["accept"].sum()))
+        st.accepts.append(int(step(prob, st, kappa)["accept"].sum()))
     st.sweep += 1
 
 
