@@ -36,6 +36,18 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile256_n256_t1024_fp32.md")
 
 
+COUNT_KERNEL_SOURCES = ("bnlat_dev.h", "device_common.h", "kernels.hip")
+
+
+def kernel_digest() -> str:
+    """sha256 over the sources the counting kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in COUNT_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2105_12620_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the counting kernel from the committed counter
     summary, or None when the kernels changed since it was taken."""
@@ -44,9 +56,7 @@ def measured_traffic():
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
-    src = os.path.join(ROOT, "paper_2105_12620_amd", "csrc", "kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if f"kernels.hip sha256: {digest}" not in text:
+    if f"counting kernel sources sha256: {kernel_digest()}" not in text:
         return None
     for line in text.splitlines():
         if line.startswith("count_kernel_traffic_bytes:"):

@@ -24,75 +24,10 @@
 #include <stdint.h>
 
 #include "bnlat_dev.h"
-
-// v_writelane_b32: write a wave-uniform value into one lane of a register.
-extern "C" __device__ int bnlat_writelane_i32(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+#include "device_common.h"
 
 namespace bnlat {
 namespace {
-
-typedef short v2i16 __attribute__((ext_vector_type(2)));
-
-// ---------------------------------------------------------------- helpers
-
-// Philox4x32-10 (Salmon et al., SC 2011): two 32x32->64 products per round,
-// key advanced by the Weyl constants between rounds.  Returns words 0 and 1.
-__device__ inline uint2 philox_w01(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                   uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-  }
-  return make_uint2(c0, c1);
-}
-
-// Q0.16 pair from the top halves of words 0 and 1.
-__device__ inline uint32_t q16_pair(uint2 w) { return (w.x >> 16) | (w.y & 0xFFFF0000u); }
-
-// Componentwise (a + b) mod 2^16 of two packed Q0.16 pairs: the toroidal
-// shift mod(s + u, 1) of Sec. 3.2.
-__device__ inline uint32_t wrap_add(uint32_t a, uint32_t b) {
-  return ((a + b) & 0xFFFFu) | (((a >> 16) + (b >> 16)) << 16);
-}
-
-// S - 2^15 per component, as two int16.
-__device__ inline uint32_t centre(uint32_t s) { return s ^ 0x80008000u; }
-
-// Element (row, t) of a tiled count buffer with `rows` rows.
-__device__ inline size_t tix(uint32_t row, uint32_t t, uint32_t rows) {
-  return ((size_t)(t >> 3) * rows + row) * 8 + (t & 7);
-}
-
-// Signed int16x2 dot product plus accumulator (v_dot2_i32_i16).  The clamp
-// bit keeps the three-operand encoding; it never engages because every
-// product sum here stays below 2^31 in magnitude.
-__device__ inline int dot2(uint32_t a, uint32_t b, int c) {
-  return __builtin_amdgcn_sdot2(__builtin_bit_cast(v2i16, a), __builtin_bit_cast(v2i16, b), c, true);
-}
-
-__device__ inline uint32_t wave_id() {
-  return __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-}
-
-__device__ inline uint32_t class_pixel(const DevView& v, uint32_t kappa, uint32_t j) {
-  const uint32_t ky = kappa / v.k, kx = kappa - ky * v.k;
-  const uint32_t a = j / v.cw, b = j - a * v.cw;
-  return (ky + v.k * a) * v.w + (kx + v.k * b);
-}
-
-__device__ inline uint32_t proposal(const DevView& v, uint32_t p, uint32_t sweep) {
-  return q16_pair(philox_w01(p, sweep, v.problem, S_PROP, v.seed_lo, v.seed_hi));
-}
 
 // Resolve the pixel, offset and output buffer (row index, row count) of work
 // item j of a count launch.
@@ -254,45 +189,6 @@ __global__ __launch_bounds__(256) void k_count_integrands_batch(const DevView* _
   const DevView v = views[i];
   count_integrands_body<MODE_CLASS>(v, kappa, v.pc, blockIdx.x - pre[i]);
 }
-
-// --------------------------------------------------------- window tables
-
-// Offsets of the (2R+1)^2 - 1 window grouped by squared distance d in
-// increasing d (row-major inside a group), with their group index.
-template <int R>
-struct Window {
-  static constexpr int M = (2 * R + 1) * (2 * R + 1) - 1;
-  static constexpr int DMAX = 2 * R * R;
-  int ox[M], oy[M], cls[M];
-  int ncls;
-  int d[DMAX + 1], csize[DMAX + 1];
-  constexpr Window() : ox(), oy(), cls(), ncls(0), d(), csize() {
-    int idx = 0;
-    for (int dd = 1; dd <= DMAX; ++dd) {
-      int found = 0;
-      for (int y = -R; y <= R; ++y)
-        for (int x = -R; x <= R; ++x)
-          if (x * x + y * y == dd) {
-            ox[idx] = x;
-            oy[idx] = y;
-            cls[idx] = ncls;
-            ++idx;
-            ++found;
-          }
-      if (found) {
-        d[ncls] = dd;
-        csize[ncls] = found;
-        ++ncls;
-      }
-    }
-  }
-};
-
-template <int R>
-struct WinConst {
-  static constexpr Window<R> w{};
-  static constexpr int NCLS = w.ncls;
-};
 
 // ------------------------------------------------------------ energy change
 //
