@@ -102,8 +102,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="tile256_n256_t1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16,batched",
-                    help="comma list of forms to run: fp32 (headline), bf16, batched")
+    ap.add_argument("--forms", default="fp32,bf16,swap,batched",
+                    help="comma list of forms to run: fp32 (headline), bf16, swap, batched")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -123,11 +123,11 @@ def main() -> int:
     K2 = w["colour_k"] ** 2
     P, T, N = w["width"] * w["height"], w["t_heaviside"], w["n"]
 
-    def timed_form(precision: int) -> dict:
+    def timed_form(precision: int, move: int = 0) -> dict:
         """K sweeps of the overlapped schedule with HIP events around every
         launch (the timed region), then K graph-replayed sweeps."""
         prob = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]), stream=stream.cuda_stream,
-                                    precision=precision)
+                                    precision=precision, move=move)
         prob.init_offsets(inp["offsets"])
         prob.compute_errors()
         prob.sweep(args.warmup)
@@ -169,6 +169,7 @@ def main() -> int:
         del src, dst
     fp32 = timed_form(bnlat.BN_FP32)
     bf16 = timed_form(bnlat.BN_BF16) if "bf16" in forms else None
+    swap = timed_form(bnlat.BN_FP32, bnlat.BN_SWAP) if "swap" in forms else None
     avg, total_ms = fp32["kernels_ms"], fp32["total_ms"]
     M = P // K2
 
@@ -234,6 +235,14 @@ def main() -> int:
             "energy_rel_diff_vs_fp32": abs(bf16["energy"] - fp32["energy"]) / abs(fp32["energy"]),
             "quality_rel_diff_vs_fp32": max(abs(a - b) / b for a, b in zip(bf16["quality_sigma_1_4_16"],
                                                                             fp32["quality_sigma_1_4_16"]))},
+        "swap": None if swap is None else {
+            "mutation": "swap (couples from the XOR-scrambled pixel permutation, no recount)",
+            "value": P * args.steps / (swap["total_ms"] * 1e-3),
+            "graph_value": P * args.steps / (swap["graph_ms"] * 1e-3),
+            "kernels_ms": {"evaluate_per_pass": swap["kernels_ms"]["evaluate_per_phase"],
+                           "commit_per_pass": swap["kernels_ms"]["commit_per_phase"],
+                           "passes": swap["kernels_ms"]["phases"]},
+            "evaluate_hbm_gbs": delta_bytes / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9},
         "batched": batch,
         "window_offsets": win,
     }

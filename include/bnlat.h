@@ -63,9 +63,22 @@ typedef enum {
  *          accepted moves are re-checked with the exact integer form.      */
 typedef enum { BN_FP32 = 0, BN_BF16 = 1 } bn_precision;
 
-/* Mutation.  BN_REDRAW: the pixel's offset is redrawn from the Philox
- * stream and its hit counts recomputed (Sec. 3.4 run with random offset
- * proposals).  BN_SWAP (pixel-pair swaps, Sec. 2 and Sec. 3.4) is reserved. */
+/* Mutation.
+ * BN_REDRAW: the pixel's offset is redrawn from the Philox stream and its hit
+ *   counts recomputed (Sec. 3.4 run with random offset proposals); a sweep is
+ *   K*K colour phases.
+ * BN_SWAP: the paper's own move (the tile is optimised by permuting its
+ *   pixels, Sec. 2; couples are swapped in parallel, Sec. 3.4).  A fixed
+ *   permutation pi of the P pixels sorts them by the 64-bit keys
+ *   (w0 << 32) | w1 of Philox((p, 0, problem_id, 0xE)); pass kappa of sweep s
+ *   XORs the listed pixel indices with word 0 of Philox((kappa, s,
+ *   problem_id, 0xF)) mod P, takes list positions [kappa M, (kappa+1) M)
+ *   with M = P / (K*K), and couples positions 2i and 2i+1.  Every couple is
+ *   evaluated on the pass-start state (exact integer energy change including
+ *   the pair term when the two pixels are within each other's window) and
+ *   accepted couples exchange offsets and hit counts; nothing is recounted.
+ *   A sweep is K*K passes.  Requires W*H a power of two, W*H >= 2 K*K, FP32
+ *   precision and Heaviside integrands only (else BN_EUNSUPPORTED). */
 typedef enum { BN_REDRAW = 0, BN_SWAP = 1 } bn_move;
 
 /* Problem description (Eq. (1) window, Sec. 3.2 lattice, Sec. 3.4 classes). */
@@ -101,8 +114,8 @@ typedef struct {
 } bn_gaussian;
 
 typedef struct {
-  uint64_t proposals;    /* pixel proposals evaluated                          */
-  uint64_t accepts;      /* proposals committed                                */
+  uint64_t proposals;    /* moves evaluated (redraw: pixels; swap: couples)    */
+  uint64_t accepts;      /* moves committed                                    */
   uint64_t bf16_vetoes;  /* BF16 accepts rejected by the exact re-check        */
   uint64_t sweep_index;  /* sweep index after the call                         */
 } bn_sweep_stats;
@@ -216,6 +229,14 @@ bn_status bn_phase_advance(bn_problem p);
 bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* delta,
                        uint8_t* accept);
 
+/* Swap problems (BN_SWAP): the phase steps above run swap pass kappa
+ * (propose lists the pass's couples, evaluate decides them, commit exchanges
+ * the accepted ones), and bn_get_swap_pass copies the last evaluated pass in
+ * couple order: pixels a, b uint32 [M/2] (y*W + x), delta double [M/2],
+ * accept uint8 [M/2]; every pointer is nullable.  bn_get_phase returns
+ * BN_ESTATE for swap problems and bn_get_swap_pass for redraw problems. */
+bn_status bn_get_swap_pass(bn_problem p, uint32_t* a, uint32_t* b, double* delta, uint8_t* accept);
+
 /* ----------------------------------------------------------------- batching */
 
 /* Independent problems (e.g. the dimension pairs of a padded sampler,
@@ -246,6 +267,9 @@ bn_status bn_validate_config(const bn_config* cfg);
  * class_w double [*n_classes]; pass NULL arrays to query the count. */
 bn_status bn_window_classes(const bn_config* cfg, uint32_t* n_classes, uint32_t* class_d,
                             double* class_w);
+/* Pixel permutation pi of the swap mutation (see BN_SWAP): out uint32 [W*H]
+ * receives pi[L] for L = 0 .. W*H-1.  Requires W*H a power of two. */
+bn_status bn_swap_permutation(const bn_config* cfg, uint32_t* out);
 /* Exact area (FP64) of the unit square on the hit side of one Heaviside. */
 bn_status bn_heaviside_area(const bn_heaviside* h, double* out);
 /* The Philox-drawn Heavisides bn_create_problem uses when given NULL. */

@@ -80,11 +80,13 @@ _SIGNATURES = {
     "bn_phase_commit": [_P, C.c_uint32],
     "bn_phase_advance": [_P],
     "bn_get_phase": [_P, _P, _P, _P, _P],
+    "bn_get_swap_pass": [_P, _P, _P, _P, _P],
     "bn_create_batch": [_P, C.c_uint32, C.c_char_p, C.POINTER(_P)],
     "bn_batch_sweep": [_P, C.c_uint32],
     "bn_destroy_batch": [_P],
     "bn_batch_tuning": [_P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)],
     "bn_validate_config": [C.POINTER(Config)],
+    "bn_swap_permutation": [C.POINTER(Config), _P],
     "bn_window_classes": [C.POINTER(Config), C.POINTER(C.c_uint32), _P, _P],
     "bn_heaviside_area": [C.POINTER(Heaviside), C.POINTER(C.c_double)],
     "bn_draw_heavisides": [C.c_uint64, C.c_uint32, C.c_uint32, _P],
@@ -146,6 +148,13 @@ def heaviside_array(table: dict) -> np.ndarray:
 # ------------------------------------------------------------ host-only calls
 def validate_config(cfg: Config) -> None:
     _call("bn_validate_config", C.byref(cfg))
+
+
+def swap_permutation(cfg: Config) -> np.ndarray:
+    """Pixel permutation of the swap mutation (host computation)."""
+    out = np.zeros(cfg.width * cfg.height, dtype=np.uint32)
+    _call("bn_swap_permutation", C.byref(cfg), _ptr(out))
+    return out
 
 
 def window_classes(cfg: Config):
@@ -331,6 +340,16 @@ class Problem:
         a = np.zeros(self.M, dtype=np.uint8)
         _call("bn_get_phase", self.handle, _ptr(u), _ptr(c), _ptr(d), _ptr(a))
         return {"u_new": u, "c_new": c, "delta": d, "accept": a.astype(bool)}
+
+    def get_swap_pass(self):
+        """Couples of the last evaluated swap pass: pixels a, b, delta, accept."""
+        half = self.M // 2
+        a = np.zeros(half, dtype=np.uint32)
+        b = np.zeros(half, dtype=np.uint32)
+        d = np.zeros(half, dtype=np.float64)
+        acc = np.zeros(half, dtype=np.uint8)
+        _call("bn_get_swap_pass", self.handle, _ptr(a), _ptr(b), _ptr(d), _ptr(acc))
+        return {"a": a, "b": b, "delta": d, "accept": acc.astype(bool)}
 
 
 class Batch:

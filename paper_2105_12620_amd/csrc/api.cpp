@@ -12,6 +12,7 @@
 
 #include "../../include/bnlat.h"
 #include "bnlat_dev.h"
+#include "swap_dev.h"
 
 using namespace bnlat;
 
@@ -38,6 +39,8 @@ bn_status fail(bn_status s, const char* fmt, ...) {
 uint32_t round_up(uint32_t v, uint32_t a) { return (v + a - 1) / a * a; }
 
 bool is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
+
+std::vector<uint32_t> swap_permutation(const bn_config& c);
 
 // ------------------------------------------------------------------ Philox
 // Host Philox4x32-10 (Salmon et al., SC 2011) for drawing integrands.
@@ -203,6 +206,12 @@ struct bn_problem_s {
   // profiling: eager overlapped sweeps with events around the launches
   bool profiling = false;
   std::vector<hipEvent_t> prof_recount, prof_eval, prof_commit;   // start/stop pairs
+  // Swap mutation: permutation tables, pixel-major counts and pass scratch;
+  // one captured sweep of K^2 passes.
+  SwapView sv{};
+  hipGraph_t swap_graph = nullptr;
+  hipGraphExec_t swap_exec = nullptr;
+  bool swap_failed = false;
 
   template <class T>
   bn_status alloc(T** ptr, size_t count) {
@@ -221,6 +230,8 @@ struct bn_problem_s {
     if (graph) (void)hipGraphDestroy(graph);
     if (pair_exec) (void)hipGraphExecDestroy(pair_exec);
     if (pair_graph) (void)hipGraphDestroy(pair_graph);
+    if (swap_exec) (void)hipGraphExecDestroy(swap_exec);
+    if (swap_graph) (void)hipGraphDestroy(swap_graph);
     if (stream) (void)hipStreamSynchronize(stream);
     if (aux) (void)hipStreamSynchronize(aux);
     for (void* p : allocs) (void)hipFree(p);
@@ -292,7 +303,13 @@ bn_status supported(const bn_config* c) {
   if (c->t_gauss > (1u << 16)) return fail(BN_EINVAL, "more than 65536 Gaussian integrands");
   if (c->precision == BN_BF16 && c->colour_k != 2)
     return fail(BN_EUNSUPPORTED, "the BF16 matrix-core form needs colour_k = 2");
-  if (c->move != BN_REDRAW) return fail(BN_EUNSUPPORTED, "swap moves are not supported by this build");
+  if (c->move == BN_SWAP) {
+    const uint64_t P = (uint64_t)c->width * c->height;
+    if (!is_pow2((uint32_t)P) || P < 2ull * c->colour_k * c->colour_k)
+      return fail(BN_EUNSUPPORTED, "swap moves need W*H a power of two and at least 2 K^2");
+    if (c->precision != BN_FP32) return fail(BN_EUNSUPPORTED, "swap moves run in the FP32 (exact integer) form only");
+    if (c->t_gauss) return fail(BN_EUNSUPPORTED, "swap moves support Heaviside integrands only");
+  }
   return BN_OK;
 }
 
@@ -527,6 +544,128 @@ bn_status overlapped_sweeps(bn_problem p, uint32_t k) {
   return BN_OK;
 }
 
+// ------------------------------------------------------------ swap mutation
+// Pixel permutation of the swap passes: pixels sorted by the 64-bit keys
+// (w0 << 32) | w1 of Philox((p, 0, problem, S_PERM)), ties by pixel index.
+std::vector<uint32_t> swap_permutation(const bn_config& c) {
+  const uint32_t P = c.width * c.height;
+  std::vector<uint64_t> key(P);
+  for (uint32_t q = 0; q < P; ++q) {
+    uint32_t w[4] = {q, 0u, c.problem_id, S_PERM};
+    philox10(w, (uint32_t)c.seed, (uint32_t)(c.seed >> 32));
+    key[q] = ((uint64_t)w[0] << 32) | w[1];
+  }
+  std::vector<uint32_t> perm(P);
+  for (uint32_t q = 0; q < P; ++q) perm[q] = q;
+  std::stable_sort(perm.begin(), perm.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+  return perm;
+}
+
+bn_status setup_swap(bn_problem p) {
+  const uint32_t P = p->v.w * p->v.h, M = P / (p->v.k * p->v.k);
+  const std::vector<uint32_t> perm = swap_permutation(p->cfg);
+  std::vector<uint32_t> pinv(P);
+  for (uint32_t L = 0; L < P; ++L) pinv[perm[L]] = L;
+  const uint32_t r = p->v.radius, dmax = 2 * r * r;
+  std::vector<int32_t> dcls(dmax + 1, -1);
+  for (size_t c = 0; c < p->cls_d.size(); ++c) dcls[p->cls_d[c]] = (int32_t)c;
+  SwapView& sv = p->sv;
+  uint32_t *perm_d, *pinv_d;
+  int32_t* dcls_d;
+  bn_status s;
+  if ((s = p->alloc(&perm_d, P)) != BN_OK || (s = p->alloc(&pinv_d, P)) != BN_OK ||
+      (s = p->alloc(&dcls_d, dmax + 1)) != BN_OK || (s = p->alloc(&sv.cpm, (size_t)P * p->v.tp)) != BN_OK ||
+      (s = p->alloc(&sv.order, M)) != BN_OK || (s = p->alloc(&sv.nsel, 1)) != BN_OK ||
+      (s = p->alloc(&sv.xs, (size_t)p->v.ncls * M)) != BN_OK || (s = p->alloc(&sv.d2, M / 2)) != BN_OK)
+    return s;
+  sv.perm = perm_d;
+  sv.pinv = pinv_d;
+  sv.dcls = dcls_d;
+  sv.m = M;
+  HIPCHK(hipMemcpyAsync(perm_d, perm.data(), (size_t)P * 4, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(pinv_d, pinv.data(), (size_t)P * 4, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(dcls_d, dcls.data(), dcls.size() * 4, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemsetAsync(sv.order, 0, (size_t)M * 4, p->stream));
+  HIPCHK(hipMemsetAsync(sv.nsel, 0, 4, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return BN_OK;
+}
+
+// One swap pass on the pixel-major counts, in three steps.
+bn_status swap_select(bn_problem p, uint32_t kappa) {
+  HIPCHK(launch_swap_select(p->v, p->sv, kappa, p->stream));
+  return BN_OK;
+}
+
+bn_status swap_evaluate(bn_problem p, uint32_t kappa) {
+  HIPCHK(launch_swap_evaluate(p->v, p->sv, kappa, p->stream));
+  return BN_OK;
+}
+
+bn_status swap_commit(bn_problem p) {
+  HIPCHK(launch_swap_commit(p->v, p->sv, p->stream));
+  return BN_OK;
+}
+
+bn_status record_swap_sweep(bn_problem p) {
+  bn_status s;
+  for (uint32_t kappa = 0; kappa < p->v.k * p->v.k; ++kappa) {
+    ProfMark me(p, &p->prof_eval, p->stream);
+    if ((s = swap_select(p, kappa)) != BN_OK || (s = swap_evaluate(p, kappa)) != BN_OK) return s;
+    if ((s = me.end()) != BN_OK) return s;
+    ProfMark mc(p, &p->prof_commit, p->stream);
+    if ((s = swap_commit(p)) != BN_OK) return s;
+    if ((s = mc.end()) != BN_OK) return s;
+  }
+  HIPCHK(launch_advance(p->v, p->stream));
+  return BN_OK;
+}
+
+bn_status build_swap_graph(bn_problem p) {
+  if (p->swap_exec || p->swap_failed) return BN_OK;
+  HIPCHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+  bn_status s = record_swap_sweep(p);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->stream, &g);
+  if (s != BN_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p->swap_failed = true;
+    return BN_OK;
+  }
+  e = hipGraphInstantiate(&p->swap_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g);
+    p->swap_exec = nullptr;
+    p->swap_failed = true;
+    return BN_OK;
+  }
+  p->swap_graph = g;
+  return BN_OK;
+}
+
+// k swap sweeps: counts to the pixel-major copy, K^2 passes per sweep
+// (graph-replayed unless profiling), counts back to the tiled layout.
+bn_status swap_sweeps(bn_problem p, uint32_t k) {
+  if (!k) return BN_OK;
+  bn_status s;
+  HIPCHK(launch_to_pixel_major(p->v, p->sv, p->stream));
+  if (!p->profiling && (s = build_swap_graph(p)) != BN_OK) return s;
+  for (uint32_t i = 0; i < k; ++i) {
+    if (p->swap_exec && !p->profiling) {
+      HIPCHK(hipGraphLaunch(p->swap_exec, p->stream));
+    } else if ((s = record_swap_sweep(p)) != BN_OK) {
+      return s;
+    }
+  }
+  HIPCHK(launch_from_pixel_major(p->v, p->sv, p->stream));
+  return BN_OK;
+}
+
 bn_status build_graph(bn_problem p) {
   if (p->graph_exec || p->graph_failed) return BN_OK;
   if (p->stream == nullptr) {
@@ -737,6 +876,16 @@ bn_status bn_window_classes(const bn_config* cfg, uint32_t* n_classes, uint32_t*
   return BN_OK;
 }
 
+bn_status bn_swap_permutation(const bn_config* cfg, uint32_t* out) {
+  bn_status s = validate(cfg);
+  if (s != BN_OK) return s;
+  if (!out) return fail(BN_EINVAL, "out is NULL");
+  if (!is_pow2(cfg->width * cfg->height)) return fail(BN_EINVAL, "W*H must be a power of two");
+  const std::vector<uint32_t> perm = swap_permutation(*cfg);
+  std::copy(perm.begin(), perm.end(), out);
+  return BN_OK;
+}
+
 bn_status bn_heaviside_area(const bn_heaviside* h, double* out) {
   if (!h || !out) return fail(BN_EINVAL, "NULL argument");
   return heaviside_area_checked(*h, out);
@@ -927,6 +1076,10 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
     delete p;
     return fail(BN_EHIP, "uploading tables: %s", hipGetErrorString(e));
   }
+  if (cfg->move == BN_SWAP && (s = setup_swap(p)) != BN_OK) {
+    delete p;
+    return s;
+  }
   *out = p;
   return BN_OK;
 }
@@ -972,14 +1125,15 @@ bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats) {
     bn_status s = sync(p);
     if (s != BN_OK) return s;
   }
-  bn_status s = overlapped_sweeps(p, k);
+  bn_status s = p->cfg.move == BN_SWAP ? swap_sweeps(p, k) : overlapped_sweeps(p, k);
   if (s != BN_OK) return s;
   p->sweep += k;
   if (k) p->errors_valid = false;
   if (stats) {
     HIPCHK(hipMemcpyAsync(after, p->v.ctr, sizeof after, hipMemcpyDeviceToHost, p->stream));
     if ((s = sync(p)) != BN_OK) return s;
-    stats->proposals = (uint64_t)k * p->v.w * p->v.h;
+    // redraw: one proposal per pixel; swap: one per couple
+    stats->proposals = (uint64_t)k * p->v.w * p->v.h / (p->cfg.move == BN_SWAP ? 2 : 1);
     stats->accepts = after[1] - before[1];
     stats->bf16_vetoes = after[2] - before[2];
     stats->sweep_index = after[0];
@@ -1218,6 +1372,10 @@ bn_status bn_phase_propose(bn_problem p, uint32_t kappa) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
   if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
+  if (p->cfg.move == BN_SWAP) {
+    HIPCHK(launch_to_pixel_major(p->v, p->sv, p->stream));
+    return swap_select(p, kappa);
+  }
   HIPCHK(launch_count(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
   HIPCHK(launch_gauss_est(p->v, MODE_CLASS, p->v.pc, p->stream));
   return BN_OK;
@@ -1227,6 +1385,7 @@ bn_status bn_phase_evaluate(bn_problem p, uint32_t kappa) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
   if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
+  if (p->cfg.move == BN_SWAP) return swap_evaluate(p, kappa);
   HIPCHK(launch_gauss_delta(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
   HIPCHK(launch_delta(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
   return BN_OK;
@@ -1236,6 +1395,13 @@ bn_status bn_phase_commit(bn_problem p, uint32_t kappa) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
   if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
+  if (p->cfg.move == BN_SWAP) {
+    bn_status s = swap_commit(p);
+    if (s != BN_OK) return s;
+    HIPCHK(launch_from_pixel_major(p->v, p->sv, p->stream));
+    p->errors_valid = false;
+    return BN_OK;
+  }
   HIPCHK(launch_commit(p->v, kappa, p->stream));
   HIPCHK(launch_gauss_commit(p->v, kappa, p->stream));
   p->errors_valid = false;
@@ -1249,8 +1415,28 @@ bn_status bn_phase_advance(bn_problem p) {
   return BN_OK;
 }
 
+bn_status bn_get_swap_pass(bn_problem p, uint32_t* a, uint32_t* b, double* delta, uint8_t* accept) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  if (p->cfg.move != BN_SWAP) return fail(BN_ESTATE, "the problem does not use swap moves");
+  const uint32_t half = p->sv.m / 2;
+  if (a || b) {
+    std::vector<uint32_t> ab((size_t)2 * half);
+    HIPCHK(hipMemcpyAsync(ab.data(), p->v.u_new, ab.size() * 4, hipMemcpyDeviceToHost, p->stream));
+    bn_status s = sync(p);
+    if (s != BN_OK) return s;
+    for (uint32_t i = 0; i < half; ++i) {
+      if (a) a[i] = ab[2 * i];
+      if (b) b[i] = ab[2 * i + 1];
+    }
+  }
+  if (delta) HIPCHK(hipMemcpyAsync(delta, p->v.delta, (size_t)half * 8, hipMemcpyDeviceToHost, p->stream));
+  if (accept) HIPCHK(hipMemcpyAsync(accept, p->v.accept, half, hipMemcpyDeviceToHost, p->stream));
+  return sync(p);
+}
+
 bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* delta, uint8_t* accept) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
+  if (p->cfg.move == BN_SWAP) return fail(BN_ESTATE, "swap passes are read with bn_get_swap_pass");
   const uint32_t M = p->v.pc;
   if (u_new) HIPCHK(hipMemcpyAsync(u_new, p->v.u_new, (size_t)M * 4, hipMemcpyDeviceToHost, p->stream));
   if (c_new) {
@@ -1272,6 +1458,7 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
     if (p->stream != members[0]->stream) return fail(BN_EINVAL, "members must share one stream");
     if (p->cfg.colour_k != members[0]->cfg.colour_k) return fail(BN_EINVAL, "members must share colour_k");
     if (p->cfg.precision != BN_FP32) return fail(BN_EUNSUPPORTED, "batched members must use FP32 precision");
+    if (p->cfg.move != BN_REDRAW) return fail(BN_EUNSUPPORTED, "batched members must use redraw moves");
     if (p->cfg.t_gauss) return fail(BN_EUNSUPPORTED, "batched members must have Heaviside integrands only");
     for (uint32_t j = 0; j < i; ++j)
       if (members[j] == p) return fail(BN_EINVAL, "member %u appears twice", i);

@@ -119,3 +119,20 @@ def test_device_calls_fail_loudly_without_gpu(L):
     with pytest.raises(bnlat.BnlatError) as e:
         bnlat.Problem(cfg())
     assert e.value.status == bnlat.BN_EHIP
+
+
+def test_swap_permutation_matches_oracle(L):
+    from oracle import sweep as osw
+    for w, h, seed, pid in [(16, 8, 5, 0), (64, 64, 3, 7), (256, 256, 2, 0)]:
+        c = cfg(width=w, height=h, seed=seed, problem_id=pid, move=bnlat.BN_SWAP)
+        ref = osw.Problem(n=16, g=(1, 7), width=w, height=h, radius=3, sigma=2.1, colour_k=2, seed=seed,
+                          problem_id=pid, table=synthgen.heaviside_table(4, seed=0), move=1)
+        np.testing.assert_array_equal(bnlat.swap_permutation(c), ref.perm)
+
+
+@pytest.mark.parametrize("kw", [dict(width=48, height=32), dict(precision=1), dict(t_gauss=8),
+                                dict(width=2, height=2, colour_k=2, radius=1)])
+def test_swap_unsupported_forms_rejected_before_device(L, kw):
+    with pytest.raises(bnlat.BnlatError) as e:
+        bnlat.Problem(cfg(move=bnlat.BN_SWAP, **kw))
+    assert e.value.status == bnlat.BN_EUNSUPPORTED
