@@ -36,7 +36,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile256_n256_t1024_fp32.md")
 
 
-COUNT_KERNEL_SOURCES = ("bnlat_dev.h", "device_common.h", "kernels.hip")
+COUNT_KERNEL_SOURCES = ("bnlat_dev.h", "device_common.h", "count.hip")
 
 
 def kernel_digest() -> str:

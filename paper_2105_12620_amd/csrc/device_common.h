@@ -114,5 +114,12 @@ struct WinConst {
   static constexpr int NCLS = w.ncls;
 };
 
+// Member of a batch that owns launch block blk (prefix sums of blocks per member).
+__device__ inline uint32_t batch_member(const uint32_t* __restrict__ pre, uint32_t nmem, uint32_t blk) {
+  uint32_t i = 0;
+  while (i + 1 < nmem && pre[i + 1] <= blk) ++i;
+  return __builtin_amdgcn_readfirstlane(i);
+}
+
 }  // namespace
 }  // namespace bnlat

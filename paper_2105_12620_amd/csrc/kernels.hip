@@ -29,167 +29,6 @@
 namespace bnlat {
 namespace {
 
-// Resolve the pixel, offset and output buffer (row index, row count) of work
-// item j of a count launch.
-template <int MODE>
-__device__ inline void count_target(const DevView& v, uint32_t kappa, uint32_t j, uint32_t m,
-                                    uint32_t& p, uint32_t& u, uint16_t*& buf, uint32_t& row,
-                                    uint32_t& rows) {
-  if (MODE == MODE_ALL) {
-    p = j;
-    u = v.U[p];
-    buf = v.cnt;
-    row = p;
-    rows = v.w * v.h;
-  } else if (MODE == MODE_CLASS) {
-    p = class_pixel(v, kappa, j);
-    u = proposal(v, p, (uint32_t)v.ctr[0]);
-    buf = v.c_new;
-    row = j;
-    rows = v.pc;
-  } else if (MODE == MODE_SWEEP) {
-    const uint32_t cls = j / v.pc, jj = j - cls * v.pc;
-    p = class_pixel(v, cls, jj);
-    u = proposal(v, p, (uint32_t)v.ctr[0] + kappa);
-    buf = v.c_new + (size_t)cls * v.pc * v.tp;
-    row = jj;
-    rows = v.pc;
-  } else {
-    p = v.pix_list[j];
-    u = v.u_new[j];
-    buf = v.c_new;
-    row = j;
-    rows = m;
-  }
-}
-
-// ----------------------------------------------------------- hit counting
-//
-// Estimator of the test-integrand map (Sec. 2): c[p][t] = number of the N
-// scrambled samples on the hit side of Heaviside t.
-//
-// k_count_points (N >= 64): the 64 lanes of a wave hold 64*PPL samples of one
-// pixel (PPL per lane); the wave walks integrands with wave-uniform
-// parameters in scalar registers.  Per (sample, integrand): one v_dot2 and
-// one v_cmp; the 64 predicate bits of a compare are counted with a scalar
-// popcount.  Counts for 64 consecutive integrands are gathered one per lane
-// and stored as one coalesced 128-byte row segment.  N > 64*PPL is handled
-// in groups of 64*PPL samples.
-template <int PPL, int MODE>
-__device__ __forceinline__ void count_points_body(const DevView& v, const int2* __restrict__ ihp,
-                                                  uint32_t kappa, uint32_t m, uint32_t tch,
-                                                  uint32_t blk) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
-  const uint32_t nch = (v.tp + tch - 1) / tch;
-  const uint32_t j = wave / nch, ch = wave - j * nch;
-  if (j >= m) return;
-  uint32_t p, u, row, rows;
-  uint16_t* buf;
-  count_target<MODE>(v, kappa, j, m, p, u, buf, row, rows);
-  if ((MODE == MODE_CLASS || MODE == MODE_SWEEP) && ch == 0 && lane == 0) v.u_new[j] = u;
-
-  const uint32_t groups = v.n / (64u * PPL);
-  uint32_t sp[PPL];
-#pragma unroll
-  for (int k = 0; k < PPL; ++k) sp[k] = centre(wrap_add(v.lat[lane + 64 * k], u));
-  const float inv_n = 1.0f / (float)v.n;
-  const uint32_t t0 = ch * tch, t1 = min(t0 + tch, v.tp);
-  for (uint32_t tb = t0; tb < t1; tb += 64) {
-    int total = 0;
-    if (tb < v.t) {
-      for (uint32_t g = 0; g < groups; ++g) {
-        if (groups > 1) {
-#pragma unroll
-          for (int k = 0; k < PPL; ++k)
-            sp[k] = centre(wrap_add(v.lat[g * 64 * PPL + lane + 64 * k], u));
-        }
-        // one integrand per step: PPL dot products and compares on the
-        // vector ALU, popcounts and adds on the scalar ALU, and the count
-        // written into lane tt
-        int myc = 0;
-        const int4* ip = (const int4*)(ihp + tb);
-#pragma unroll 1
-        for (int blk = 0; blk < 8; ++blk) {
-          // eight integrands' parameters in one scalar load
-          const int4 q0 = ip[4 * blk], q1 = ip[4 * blk + 1], q2 = ip[4 * blk + 2], q3 = ip[4 * blk + 3];
-          const int nn[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
-          const int dd[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
-#pragma unroll
-          for (int k8 = 0; k8 < 8; ++k8) {
-            int c = 0;
-#pragma unroll
-            for (int k = 0; k < PPL; ++k)
-              c += __popcll(__ballot(dot2((uint32_t)nn[k8], sp[k], 0) > dd[k8]));
-            myc = bnlat_writelane_i32(c, 8 * blk + k8, myc);
-          }
-        }
-        total += myc;
-      }
-    }
-    buf[tix(row, tb + lane, rows)] = (uint16_t)total;
-    if (MODE == MODE_ALL)
-      v.err[(size_t)p * v.tp + tb + lane] = (float)total * inv_n - v.area[tb + lane];
-  }
-}
-
-template <int PPL, int MODE>
-__global__ __launch_bounds__(256) void k_count_points(DevView v, const int2* __restrict__ ihp,
-                                                      uint32_t kappa, uint32_t m, uint32_t tch) {
-  count_points_body<PPL, MODE>(v, ihp, kappa, m, tch, blockIdx.x);
-}
-
-// Member of a batch that owns launch block blk (prefix sums of blocks per member).
-__device__ inline uint32_t batch_member(const uint32_t* __restrict__ pre, uint32_t nmem, uint32_t blk) {
-  uint32_t i = 0;
-  while (i + 1 < nmem && pre[i + 1] <= blk) ++i;
-  return __builtin_amdgcn_readfirstlane(i);
-}
-
-template <int PPL>
-__global__ __launch_bounds__(256) void k_count_points_batch(const DevView* __restrict__ views,
-                                                            const uint32_t* __restrict__ pre,
-                                                            uint32_t nmem, uint32_t kappa) {
-  const uint32_t i = batch_member(pre, nmem, blockIdx.x);
-  const DevView v = views[i];
-  count_points_body<PPL, MODE_CLASS>(v, v.ihp, kappa, v.pc, v.tch, blockIdx.x - pre[i]);
-}
-
-// k_count_integrands (N < 64): lanes hold 64 integrands of one pixel and walk
-// the N samples, which are wave-uniform.
-template <int MODE>
-__device__ __forceinline__ void count_integrands_body(const DevView& v, uint32_t kappa, uint32_t m,
-                                                      uint32_t blk) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
-  const uint32_t nch = v.tp >> 6;
-  const uint32_t j = wave / nch, ch = wave - j * nch;
-  if (j >= m) return;
-  uint32_t p, u, row, rows;
-  uint16_t* buf;
-  count_target<MODE>(v, kappa, j, m, p, u, buf, row, rows);
-  if ((MODE == MODE_CLASS || MODE == MODE_SWEEP) && ch == 0 && lane == 0) v.u_new[j] = u;
-  const uint32_t t = ch * 64 + lane;
-  const int2 q = v.ihp[t];
-  int c = 0;
-  for (uint32_t i = 0; i < v.n; ++i) c += dot2((uint32_t)q.x, centre(wrap_add(v.lat[i], u)), 0) > q.y;
-  buf[tix(row, t, rows)] = (uint16_t)c;
-  if (MODE == MODE_ALL) v.err[(size_t)p * v.tp + t] = (float)c * (1.0f / (float)v.n) - v.area[t];
-}
-
-template <int MODE>
-__global__ __launch_bounds__(256) void k_count_integrands(DevView v, uint32_t kappa, uint32_t m) {
-  count_integrands_body<MODE>(v, kappa, m, blockIdx.x);
-}
-
-__global__ __launch_bounds__(256) void k_count_integrands_batch(const DevView* __restrict__ views,
-                                                                const uint32_t* __restrict__ pre,
-                                                                uint32_t nmem, uint32_t kappa) {
-  const uint32_t i = batch_member(pre, nmem, blockIdx.x);
-  const DevView v = views[i];
-  count_integrands_body<MODE_CLASS>(v, kappa, v.pc, blockIdx.x - pre[i]);
-}
-
 // ------------------------------------------------------------ energy change
 //
 // Energy change of one pixel's move (Eq. (1) over the window, both pair
@@ -549,27 +388,61 @@ __global__ __launch_bounds__(512) void k_delta_mfma(DevView v, uint32_t kappa, u
 #pragma unroll
     for (int ct = 0; ct < 3; ++ct) acc[oy][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const uint32_t t_begin = blockIdx.z * trlen, t_end = min(t_begin + trlen, v.tp);
-  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 16) {
-    __syncthreads();
-    // region counts for integrands t0..t0+15 (two 8-integrand tiles)
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(2 * G::RROWS * G::RUSED); i += blockDim.x) {
+  // Staging plan, fixed for the whole integrand range: thread i stages region
+  // items i, i + 512, ... (an item = 8 counts of one region pixel, half 0 or 1
+  // of the 16-integrand slice); the global pixel of each item is computed once.
+  constexpr int NT = 64 * G::BYC;
+  constexpr int NITEM = 2 * G::RROWS * G::RUSED;
+  constexpr int ITER = (NITEM + NT - 1) / NT;
+  uint32_t item_pix[ITER], item_lds[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const uint32_t i = threadIdx.x + it * NT;
+    item_pix[it] = 0xFFFFFFFFu;
+    item_lds[it] = 0;
+    if (i < (uint32_t)NITEM) {
       const uint32_t half = i / (G::RROWS * G::RUSED), pix = i - half * (G::RROWS * G::RUSED);
       const uint32_t rr = pix / G::RUSED, cc = pix - rr * G::RUSED;
       uint32_t gy = ys + rr, gx = xs + cc;
       while (gy >= v.h) gy -= v.h;
       while (gx >= v.w) gx -= v.w;
-      const uint4 q = *(const uint4*)(v.cnt + tix(gy * v.w + gx, t0 + 8 * half, P));
-      reg[((2 * half) * G::RROWS + rr) * G::RCOLS + cc] = to_bf16x4(q.x, q.y);
-      reg[((2 * half + 1) * G::RROWS + rr) * G::RCOLS + cc] = to_bf16x4(q.z, q.w);
+      item_pix[it] = (gy * v.w + gx) | (half << 31);
+      item_lds[it] = ((2 * half) * G::RROWS + rr) * G::RCOLS + cc;
+    }
+  }
+  const uint32_t own_j = own_ok ? own_a * v.cw + own_b : 0;
+
+  // Software pipeline: the loads of slice t0 + 16 are in flight while the
+  // matrix cores work on slice t0.
+  uint4 q[ITER], cn = make_uint4(0, 0, 0, 0), co = make_uint4(0, 0, 0, 0);
+  const uint32_t t_begin = blockIdx.z * trlen, t_end = min(t_begin + trlen, v.tp);
+  auto load_slice = [&](uint32_t t0) {
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      if (item_pix[it] != 0xFFFFFFFFu) {
+        const uint32_t half = item_pix[it] >> 31, pix = item_pix[it] & 0x7FFFFFFFu;
+        q[it] = *(const uint4*)(v.cnt + tix(pix, t0 + 8 * half, P));
+      }
+    }
+    if (own_ok) {
+      cn = *(const uint4*)(v.c_new + tix(own_j, t0 + 8 * own_half, v.pc));
+      co = *(const uint4*)(v.cnt + tix(own_p, t0 + 8 * own_half, P));
+    }
+  };
+  if (t_begin < t_end) load_slice(t_begin);
+  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 16) {
+    // region counts for integrands t0..t0+15 (two 8-integrand tiles) as BF16
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      if (item_pix[it] != 0xFFFFFFFFu) {
+        reg[item_lds[it]] = to_bf16x4(q[it].x, q[it].y);
+        reg[item_lds[it] + G::RROWS * G::RCOLS] = to_bf16x4(q[it].z, q[it].w);
+      }
     }
     // count changes of the moved pixels
     if (threadIdx.x < 2u * G::NB) {
       uint2 lo = make_uint2(0, 0), hi = make_uint2(0, 0);
       if (own_ok) {
-        const uint32_t j = own_a * v.cw + own_b;
-        const uint4 cn = *(const uint4*)(v.c_new + tix(j, t0 + 8 * own_half, v.pc));
-        const uint4 co = *(const uint4*)(v.cnt + tix(own_p, t0 + 8 * own_half, P));
         const uint32_t nw[4] = {cn.x, cn.y, cn.z, cn.w}, ow[4] = {co.x, co.y, co.z, co.w};
         int d[8];
 #pragma unroll
@@ -588,6 +461,7 @@ __global__ __launch_bounds__(512) void k_delta_mfma(DevView v, uint32_t kappa, u
       dcs[(2 * own_half + 1) * G::NB + own_cp] = hi;
     }
     __syncthreads();
+    if (t0 + 16 < t_end) load_slice(t0 + 16);
     // lane l: MFMA row (pixel) l % 16, integrands 4 (l / 16) .. +3 of the slice
     const uint32_t quarter = lane >> 4, m = lane & 15;
     const uint2 a2 = dcs[quarter * G::NB + w * G::BXC + m];
@@ -602,6 +476,7 @@ __global__ __launch_bounds__(512) void k_delta_mfma(DevView v, uint32_t kappa, u
                                                                 acc[oy][ct], 0, 0, 0);
       }
     }
+    __syncthreads();
   }
   __syncthreads();
 
@@ -1014,27 +889,6 @@ __global__ __launch_bounds__(256) void k_gauss_errors(DevView v) {
   v.gerr[i] = (float)((double)v.gest[i] - v.gint[t]);
 }
 
-template <int MODE>
-hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStream_t s) {
-  if (m == 0) return hipSuccess;
-  if (v.n < 64) {
-    const uint64_t waves = (uint64_t)m * (v.tp >> 6);
-    hipLaunchKernelGGL(k_count_integrands<MODE>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
-                       v, kappa, m);
-    return hipGetLastError();
-  }
-  const uint32_t tch = v.tch;
-  const uint64_t waves = (uint64_t)m * ((v.tp + tch - 1) / tch);
-  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
-  switch (v.n) {
-    case 64: hipLaunchKernelGGL((k_count_points<1, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
-    case 128: hipLaunchKernelGGL((k_count_points<2, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
-    case 256: hipLaunchKernelGGL((k_count_points<4, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
-    case 512: hipLaunchKernelGGL((k_count_points<8, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
-    default: hipLaunchKernelGGL((k_count_points<16, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
-  }
-  return hipGetLastError();
-}
 
 template <int MODE>
 hipError_t delta_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStream_t s) {
@@ -1102,14 +956,6 @@ hipError_t launch_init_offsets(const DevView& v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
-  switch (mode) {
-    case MODE_ALL: return count_dispatch<MODE_ALL>(v, kappa, m, s);
-    case MODE_CLASS: return count_dispatch<MODE_CLASS>(v, kappa, m, s);
-    case MODE_SWEEP: return count_dispatch<MODE_SWEEP>(v, kappa, m, s);
-    default: return count_dispatch<MODE_LIST>(v, kappa, m, s);
-  }
-}
 
 template <int R>
 hipError_t mfma_launch(const DevView& v, uint32_t kappa, hipStream_t s) {
@@ -1276,23 +1122,6 @@ hipError_t launch_gauss_energy(const DevView& v, double* gsum, hipStream_t s) {
 
 // ------------------------------------------------------------------ batches
 
-int count_kind(const DevView& v) {
-  if (v.n < 64) return 0;
-  switch (v.n) {
-    case 64: return 1;
-    case 128: return 2;
-    case 256: return 4;
-    case 512: return 8;
-    default: return 16;
-  }
-}
-
-uint32_t count_blocks(const DevView& v) {
-  if (v.n < 64) return (uint32_t)(((uint64_t)v.pc * (v.tp >> 6) + 3) / 4);
-  const uint64_t waves = (uint64_t)v.pc * ((v.tp + v.tch - 1) / v.tch);
-  return (uint32_t)((waves + 3) / 4);
-}
-
 uint32_t stage_by(uint32_t k) { return k == 4 ? 2 : 8; }
 
 void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen) {
@@ -1302,19 +1131,6 @@ void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, 
   *gz = stage_slices(v, *gx * *gy, trlen);
 }
 
-hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
-                              uint32_t blocks, uint32_t kappa, hipStream_t s) {
-  const dim3 grid(blocks), block(256);
-  switch (kind) {
-    case 0: hipLaunchKernelGGL(k_count_integrands_batch, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 1: hipLaunchKernelGGL(k_count_points_batch<1>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 2: hipLaunchKernelGGL(k_count_points_batch<2>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 4: hipLaunchKernelGGL(k_count_points_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 8: hipLaunchKernelGGL(k_count_points_batch<8>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    default: hipLaunchKernelGGL(k_count_points_batch<16>, grid, block, 0, s, views, pre, nmem, kappa); break;
-  }
-  return hipGetLastError();
-}
 
 namespace {
 template <int R, int K>
