@@ -95,6 +95,58 @@ def cpu_baseline(w: dict, inp: dict, sweeps: int = 16, row_pixels: int = 128) ->
             "seconds": dt}
 
 
+SIGMAS_B = [0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 20.0]
+
+
+def quality_experiment(sweeps: int) -> dict:
+    """The criterion of Sec. 3.3 (Fig. 1c) and the versatility claim of
+    Sec. 3.5 on the GPU path: a 128x128 tile at 16 samples per pixel
+    (generator (1, 5), the one of Fig. 1a), optimised on 256 Heavisides with
+    each mutation and each direction, then judged by the blurred error of
+    held-out integrands (1024 other Heavisides; 1024 Gaussians) against the
+    random tile it started from."""
+    from paper_2105_12620_amd import bnlat
+
+    w = dict(n=16, g=(1, 5), width=128, height=128, t_heaviside=256, t_gauss=0, sigma=2.1, radius=3,
+             colour_k=2, seed=11, problem_id=0)
+    train = bnlat.draw_heavisides(11, 0, 256)
+    held_h = bnlat.draw_heavisides(12, 0, 1024)
+    held_g = bnlat.draw_gaussians(13, 0, 1024)
+    u0 = synthgen.offsets(128, 128, seed=14)
+
+    def judge(u):
+        with bnlat.create_problem(dict(w, t_heaviside=1024), held_h) as q:
+            q.init_offsets(u)
+            q.compute_errors()
+            qh = q.quality_metric(SIGMAS_B)
+        with bnlat.create_problem(dict(w, t_heaviside=1, t_gauss=1024), held_h[:1], gaussians=held_g) as q:
+            q.init_offsets(u)
+            q.compute_errors()
+            qg = q.quality_metric(SIGMAS_B, rows=bnlat.BN_ROWS_GAUSSIAN)
+        return qh, qg
+
+    base_h, base_g = judge(u0)
+    out = {"sigmas_b": SIGMAS_B, "sweeps": sweeps,
+           "random": {"heaviside": base_h.tolist(), "gaussian": base_g.tolist()}}
+    for move, mname in ((bnlat.BN_REDRAW, "redraw"), (bnlat.BN_SWAP, "swap")):
+        for objective, oname in ((1, "descend"), (-1, "ascend")):
+            with bnlat.create_problem(w, train, move=move, objective=objective) as p:
+                p.init_offsets(u0)
+                p.compute_errors()
+                e0 = p.energy()
+                t0 = time.perf_counter()
+                st = p.sweep(sweeps, stats=True)
+                e1 = p.energy()
+                dt = time.perf_counter() - t0
+                u = p.get_offsets()
+            qh, qg = judge(u)
+            out[f"{mname}_{oname}"] = {
+                "energy_before": e0, "energy_after": e1, "accepts": st["accepts"], "seconds": dt,
+                "heaviside": qh.tolist(), "gaussian": qg.tolist(),
+                "heaviside_ratio": (qh / base_h).tolist(), "gaussian_ratio": (qg / base_g).tolist()}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +158,9 @@ def main() -> int:
                     help="comma list of forms to run: fp32 (headline), bf16, swap, batched")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--experiment", choices=["quality"], default=None,
+                    help="instead of the benchmark, run the blur-criterion experiment and print its JSON line")
+    ap.add_argument("--sweeps", type=int, default=1000, help="sweeps per optimisation in --experiment")
     args = ap.parse_args()
     forms = set(args.forms.split(","))
     if args.gpus != 1:
@@ -117,6 +172,9 @@ def main() -> int:
     from paper_2105_12620_amd import bnlat
 
     torch.cuda.set_device(0)
+    if args.experiment == "quality":
+        print(json.dumps(quality_experiment(args.sweeps)), flush=True)
+        return 0
     w = dict(synthgen.WORKLOADS[args.workload])
     inp = synthgen.problem_inputs(w)
     stream = torch.cuda.Stream()

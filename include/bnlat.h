@@ -171,6 +171,12 @@ bn_status bn_energy(bn_problem p, double* out);
  * normalised Gaussian of standard deviation sigma periodised on the torus,
  * applied separably.  n <= 64.  Synchronises. */
 bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, double* out);
+/* The same criterion over one family of integrand rows (Sec. 3.5 evaluates
+ * low-frequency integrands on tiles optimised for Heavisides):
+ * BN_ROWS_ALL as above, BN_ROWS_HEAVISIDE the T Heaviside rows only,
+ * BN_ROWS_GAUSSIAN the T_G Gaussian rows only (BN_EINVAL when T_G = 0). */
+typedef enum { BN_ROWS_ALL = 0, BN_ROWS_HEAVISIDE = 1, BN_ROWS_GAUSSIAN = 2 } bn_rows;
+bn_status bn_quality_metric_family(bn_problem p, bn_rows rows, const double* sigmas, uint32_t n, double* out);
 
 /* Copy the offset tile to host_u: uint16 [H][W][2].  Synchronises. */
 bn_status bn_get_offsets(bn_problem p, uint16_t* host_u);

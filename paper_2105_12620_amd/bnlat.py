@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbnlat.so")
 BN_OK, BN_EINVAL, BN_ENOMEM, BN_EHIP, BN_ESTATE, BN_EUNSUPPORTED, BN_ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 BN_FP32, BN_BF16 = 0, 1
 BN_REDRAW, BN_SWAP = 0, 1
+BN_ROWS_ALL, BN_ROWS_HEAVISIDE, BN_ROWS_GAUSSIAN = 0, 1, 2
 
 
 class BnlatError(RuntimeError):
@@ -65,6 +66,7 @@ _SIGNATURES = {
     "bn_sweep": [_P, C.c_uint32, C.POINTER(SweepStats)],
     "bn_energy": [_P, C.POINTER(C.c_double)],
     "bn_quality_metric": [_P, _P, C.c_uint32, _P],
+    "bn_quality_metric_family": [_P, C.c_int, _P, C.c_uint32, _P],
     "bn_get_offsets": [_P, _P],
     "bn_get_counts": [_P, _P],
     "bn_get_errors": [_P, _P],
@@ -259,10 +261,14 @@ class Problem:
         _call("bn_energy", self.handle, C.byref(out))
         return out.value
 
-    def quality_metric(self, sigmas) -> np.ndarray:
+    def quality_metric(self, sigmas, rows: int = 0) -> np.ndarray:
+        """Blur criterion per sigma over all rows (0), Heaviside rows (1) or Gaussian rows (2)."""
         s = np.ascontiguousarray(sigmas, dtype=np.float64)
         out = np.zeros_like(s)
-        _call("bn_quality_metric", self.handle, _ptr(s), s.shape[0], _ptr(out))
+        if rows:
+            _call("bn_quality_metric_family", self.handle, rows, _ptr(s), s.shape[0], _ptr(out))
+        else:
+            _call("bn_quality_metric", self.handle, _ptr(s), s.shape[0], _ptr(out))
         return out
 
     def get_offsets(self) -> np.ndarray:

@@ -587,6 +587,8 @@ bn_status setup_swap(bn_problem p) {
   HIPCHK(hipMemcpyAsync(dcls_d, dcls.data(), dcls.size() * 4, hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipMemsetAsync(sv.order, 0, (size_t)M * 4, p->stream));
   HIPCHK(hipMemsetAsync(sv.nsel, 0, 4, p->stream));
+  HIPCHK(hipMemsetAsync(sv.xs, 0, (size_t)p->v.ncls * M * 8, p->stream));
+  HIPCHK(hipMemsetAsync(sv.d2, 0, (size_t)(M / 2) * 8, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return BN_OK;
 }
@@ -1169,7 +1171,14 @@ bn_status bn_energy(bn_problem p, double* out) {
 }
 
 bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, double* out) {
+  return bn_quality_metric_family(p, BN_ROWS_ALL, sigmas, n, out);
+}
+
+bn_status bn_quality_metric_family(bn_problem p, bn_rows rows, const double* sigmas, uint32_t n, double* out) {
   if (!p || (n && (!sigmas || !out))) return fail(BN_EINVAL, "NULL argument");
+  if (rows != BN_ROWS_ALL && rows != BN_ROWS_HEAVISIDE && rows != BN_ROWS_GAUSSIAN)
+    return fail(BN_EINVAL, "unknown row family");
+  if (rows == BN_ROWS_GAUSSIAN && !p->v.tg) return fail(BN_EINVAL, "the problem has no Gaussian integrands");
   if (n > 64) return fail(BN_EINVAL, "at most 64 blur sizes");
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
   for (uint32_t i = 0; i < n; ++i)
@@ -1214,7 +1223,7 @@ bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, doub
     const float* fields[2] = {p->v.err, p->v.gerr};
     const uint32_t pitches[2] = {p->v.tp, p->v.tgp}, valids[2] = {p->v.t, p->v.tg};
     for (int f = 0; f < 2 && e == hipSuccess; ++f) {
-      if (!pitches[f]) continue;
+      if (!pitches[f] || (rows == BN_ROWS_HEAVISIDE && f == 1) || (rows == BN_ROWS_GAUSSIAN && f == 0)) continue;
       uint32_t np = 0;
       e = launch_blur(p->v, fields[f], pitches[f], valids[f], kx, (uint32_t)hkx.size(), dx, ky,
                       (uint32_t)hky.size(), dy, tmp, part, &np, p->stream);
@@ -1226,7 +1235,8 @@ bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, doub
       release();
       return fail(BN_EHIP, "quality metric: %s", hipGetErrorString(e));
     }
-    out[i] = std::sqrt(acc / ((double)P * (p->v.t + p->v.tg)));
+    const uint32_t count = rows == BN_ROWS_HEAVISIDE ? p->v.t : rows == BN_ROWS_GAUSSIAN ? p->v.tg : p->v.t + p->v.tg;
+    out[i] = std::sqrt(acc / ((double)P * count));
   }
   release();
   return BN_OK;

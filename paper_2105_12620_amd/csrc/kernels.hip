@@ -746,10 +746,12 @@ __global__ __launch_bounds__(256) void k_blur_y_sq(DevView v, uint32_t pitch, ui
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = wave_id();
   const uint32_t nch = pitch >> 6;
-  const uint32_t p = wave / nch, ch = wave - p * nch;
+  // waves walk down one column (and 64-integrand chunk) at a time, so the
+  // waves in flight share the column's taps in L2
+  const uint32_t y = wave % v.h, rest = wave / v.h;
+  const uint32_t x = rest / nch, ch = rest - x * nch;
   double sq = 0.0;
-  if (p < v.w * v.h) {
-    const uint32_t y = p / v.w, x = p - y * v.w;
+  if (x < v.w) {
     const uint32_t t = ch * 64 + lane;
     float acc = 0.0f;
     for (uint32_t i = 0; i < nk; ++i) {

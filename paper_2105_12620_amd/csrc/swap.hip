@@ -13,9 +13,11 @@
 // summed in FP64 in increasing d exactly as for the redraw mutation.
 //
 // During a swap sweep the counts live in a pixel-major copy cpm [P][tp], so a
-// wave reads a neighbour's 512 integrands as one 1 KiB run.
+// wave reads a neighbour's 256 integrands as one 512-byte run.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "bnlat_dev.h"
 #include "device_common.h"
@@ -74,18 +76,28 @@ __global__ __launch_bounds__(256) void k_swap_select(DevView v, SwapView sv, uin
   if (in && base + rank < sv.m) sv.order[base + rank] = j;
 }
 
-// One wave per couple member (list slot j): lanes hold 8 integrands each of
-// dc = c_partner - c_own and take the int16 dot products with the 8 counts
-// of every window neighbour of the member.  Per-lane partial sums of one
-// 512-integrand chunk stay below 2^31 (8 offsets x 8 integrands x N^2 with
-// N <= 4096) and are widened to 64 bits after each chunk.
+// One wave per couple member (list slot j) and integrand slice: lanes hold 4
+// integrands each of dc = c_partner - c_own and take the int16 dot products
+// with the 4 counts of every window neighbour of the member (one 512-byte run
+// per neighbour and 256 integrands).  Per-lane partial sums of one chunk stay
+// below 2^31 (at most 12 offsets per class x 4 integrands x N^2, N <= 4096)
+// and are widened to 64 bits after each chunk; slices meet in exact int64
+// atomics.
+//
+// Launch order: hardware workgroup i runs on XCD i mod 8, so XCD x is given
+// the contiguous run of member blocks [x nbx, (x + 1) nbx) and walks it once
+// per integrand slice; its L2 then holds the window rows of one band of the
+// tile for one slice.
 template <int R>
-__global__ __launch_bounds__(256) void k_swap_eval(DevView v, SwapView sv, uint32_t kappa) {
+__global__ __launch_bounds__(256) void k_swap_eval(DevView v, SwapView sv, uint32_t kappa, uint32_t nbx,
+                                                   uint32_t nz, uint32_t tslice) {
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t slot = wave_id();
-  if (slot >= sv.m) return;
+  const uint32_t xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const uint32_t z = q / nbx, mb = xcd * nbx + (q - z * nbx);
+  const uint32_t slot = mb * 4 + (threadIdx.x >> 6);
+  if (z >= nz || slot >= sv.m) return;
   const uint32_t j = __builtin_amdgcn_readfirstlane(sv.order[slot]);
   if (j >= sv.m) return;
   const uint32_t mask = swap_mask(v, kappa);
@@ -102,16 +114,17 @@ __global__ __launch_bounds__(256) void k_swap_eval(DevView v, SwapView sv, uint3
 #pragma unroll
   for (int c = 0; c < NCLS; ++c) zd[c] = 0;
   long long dd = 0;
-  for (uint32_t t0 = 0; t0 < v.tp; t0 += 512) {
-    const uint32_t t = t0 + 8 * lane;
-    if (t >= v.tp) continue;
-    const uint4 ca = *(const uint4*)(sv.cpm + (size_t)a * v.tp + t);
-    const uint4 cb = *(const uint4*)(sv.cpm + (size_t)b * v.tp + t);
-    const uint32_t aw[4] = {ca.x, ca.y, ca.z, ca.w}, bw[4] = {cb.x, cb.y, cb.z, cb.w};
-    uint32_t dl[4];
+  const uint32_t t_begin = z * tslice, t_end = min(t_begin + tslice, v.tp);
+  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 256) {
+    const uint32_t t = t0 + 4 * lane;
+    if (t >= t_end) continue;
+    const uint2 ca = *(const uint2*)(sv.cpm + (size_t)a * v.tp + t);
+    const uint2 cb = *(const uint2*)(sv.cpm + (size_t)b * v.tp + t);
+    const uint32_t aw[2] = {ca.x, ca.y}, bw[2] = {cb.x, cb.y};
+    uint32_t dl[2];
     int sq = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 2; ++k) {
       const int d0 = (int)(bw[k] & 0xFFFFu) - (int)(aw[k] & 0xFFFFu);
       const int d1 = (int)(bw[k] >> 16) - (int)(aw[k] >> 16);
       dl[k] = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
@@ -123,13 +136,11 @@ __global__ __launch_bounds__(256) void k_swap_eval(DevView v, SwapView sv, uint3
     for (int c = 0; c < NCLS; ++c) part[c] = 0;
 #pragma unroll
     for (int mm = 0; mm < W.M; ++mm) {
-      const uint32_t q = rowq[W.oy[mm] + R] + colq[W.ox[mm] + R];
-      const uint4 cq = *(const uint4*)(sv.cpm + (size_t)q * v.tp + t);
+      const uint32_t qq = rowq[W.oy[mm] + R] + colq[W.ox[mm] + R];
+      const uint2 cq = *(const uint2*)(sv.cpm + (size_t)qq * v.tp + t);
       int acc = part[W.cls[mm]];
       acc = dot2(dl[0], cq.x, acc);
       acc = dot2(dl[1], cq.y, acc);
-      acc = dot2(dl[2], cq.z, acc);
-      acc = dot2(dl[3], cq.w, acc);
       part[W.cls[mm]] = acc;
     }
 #pragma unroll
@@ -140,15 +151,16 @@ __global__ __launch_bounds__(256) void k_swap_eval(DevView v, SwapView sv, uint3
     long long s = zd[c];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) sv.xs[(size_t)c * sv.m + j] = -2 * s;
+    if (lane == 0 && s) atomicAdd((unsigned long long*)&sv.xs[(size_t)c * sv.m + j], (unsigned long long)(-2 * s));
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) dd += __shfl_xor(dd, off);
-  if (lane == 0 && !(j & 1u)) sv.d2[j >> 1] = dd;
+  if (lane == 0 && !(j & 1u) && dd) atomicAdd((unsigned long long*)&sv.d2[j >> 1], (unsigned long long)dd);
 }
 
 // One thread per couple: add the two members' class sums and the pair
-// correction, take the FP64 weighted sum in increasing d and decide.
+// correction, take the FP64 weighted sum in increasing d and decide; the sums
+// are cleared for the next pass.
 __global__ __launch_bounds__(256) void k_swap_finish(DevView v, SwapView sv, uint32_t kappa) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t half = sv.m >> 1;
@@ -172,10 +184,14 @@ __global__ __launch_bounds__(256) void k_swap_finish(DevView v, SwapView sv, uin
     }
   }
   const long long d2 = sv.d2[i];
+  sv.d2[i] = 0;
   double acc = 0.0;
   for (uint32_t c = 0; c < v.ncls; ++c) {
     const int ci = (int)c;
-    long long x = sv.xs[(size_t)c * sv.m + 2 * i] + sv.xs[(size_t)c * sv.m + 2 * i + 1];
+    long long* xp = sv.xs + (size_t)c * sv.m + 2 * i;
+    long long x = xp[0] + xp[1];
+    xp[0] = 0;
+    xp[1] = 0;
     x += 2 * d2 * (long long)((l0 == ci) + (l1 == ci) + (l2 == ci) + (l3 == ci));
     acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)x));
   }
@@ -229,14 +245,18 @@ hipError_t launch_swap_select(const DevView& v, const SwapView& sv, uint32_t kap
 }
 
 hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
-  const dim3 grid((sv.m + 3) / 4), block(256);
+  // integrand slices of 256 (at most 4), member blocks of 4 waves split over 8 XCDs
+  const uint32_t nz = std::min<uint32_t>(4, (v.tp + 255) / 256);
+  const uint32_t tslice = ((v.tp + nz - 1) / nz + 255) / 256 * 256;
+  const uint32_t nblk = (sv.m + 3) / 4, nbx = (nblk + 7) / 8;
+  const dim3 grid(8 * nbx * nz), block(256);
   switch (v.radius) {
-    case 1: hipLaunchKernelGGL(k_swap_eval<1>, grid, block, 0, s, v, sv, kappa); break;
-    case 2: hipLaunchKernelGGL(k_swap_eval<2>, grid, block, 0, s, v, sv, kappa); break;
-    case 3: hipLaunchKernelGGL(k_swap_eval<3>, grid, block, 0, s, v, sv, kappa); break;
-    case 4: hipLaunchKernelGGL(k_swap_eval<4>, grid, block, 0, s, v, sv, kappa); break;
-    case 5: hipLaunchKernelGGL(k_swap_eval<5>, grid, block, 0, s, v, sv, kappa); break;
-    case 6: hipLaunchKernelGGL(k_swap_eval<6>, grid, block, 0, s, v, sv, kappa); break;
+    case 1: hipLaunchKernelGGL(k_swap_eval<1>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
+    case 2: hipLaunchKernelGGL(k_swap_eval<2>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
+    case 3: hipLaunchKernelGGL(k_swap_eval<3>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
+    case 4: hipLaunchKernelGGL(k_swap_eval<4>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
+    case 5: hipLaunchKernelGGL(k_swap_eval<5>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
+    case 6: hipLaunchKernelGGL(k_swap_eval<6>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
     default: return hipErrorInvalidValue;
   }
   const uint32_t half = sv.m >> 1;

@@ -21,8 +21,8 @@ struct SwapView {
   uint16_t* cpm;          // [P][tp] hit counts, pixel-major (the working copy during swap sweeps)
   uint32_t* order;        // [M] the pass's list slots in selection order
   uint32_t* nsel;         // [1] selection counter
-  long long* xs;          // [ncls][M] integer class sums of each couple member's move
-  long long* d2;          // [M/2] sum_t (c_a,t - c_b,t)^2 of each couple
+  long long* xs;          // [ncls][M] integer class sums of each couple member's move (zero between passes)
+  long long* d2;          // [M/2] sum_t (c_a,t - c_b,t)^2 of each couple (zero between passes)
   const int32_t* dcls;    // [2 r^2 + 1] class index of a squared distance (-1: none)
   uint32_t m;             // list positions per pass
 };

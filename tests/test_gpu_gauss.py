@@ -97,3 +97,27 @@ def test_drawn_gaussians_used_when_none_given():
     with bnlat.create_problem(w, None) as p:
         _, _, g, _ = p.get_integrands(gaussians=True)
     np.testing.assert_array_equal(g, bnlat.draw_gaussians(w["seed"], 0, w["t_gauss"]))
+
+
+def test_quality_metric_per_family():
+    """The criterion over Heaviside rows only and Gaussian rows only, against
+    the oracle's criterion of each family's error field; the all-rows value
+    is their count-weighted root mean square."""
+    w = MIX["mix_n64"]
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.initial_state(ref, inp["offsets"])
+    e = osw.errors(ref, st)
+    T, TG = w["t_heaviside"], w["t_gauss"]
+    sig = (0.5, 2.0, 8.0)
+    with gpu_problem(w, inp) as p:
+        qh = p.quality_metric(sig, rows=bnlat.BN_ROWS_HEAVISIDE)
+        qg = p.quality_metric(sig, rows=bnlat.BN_ROWS_GAUSSIAN)
+        qa = p.quality_metric(sig)
+    np.testing.assert_allclose(qh, quality.quality(e[..., :T], sig), rtol=1e-5)
+    np.testing.assert_allclose(qg, quality.quality(e[..., T:], sig), rtol=1e-5)
+    np.testing.assert_allclose(qa, np.sqrt((T * qh ** 2 + TG * qg ** 2) / (T + TG)), rtol=1e-6)
+    wh = workload(n=16, g=(1, 7), width=8, height=8, t_heaviside=5, radius=2)
+    with gpu_problem(wh, synthgen.problem_inputs(wh)) as q:
+        with pytest.raises(bnlat.BnlatError):
+            q.quality_metric(sig, rows=bnlat.BN_ROWS_GAUSSIAN)
