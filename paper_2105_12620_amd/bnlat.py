@@ -76,6 +76,7 @@ _SIGNATURES = {
     "bn_get_sweep_index": [_P, C.POINTER(C.c_uint64)],
     "bn_set_sweep_index": [_P, C.c_uint64],
     "bn_set_profiling": [_P, C.c_int],
+    "bn_set_recount_blocks": [_P, C.c_uint32],
     "bn_get_profile": [_P, C.POINTER(ProfileStats)],
     "bn_phase_propose": [_P, C.c_uint32],
     "bn_phase_evaluate": [_P, C.c_uint32],
@@ -320,6 +321,9 @@ class Problem:
 
     def set_profiling(self, enable: bool):
         _call("bn_set_profiling", self.handle, 1 if enable else 0)
+
+    def set_recount_blocks(self, blocks: int):
+        _call("bn_set_recount_blocks", self.handle, blocks)
 
     def get_profile(self) -> dict:
         st = ProfileStats()

@@ -995,6 +995,16 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   v.ncls = (uint32_t)p->cls_d.size();
   v.tch = std::min<uint32_t>(256, v.tp);
   v.slice_target = 512;
+  // The BF16 colour phases share the CUs with the sweep-wide recount; capping
+  // the recount at six workgroups per CU (24 of 32 wave slots) measured 13 %
+  // faster sweeps for that form, while the FP32 form is fastest uncapped.
+  v.count_cap = 0;
+  if (cfg->precision == BN_BF16) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      v.count_cap = 6u * (uint32_t)cus;
+  }
   v.tg = cfg->t_gauss;
   v.tgp = round_up(v.tg, 64);
   const size_t P = (size_t)v.w * v.h;
@@ -1354,6 +1364,21 @@ bn_status bn_get_profile(bn_problem p, bn_profile_stats* out) {
   HIPCHK(total(p->prof_commit, &out->commit_ms));
   out->recount_launches = p->prof_recount.size() / 2;
   out->phases = p->prof_eval.size() / 2;
+  return BN_OK;
+}
+
+bn_status bn_set_recount_blocks(bn_problem p, uint32_t blocks) {
+  if (!p) return fail(BN_EINVAL, "NULL problem");
+  bn_status s = sync(p);
+  if (s != BN_OK) return s;
+  if (p->aux) HIPCHK(hipStreamSynchronize(p->aux));
+  p->v.count_cap = blocks;
+  // captured graphs hold the old launch shape
+  if (p->pair_exec) (void)hipGraphExecDestroy(p->pair_exec);
+  if (p->pair_graph) (void)hipGraphDestroy(p->pair_graph);
+  p->pair_exec = nullptr;
+  p->pair_graph = nullptr;
+  p->pair_failed = false;
   return BN_OK;
 }
 

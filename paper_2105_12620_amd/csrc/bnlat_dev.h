@@ -46,6 +46,7 @@ struct DevView {
   uint32_t mfma;             // 1: BF16 matrix-core evaluation of the colour phases
   uint32_t tch;              // integrands per wave in the counting kernels (launch shape)
   uint32_t slice_target;     // workgroups the staged energy-change launch aims for
+  uint32_t count_cap;        // workgroup cap of the sweep-wide recount launch (0: none)
   // Gaussian integrands (tgp = 0 when there are none)
   uint32_t tg, tgp;          // count, padded to 64
   const double2* gmu;        // [tgp] centres

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "bnlat_dev.h"
 #include "device_common.h"
 
@@ -119,10 +121,15 @@ __device__ __forceinline__ void count_points_body(const DevView& v, const int2* 
   }
 }
 
+// The launch may have fewer workgroups than the vblocks its work needs (the
+// sweep-wide recount of the overlapped schedule is capped so that it leaves
+// room on every CU for the colour phases running beside it): workgroups then
+// stride over the virtual blocks.
 template <int PPL, int MODE>
 __global__ __launch_bounds__(256) void k_count_points(DevView v, const int2* __restrict__ ihp,
-                                                      uint32_t kappa, uint32_t m, uint32_t tch) {
-  count_points_body<PPL, MODE>(v, ihp, kappa, m, tch, blockIdx.x);
+                                                      uint32_t kappa, uint32_t m, uint32_t tch,
+                                                      uint32_t vblocks) {
+  for (uint32_t b = blockIdx.x; b < vblocks; b += gridDim.x) count_points_body<PPL, MODE>(v, ihp, kappa, m, tch, b);
 }
 
 template <int PPL>
@@ -180,13 +187,15 @@ hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
   }
   const uint32_t tch = v.tch;
   const uint64_t waves = (uint64_t)m * ((v.tp + tch - 1) / tch);
-  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+  const uint32_t vb = (uint32_t)((waves + 3) / 4);
+  const uint32_t nb = (MODE == MODE_SWEEP && v.count_cap) ? std::min(vb, v.count_cap) : vb;
+  const dim3 grid(nb), block(256);
   switch (v.n) {
-    case 64: hipLaunchKernelGGL((k_count_points<1, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
-    case 128: hipLaunchKernelGGL((k_count_points<2, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
-    case 256: hipLaunchKernelGGL((k_count_points<4, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
-    case 512: hipLaunchKernelGGL((k_count_points<8, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
-    default: hipLaunchKernelGGL((k_count_points<16, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch); break;
+    case 64: hipLaunchKernelGGL((k_count_points<1, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
+    case 128: hipLaunchKernelGGL((k_count_points<2, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
+    case 256: hipLaunchKernelGGL((k_count_points<4, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
+    case 512: hipLaunchKernelGGL((k_count_points<8, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
+    default: hipLaunchKernelGGL((k_count_points<16, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
   }
   return hipGetLastError();
 }

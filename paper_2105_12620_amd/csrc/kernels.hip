@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) void k_delta_finish_batch(const DevView* __res
 // ---------------------------------------------- energy change on matrix cores
 //
 // BF16 form of the neighbourhood Gram products (K = 2 colour classes per
-// axis).  A block holds 8 class rows x 16 class pixels; wave w owns class row
+// axis).  A block holds BYC class rows x 16 class pixels; wave w owns class row
 // w, i.e. the 16 rows of an MFMA tile.  For every 16-integrand slice the
 // counts of the block's window region are staged in LDS as BF16 (integer
 // counts up to 256 are exact in BF16), together with the moved pixels'
@@ -322,9 +322,9 @@ __global__ __launch_bounds__(256) void k_delta_finish_batch(const DevView* __res
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int R>
+template <int R, int BYC_>
 struct MfmaGeom {
-  static constexpr int BYC = 8;                       // class rows (waves) per block
+  static constexpr int BYC = BYC_;                    // class rows (waves) per block
   static constexpr int BXC = 16;                      // class pixels per row (MFMA rows)
   static constexpr int RROWS = 2 * (BYC - 1) + 1 + 2 * R;
   static constexpr int RUSED = 2 * (BXC - 1) + 1 + 2 * R;   // region columns read
@@ -351,11 +351,11 @@ __device__ inline uint32_t bf16_pair(int x, int y) {
   return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
 
-template <int R>
-__global__ __launch_bounds__(512) void k_delta_mfma(DevView v, uint32_t kappa, uint32_t trlen,
+template <int R, int BYC>
+__global__ __launch_bounds__(64 * BYC) void k_delta_mfma(DevView v, uint32_t kappa, uint32_t trlen,
                                                     long long* __restrict__ xsum,
                                                     uint32_t* __restrict__ unsure) {
-  using G = MfmaGeom<R>;
+  using G = MfmaGeom<R, BYC>;
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
   extern __shared__ uint2 lds8[];
@@ -961,12 +961,14 @@ hipError_t launch_init_offsets(const DevView& v, hipStream_t s) {
 
 template <int R>
 hipError_t mfma_launch(const DevView& v, uint32_t kappa, hipStream_t s) {
-  using G = MfmaGeom<R>;
+  // four class rows (one wave per SIMD) per block: a block then fits beside
+  // the waves of a concurrently running counting launch
+  using G = MfmaGeom<R, 4>;
   const uint32_t bx = (v.cw + G::BXC - 1) / G::BXC, by = (v.ch + G::BYC - 1) / G::BYC;
   uint32_t trlen = 0;
   const uint32_t ns = stage_slices(v, bx * by, &trlen);
   const size_t lds = (size_t)G::LDS_BYTES;
-  hipLaunchKernelGGL((k_delta_mfma<R>), dim3(bx, by, ns), dim3(64 * G::BYC), lds, s, v, kappa, trlen,
+  hipLaunchKernelGGL((k_delta_mfma<R, G::BYC>), dim3(bx, by, ns), dim3(64 * G::BYC), lds, s, v, kappa, trlen,
                      v.xpart, v.unsure);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

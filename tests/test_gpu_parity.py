@@ -230,3 +230,23 @@ def test_profiled_and_mixed_schedules_agree():
         p.sweep(1)
         np.testing.assert_array_equal(p.get_offsets(), st.u)
         assert p.get_sweep_index() == 5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_recount_cap_does_not_change_results(precision):
+    """The sweep-wide recount with a workgroup cap (workgroups striding over
+    the work) gives the oracle's trajectory for any cap, before and after the
+    captured graph is rebuilt."""
+    w = dict(EDGE["n256_r4"], precision=precision)
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.run(ref, osw.initial_state(ref, inp["offsets"]), 6)
+    with gpu_problem(w, inp) as p:
+        p.set_recount_blocks(3)
+        p.sweep(2)
+        p.set_recount_blocks(0)
+        p.sweep(2)
+        p.set_recount_blocks(7)
+        p.sweep(2)
+        np.testing.assert_array_equal(p.get_offsets(), st.u)
+        np.testing.assert_array_equal(p.get_counts().reshape(st.c.shape), st.c)
