@@ -574,9 +574,8 @@ bn_status setup_swap(bn_problem p) {
   int32_t* dcls_d;
   bn_status s;
   if ((s = p->alloc(&perm_d, P)) != BN_OK || (s = p->alloc(&pinv_d, P)) != BN_OK ||
-      (s = p->alloc(&dcls_d, dmax + 1)) != BN_OK || (s = p->alloc(&sv.cpm, (size_t)P * p->v.tp)) != BN_OK ||
-      (s = p->alloc(&sv.order, M)) != BN_OK || (s = p->alloc(&sv.nsel, 1)) != BN_OK ||
-      (s = p->alloc(&sv.xs, (size_t)p->v.ncls * M)) != BN_OK || (s = p->alloc(&sv.d2, M / 2)) != BN_OK)
+      (s = p->alloc(&dcls_d, dmax + 1)) != BN_OK || (s = p->alloc(&sv.xs, (size_t)p->v.ncls * M)) != BN_OK ||
+      (s = p->alloc(&sv.d2, M / 2)) != BN_OK)
     return s;
   sv.perm = perm_d;
   sv.pinv = pinv_d;
@@ -585,20 +584,13 @@ bn_status setup_swap(bn_problem p) {
   HIPCHK(hipMemcpyAsync(perm_d, perm.data(), (size_t)P * 4, hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipMemcpyAsync(pinv_d, pinv.data(), (size_t)P * 4, hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipMemcpyAsync(dcls_d, dcls.data(), dcls.size() * 4, hipMemcpyHostToDevice, p->stream));
-  HIPCHK(hipMemsetAsync(sv.order, 0, (size_t)M * 4, p->stream));
-  HIPCHK(hipMemsetAsync(sv.nsel, 0, 4, p->stream));
   HIPCHK(hipMemsetAsync(sv.xs, 0, (size_t)p->v.ncls * M * 8, p->stream));
   HIPCHK(hipMemsetAsync(sv.d2, 0, (size_t)(M / 2) * 8, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   return BN_OK;
 }
 
-// One swap pass on the pixel-major counts, in three steps.
-bn_status swap_select(bn_problem p, uint32_t kappa) {
-  HIPCHK(launch_swap_select(p->v, p->sv, kappa, p->stream));
-  return BN_OK;
-}
-
+// One swap pass: evaluate and decide every couple, then exchange.
 bn_status swap_evaluate(bn_problem p, uint32_t kappa) {
   HIPCHK(launch_swap_evaluate(p->v, p->sv, kappa, p->stream));
   return BN_OK;
@@ -613,7 +605,7 @@ bn_status record_swap_sweep(bn_problem p) {
   bn_status s;
   for (uint32_t kappa = 0; kappa < p->v.k * p->v.k; ++kappa) {
     ProfMark me(p, &p->prof_eval, p->stream);
-    if ((s = swap_select(p, kappa)) != BN_OK || (s = swap_evaluate(p, kappa)) != BN_OK) return s;
+    if ((s = swap_evaluate(p, kappa)) != BN_OK) return s;
     if ((s = me.end()) != BN_OK) return s;
     ProfMark mc(p, &p->prof_commit, p->stream);
     if ((s = swap_commit(p)) != BN_OK) return s;
@@ -650,12 +642,10 @@ bn_status build_swap_graph(bn_problem p) {
   return BN_OK;
 }
 
-// k swap sweeps: counts to the pixel-major copy, K^2 passes per sweep
-// (graph-replayed unless profiling), counts back to the tiled layout.
+// k swap sweeps of K^2 passes (graph-replayed unless profiling).
 bn_status swap_sweeps(bn_problem p, uint32_t k) {
   if (!k) return BN_OK;
   bn_status s;
-  HIPCHK(launch_to_pixel_major(p->v, p->sv, p->stream));
   if (!p->profiling && (s = build_swap_graph(p)) != BN_OK) return s;
   for (uint32_t i = 0; i < k; ++i) {
     if (p->swap_exec && !p->profiling) {
@@ -664,7 +654,6 @@ bn_status swap_sweeps(bn_problem p, uint32_t k) {
       return s;
     }
   }
-  HIPCHK(launch_from_pixel_major(p->v, p->sv, p->stream));
   return BN_OK;
 }
 
@@ -1407,10 +1396,7 @@ bn_status bn_phase_propose(bn_problem p, uint32_t kappa) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
   if (kappa >= p->v.k * p->v.k) return fail(BN_EINVAL, "class %u out of range", kappa);
-  if (p->cfg.move == BN_SWAP) {
-    HIPCHK(launch_to_pixel_major(p->v, p->sv, p->stream));
-    return swap_select(p, kappa);
-  }
+  if (p->cfg.move == BN_SWAP) return BN_OK;   // couples are listed by the evaluation
   HIPCHK(launch_count(p->v, MODE_CLASS, kappa, p->v.pc, p->stream));
   HIPCHK(launch_gauss_est(p->v, MODE_CLASS, p->v.pc, p->stream));
   return BN_OK;
@@ -1433,7 +1419,6 @@ bn_status bn_phase_commit(bn_problem p, uint32_t kappa) {
   if (p->cfg.move == BN_SWAP) {
     bn_status s = swap_commit(p);
     if (s != BN_OK) return s;
-    HIPCHK(launch_from_pixel_major(p->v, p->sv, p->stream));
     p->errors_valid = false;
     return BN_OK;
   }

@@ -11,9 +11,6 @@
 // terms |d| (c_b^2 - c_a^2) of the two single moves cancel).  Then
 //   dE = (2 / N^2) sum_d w(d) X_d,
 // summed in FP64 in increasing d exactly as for the redraw mutation.
-//
-// During a swap sweep the counts live in a pixel-major copy cpm [P][tp], so a
-// wave reads a neighbour's 256 integrands as one 512-byte run.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -32,130 +29,164 @@ __device__ inline uint32_t swap_mask(const DevView& v, uint32_t kappa) {
   return philox_w01(kappa, sweep, v.problem, S_SWAP, v.seed_lo, v.seed_hi).x & (v.w * v.h - 1);
 }
 
-// One thread per 16-byte integrand tile of a pixel.
-__global__ __launch_bounds__(256) void k_to_pixel_major(DevView v, SwapView sv) {
-  const uint32_t P = v.w * v.h, tiles = v.tp >> 3;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)P * tiles) return;
-  const uint32_t tt = (uint32_t)(i / P), p = (uint32_t)(i - (size_t)tt * P);
-  *(uint4*)(sv.cpm + (size_t)p * v.tp + 8 * tt) = *(const uint4*)(v.cnt + i * 8);
-}
+// LDS-staged member evaluation.  A workgroup owns a 32 x 6 block of tile
+// pixels; its pass members (pixels whose scrambled list position falls in the
+// pass) are listed in LDS.  For 32 integrands at a time the counts of the
+// block plus its window halo are staged in LDS (region RH x RW, 16 words of
+// two int16 counts per pixel), and every member is served by a group of 16
+// lanes, lane k holding integrand pair k of dc = c_partner - c_own (partner
+// counts read from HBM, own counts from LDS).  Per window offset a group reads
+// 16 consecutive words of the neighbour and takes one v_dot2 per lane.
+// Integrand slices of the tile run in separate workgroups (grid z) and meet
+// in exact int64 atomics; per-lane int32 partial sums stay below 2^31 because
+// the host bounds a slice to S stages with S * 24 N^2 < 2^31 (at most 12
+// offsets per distance class, 2 integrands per lane per stage).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_from_pixel_major(DevView v, SwapView sv) {
-  const uint32_t P = v.w * v.h, tiles = v.tp >> 3;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)P * tiles) return;
-  const uint32_t tt = (uint32_t)(i / P), p = (uint32_t)(i - (size_t)tt * P);
-  *(uint4*)(v.cnt + i * 8) = *(const uint4*)(sv.cpm + (size_t)p * v.tp + 8 * tt);
-}
-
-__global__ void k_swap_reset(SwapView sv) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *sv.nsel = 0;
-}
-
-// Every pixel p of the tile tests whether its scrambled list position
-// pinv[p ^ mask] falls in the pass; members are appended (wave by wave, in
-// roughly raster order) to order[] as list slots j = L - kappa M.
-__global__ __launch_bounds__(256) void k_swap_select(DevView v, SwapView sv, uint32_t kappa) {
-  const uint32_t P = v.w * v.h;
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t mask = swap_mask(v, kappa);
-  bool in = false;
-  uint32_t j = 0;
-  if (p < P) {
-    const uint32_t L = sv.pinv[p ^ mask];
-    in = L / sv.m == kappa;
-    j = L - kappa * sv.m;
-  }
-  const unsigned long long bal = __ballot(in);
-  const uint32_t rank = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-  uint32_t base = 0;
-  if (lane == 0 && bal) base = atomicAdd(sv.nsel, (uint32_t)__popcll(bal));
-  base = __shfl(base, 0);
-  if (in && base + rank < sv.m) sv.order[base + rank] = j;
-}
-
-// One wave per couple member (list slot j) and integrand slice: lanes hold 4
-// integrands each of dc = c_partner - c_own and take the int16 dot products
-// with the 4 counts of every window neighbour of the member (one 512-byte run
-// per neighbour and 256 integrands).  Per-lane partial sums of one chunk stay
-// below 2^31 (at most 12 offsets per class x 4 integrands x N^2, N <= 4096)
-// and are widened to 64 bits after each chunk; slices meet in exact int64
-// atomics.
-//
-// Launch order: hardware workgroup i runs on XCD i mod 8, so XCD x is given
-// the contiguous run of member blocks [x nbx, (x + 1) nbx) and walks it once
-// per integrand slice; its L2 then holds the window rows of one band of the
-// tile for one slice.
 template <int R>
-__global__ __launch_bounds__(256) void k_swap_eval(DevView v, SwapView sv, uint32_t kappa, uint32_t nbx,
-                                                   uint32_t nz, uint32_t tslice) {
+struct SwapGeom {
+  static constexpr int BW = 32, BH = 6;          // tile pixels per workgroup
+  static constexpr int RW = BW + 2 * R, RH = BH + 2 * R;
+  static constexpr int RA = RW * RH;             // region pixels
+  static constexpr int WPP = 16;                 // words per pixel and stage (32 integrands)
+  static constexpr int NT = 512;                 // threads
+  static constexpr int GROUPS = NT / WPP;        // 32 member groups
+  static constexpr int SLOTS = 2;                // members per group and round
+  static constexpr int CAP = GROUPS * SLOTS;     // members per round
+  static constexpr int ITEMS = RA * 4;           // 16-byte staging loads per stage
+  static constexpr int ITER = (ITEMS + NT - 1) / NT;
+  static constexpr int NWV = (BW * BH + 63) / 64; // waves that test membership
+  static constexpr int LDS_WORDS = RA * WPP + 3 * BW * BH + NWV;
+};
+
+template <int R>
+__global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v, SwapView sv, uint32_t kappa,
+                                                                    uint32_t slen) {
+  using G = SwapGeom<R>;
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
-  const uint32_t z = q / nbx, mb = xcd * nbx + (q - z * nbx);
-  const uint32_t slot = mb * 4 + (threadIdx.x >> 6);
-  if (z >= nz || slot >= sv.m) return;
-  const uint32_t j = __builtin_amdgcn_readfirstlane(sv.order[slot]);
-  if (j >= sv.m) return;
+  extern __shared__ uint32_t lds[];
+  uint32_t* reg = lds;                             // [RA][16]
+  uint32_t* mpos = lds + G::RA * G::WPP;           // [BW*BH] region pixel of each member
+  uint32_t* mj = mpos + G::BW * G::BH;             // [BW*BH] list slot
+  uint32_t* mb = mj + G::BW * G::BH;               // [BW*BH] partner pixel
+  uint32_t* wcnt = mb + G::BW * G::BH;             // [NWV] members per wave
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t P = v.w * v.h;
   const uint32_t mask = swap_mask(v, kappa);
-  const uint32_t L = kappa * sv.m + j;
-  const uint32_t a = sv.perm[L] ^ mask, b = sv.perm[L ^ 1u] ^ mask;
-  const uint32_t y = a / v.w, x = a - y * v.w;
-  uint32_t rowq[2 * R + 1], colq[2 * R + 1];
-#pragma unroll
-  for (int i = 0; i < 2 * R + 1; ++i) {
-    rowq[i] = ((y + v.h + i - R) % v.h) * v.w;
-    colq[i] = (x + v.w + i - R) % v.w;
-  }
-  long long zd[NCLS];
-#pragma unroll
-  for (int c = 0; c < NCLS; ++c) zd[c] = 0;
-  long long dd = 0;
-  const uint32_t t_begin = z * tslice, t_end = min(t_begin + tslice, v.tp);
-  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 256) {
-    const uint32_t t = t0 + 4 * lane;
-    if (t >= t_end) continue;
-    const uint2 ca = *(const uint2*)(sv.cpm + (size_t)a * v.tp + t);
-    const uint2 cb = *(const uint2*)(sv.cpm + (size_t)b * v.tp + t);
-    const uint32_t aw[2] = {ca.x, ca.y}, bw[2] = {cb.x, cb.y};
-    uint32_t dl[2];
-    int sq = 0;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int d0 = (int)(bw[k] & 0xFFFFu) - (int)(aw[k] & 0xFFFFu);
-      const int d1 = (int)(bw[k] >> 16) - (int)(aw[k] >> 16);
-      dl[k] = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
-      sq = dot2(dl[k], dl[k], sq);
+  const uint32_t x0 = blockIdx.x * G::BW, y0 = blockIdx.y * G::BH;
+
+  // members of the block, in raster order
+  bool in = false;
+  uint32_t j = 0, b = 0, pos = 0;
+  if (tid < (uint32_t)(G::BW * G::BH)) {
+    const uint32_t ly = tid / G::BW, lx = tid % G::BW;
+    if (y0 + ly < v.h && x0 + lx < v.w) {
+      const uint32_t L = sv.pinv[((y0 + ly) * v.w + x0 + lx) ^ mask];
+      in = L / sv.m == kappa;
+      j = L - kappa * sv.m;
+      b = sv.perm[L ^ 1u] ^ mask;
+      pos = (ly + R) * G::RW + lx + R;
     }
-    dd += sq;
-    int part[NCLS];
+  }
+  const unsigned long long bal = __ballot(in);
+  if (lane == 0 && wv < (uint32_t)G::NWV) wcnt[wv] = (uint32_t)__popcll(bal);
+  __syncthreads();
+  uint32_t before = 0, nm = 0;
 #pragma unroll
-    for (int c = 0; c < NCLS; ++c) part[c] = 0;
+  for (int q = 0; q < G::NWV; ++q) {
+    if ((uint32_t)q < wv) before += wcnt[q];
+    nm += wcnt[q];
+  }
+  if (in) {
+    const uint32_t idx = before + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+    mpos[idx] = pos;
+    mj[idx] = j;
+    mb[idx] = b;
+  }
+
+  // staging plan: item i = (tile i / RA of the stage, region pixel i % RA)
+  const uint32_t ys = (y0 + v.h * (R / v.h + 1) - R) % v.h;
+  const uint32_t xs = (x0 + v.w * (R / v.w + 1) - R) % v.w;
+  // (items past the end reload the last item and are not stored; W and H
+  // are powers of two for swap problems, so wrapping is a mask)
+  const uint32_t wm = v.w - 1, hm = v.h - 1;
+  const bool last_ok = tid + (G::ITER - 1) * G::NT < (uint32_t)G::ITEMS;
+
+  const uint32_t grp = tid / G::WPP, k = tid % G::WPP;
+  const uint32_t t_begin = blockIdx.z * slen, t_end = min(t_begin + slen, v.tp);
+  __syncthreads();
+  for (uint32_t base = 0; base < nm; base += G::CAP) {
+    int acc[G::SLOTS][NCLS];
+    int dd[G::SLOTS];
+    uint32_t spos[G::SLOTS], sb[G::SLOTS];
+    bool ok[G::SLOTS];
 #pragma unroll
-    for (int mm = 0; mm < W.M; ++mm) {
-      const uint32_t qq = rowq[W.oy[mm] + R] + colq[W.ox[mm] + R];
-      const uint2 cq = *(const uint2*)(sv.cpm + (size_t)qq * v.tp + t);
-      int acc = part[W.cls[mm]];
-      acc = dot2(dl[0], cq.x, acc);
-      acc = dot2(dl[1], cq.y, acc);
-      part[W.cls[mm]] = acc;
+    for (int s = 0; s < G::SLOTS; ++s) {
+      const uint32_t mi = base + grp * G::SLOTS + s;
+      ok[s] = mi < nm;
+      spos[s] = ok[s] ? mpos[mi] : 0;
+      sb[s] = ok[s] ? mb[mi] : 0;
+      dd[s] = 0;
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) acc[s][c] = 0;
     }
+    for (uint32_t t0 = t_begin; t0 < t_end; t0 += 32) {
+      u32x4 q[G::ITER];
 #pragma unroll
-    for (int c = 0; c < NCLS; ++c) zd[c] += part[c];
+      for (int it = 0; it < G::ITER; ++it) {
+        const uint32_t i = min(tid + it * G::NT, (uint32_t)G::ITEMS - 1u);
+        const uint32_t tile = i / G::RA, pix = i - tile * G::RA;
+        const uint32_t rr = pix / G::RW, cc = pix - rr * G::RW;
+        const uint32_t gq = ((ys + rr) & hm) * v.w + ((xs + cc) & wm);
+        q[it] = *(const u32x4*)(v.cnt + tix(gq, t0 + 8 * tile, P));
+      }
+      uint32_t pw[G::SLOTS];
+#pragma unroll
+      for (int s = 0; s < G::SLOTS; ++s) pw[s] = *(const uint32_t*)(v.cnt + tix(sb[s], t0 + 2 * k, P));
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < G::ITER; ++it) {
+        const uint32_t i = tid + it * G::NT;
+        const uint32_t tile = i / G::RA, pix = i - tile * G::RA;
+        if (it < G::ITER - 1 || last_ok) *(u32x4*)(reg + pix * G::WPP + 4 * tile) = q[it];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < G::SLOTS; ++s) {
+        if (ok[s]) {
+          const uint32_t* rp = reg + spos[s] * G::WPP + k;
+          const uint32_t own = rp[0];
+          const int d0 = (int)(pw[s] & 0xFFFFu) - (int)(own & 0xFFFFu);
+          const int d1 = (int)(pw[s] >> 16) - (int)(own >> 16);
+          const uint32_t dl = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
+          dd[s] = dot2(dl, dl, dd[s]);
+#pragma unroll
+          for (int mm = 0; mm < W.M; ++mm) {
+            const int disp = (W.oy[mm] * G::RW + W.ox[mm]) * G::WPP;
+            acc[s][W.cls[mm]] = dot2(dl, rp[disp], acc[s][W.cls[mm]]);
+          }
+        }
+      }
+    }
+    // members' class sums: reduce over the group's 16 lanes, add to HBM
+#pragma unroll
+    for (int s = 0; s < G::SLOTS; ++s) {
+      if (!ok[s]) break;   // slots fill in order
+      const uint32_t js = mj[base + grp * G::SLOTS + s];
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) {
+        long long x = acc[s][c];
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (k == 0 && x) atomicAdd((unsigned long long*)&sv.xs[(size_t)c * sv.m + js], (unsigned long long)(-2 * x));
+      }
+      long long d = dd[s];
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) d += __shfl_xor(d, off);
+      if (k == 0 && !(js & 1u) && d) atomicAdd((unsigned long long*)&sv.d2[js >> 1], (unsigned long long)d);
+    }
   }
-#pragma unroll
-  for (int c = 0; c < NCLS; ++c) {
-    long long s = zd[c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0 && s) atomicAdd((unsigned long long*)&sv.xs[(size_t)c * sv.m + j], (unsigned long long)(-2 * s));
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) dd += __shfl_xor(dd, off);
-  if (lane == 0 && !(j & 1u) && dd) atomicAdd((unsigned long long*)&sv.d2[j >> 1], (unsigned long long)dd);
 }
 
 // One thread per couple: add the two members' class sums and the pair
@@ -202,7 +233,7 @@ __global__ __launch_bounds__(256) void k_swap_finish(DevView v, SwapView sv, uin
   v.u_new[2 * i + 1] = b;
 }
 
-// One wave per accepted couple: exchange offsets and count rows.
+// One wave per accepted couple: exchange offsets and count tiles.
 __global__ __launch_bounds__(256) void k_swap_commit(DevView v, SwapView sv) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t i = wave_id();
@@ -214,9 +245,10 @@ __global__ __launch_bounds__(256) void k_swap_commit(DevView v, SwapView sv) {
     v.U[b] = ua;
     atomicAdd(&v.ctr[1], 1ull);
   }
-  for (uint32_t t = 8 * lane; t < v.tp; t += 512) {
-    uint4* ra = (uint4*)(sv.cpm + (size_t)a * v.tp + t);
-    uint4* rb = (uint4*)(sv.cpm + (size_t)b * v.tp + t);
+  const uint32_t P = v.w * v.h;
+  for (uint32_t tt = lane; tt < (v.tp >> 3); tt += 64) {
+    uint4* ra = (uint4*)(v.cnt + ((size_t)tt * P + a) * 8);
+    uint4* rb = (uint4*)(v.cnt + ((size_t)tt * P + b) * 8);
     const uint4 qa = *ra, qb = *rb;
     *ra = qb;
     *rb = qa;
@@ -225,40 +257,35 @@ __global__ __launch_bounds__(256) void k_swap_commit(DevView v, SwapView sv) {
 
 }  // namespace
 
-hipError_t launch_to_pixel_major(const DevView& v, const SwapView& sv, hipStream_t s) {
-  const size_t items = (size_t)v.w * v.h * (v.tp >> 3);
-  hipLaunchKernelGGL(k_to_pixel_major, dim3((uint32_t)((items + 255) / 256)), dim3(256), 0, s, v, sv);
-  return hipGetLastError();
-}
-
-hipError_t launch_from_pixel_major(const DevView& v, const SwapView& sv, hipStream_t s) {
-  const size_t items = (size_t)v.w * v.h * (v.tp >> 3);
-  hipLaunchKernelGGL(k_from_pixel_major, dim3((uint32_t)((items + 255) / 256)), dim3(256), 0, s, v, sv);
-  return hipGetLastError();
-}
-
-hipError_t launch_swap_select(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
-  hipLaunchKernelGGL(k_swap_reset, dim3(1), dim3(64), 0, s, sv);
-  const uint32_t P = v.w * v.h;
-  hipLaunchKernelGGL(k_swap_select, dim3((P + 255) / 256), dim3(256), 0, s, v, sv, kappa);
-  return hipGetLastError();
-}
-
+// Integrand slices: enough workgroups to fill the device, and few enough
+// stages per slice that every per-lane int32 partial sum stays below 2^31.
 hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
-  // integrand slices of 256 (at most 4), member blocks of 4 waves split over 8 XCDs
-  const uint32_t nz = std::min<uint32_t>(4, (v.tp + 255) / 256);
-  const uint32_t tslice = ((v.tp + nz - 1) / nz + 255) / 256 * 256;
-  const uint32_t nblk = (sv.m + 3) / 4, nbx = (nblk + 7) / 8;
-  const dim3 grid(8 * nbx * nz), block(256);
+  const uint32_t gx = (v.w + 31) / 32, gy = (v.h + 5) / 6, chunks = v.tp / 32;
+  const double n2 = (double)v.n * v.n;
+  const uint32_t smax = (uint32_t)std::max(1.0, std::floor(2147483647.0 / (24.0 * n2)));
+  uint32_t nz = std::max<uint32_t>(1, std::min<uint32_t>(chunks, (1024 + gx * gy - 1) / (gx * gy)));
+  uint32_t per = (chunks + nz - 1) / nz;
+  if (per > smax) per = smax;
+  nz = (chunks + per - 1) / per;
+  const uint32_t slen = per * 32;
+  const dim3 grid(gx, gy, nz), block(512);
   switch (v.radius) {
-    case 1: hipLaunchKernelGGL(k_swap_eval<1>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
-    case 2: hipLaunchKernelGGL(k_swap_eval<2>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
-    case 3: hipLaunchKernelGGL(k_swap_eval<3>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
-    case 4: hipLaunchKernelGGL(k_swap_eval<4>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
-    case 5: hipLaunchKernelGGL(k_swap_eval<5>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
-    case 6: hipLaunchKernelGGL(k_swap_eval<6>, grid, block, 0, s, v, sv, kappa, nbx, nz, tslice); break;
+#define BN_SWAP_STAGE(RR)                                                                           \
+  case RR:                                                                                          \
+    hipLaunchKernelGGL(k_swap_stage<RR>, grid, block, (size_t)SwapGeom<RR>::LDS_WORDS * 4, s, v, sv, \
+                       kappa, slen);                                                                \
+    break;
+    BN_SWAP_STAGE(1)
+    BN_SWAP_STAGE(2)
+    BN_SWAP_STAGE(3)
+    BN_SWAP_STAGE(4)
+    BN_SWAP_STAGE(5)
+    BN_SWAP_STAGE(6)
+#undef BN_SWAP_STAGE
     default: return hipErrorInvalidValue;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const uint32_t half = sv.m >> 1;
   hipLaunchKernelGGL(k_swap_finish, dim3((half + 255) / 256), dim3(256), 0, s, v, sv, kappa);
   return hipGetLastError();

@@ -18,22 +18,15 @@ constexpr uint32_t S_SWAP = 0xF;   // XOR masks of the passes
 struct SwapView {
   const uint32_t* perm;   // [P] pixel at list position L
   const uint32_t* pinv;   // [P] list position of pixel p
-  uint16_t* cpm;          // [P][tp] hit counts, pixel-major (the working copy during swap sweeps)
-  uint32_t* order;        // [M] the pass's list slots in selection order
-  uint32_t* nsel;         // [1] selection counter
   long long* xs;          // [ncls][M] integer class sums of each couple member's move (zero between passes)
   long long* d2;          // [M/2] sum_t (c_a,t - c_b,t)^2 of each couple (zero between passes)
   const int32_t* dcls;    // [2 r^2 + 1] class index of a squared distance (-1: none)
   uint32_t m;             // list positions per pass
 };
 
-// Offsets and counts: the tiled layout [tp/8][P][8] <-> pixel-major [P][tp].
-hipError_t launch_to_pixel_major(const DevView& v, const SwapView& sv, hipStream_t s);
-hipError_t launch_from_pixel_major(const DevView& v, const SwapView& sv, hipStream_t s);
-// Pass kappa of the sweep in the device counter: list the pass's slots,
-// evaluate every couple (delta/accept [M/2], couple pixels into u_new[2i],
-// u_new[2i+1]), exchange the accepted couples.
-hipError_t launch_swap_select(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s);
+// Pass kappa of the sweep in the device counter: evaluate every couple
+// (delta/accept [M/2], couple pixels into u_new[2i], u_new[2i+1]), then
+// exchange the accepted couples' offsets and count tiles.
 hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s);
 hipError_t launch_swap_commit(const DevView& v, const SwapView& sv, hipStream_t s);
 
