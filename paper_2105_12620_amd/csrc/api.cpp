@@ -563,6 +563,7 @@ std::vector<uint32_t> swap_permutation(const bn_config& c) {
 
 bn_status setup_swap(bn_problem p) {
   const uint32_t P = p->v.w * p->v.h, M = P / (p->v.k * p->v.k);
+  HIPCHK(prepare_swap_kernels());
   const std::vector<uint32_t> perm = swap_permutation(p->cfg);
   std::vector<uint32_t> pinv(P);
   for (uint32_t L = 0; L < P; ++L) pinv[perm[L]] = L;

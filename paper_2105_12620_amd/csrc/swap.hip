@@ -31,16 +31,23 @@ __device__ inline uint32_t swap_mask(const DevView& v, uint32_t kappa) {
 
 // LDS-staged member evaluation.  A workgroup owns a 32 x 6 block of tile
 // pixels; its pass members (pixels whose scrambled list position falls in the
-// pass) are listed in LDS.  For 32 integrands at a time the counts of the
-// block plus its window halo are staged in LDS (region RH x RW, 16 words of
-// two int16 counts per pixel), and every member is served by a group of 16
-// lanes, lane k holding integrand pair k of dc = c_partner - c_own (partner
-// counts read from HBM, own counts from LDS).  Per window offset a group reads
-// 16 consecutive words of the neighbour and takes one v_dot2 per lane.
+// pass) are listed in LDS.  For 64 integrands at a time the counts of the
+// block plus its window halo are staged in LDS (region RH x RW), and every
+// member is served by a group of 16 lanes, lane k holding integrands
+// 4k .. 4k+3 of dc = c_partner - c_own (partner counts read from HBM, own
+// counts from LDS).  Per window offset a group reads the neighbour's 32 words
+// with one ds_read_b64 per lane and takes two v_dot2 per lane.
+//
+// Staging goes straight from HBM to LDS (global_load_lds_dwordx4: lane l of a
+// load writes 16 bytes at the wave's LDS base + 16 l).  LDS holds eight planes
+// (one per 8-integrand tile) of RA_PAD pixels x 4 words; the plane stride is 4
+// words past a multiple of 32, so the 32 words a group reads for one
+// neighbour fall in 32 distinct banks.
+//
 // Integrand slices of the tile run in separate workgroups (grid z) and meet
 // in exact int64 atomics; per-lane int32 partial sums stay below 2^31 because
-// the host bounds a slice to S stages with S * 24 N^2 < 2^31 (at most 12
-// offsets per distance class, 2 integrands per lane per stage).
+// the host bounds a slice to S stages with S * 48 N^2 < 2^31 (at most 12
+// offsets per distance class, 4 integrands per lane per stage).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <int R>
@@ -48,15 +55,20 @@ struct SwapGeom {
   static constexpr int BW = 32, BH = 6;          // tile pixels per workgroup
   static constexpr int RW = BW + 2 * R, RH = BH + 2 * R;
   static constexpr int RA = RW * RH;             // region pixels
-  static constexpr int WPP = 16;                 // words per pixel and stage (32 integrands)
+  static constexpr int RA_PAD = (RA + 63) / 64 * 64;
+  static constexpr int PLANE = RA_PAD * 4 + 4;   // words per 8-integrand plane
+  static constexpr int NPLANE = 8;               // 8-integrand tiles per stage (64 integrands)
+  static constexpr int BUF = NPLANE * PLANE;     // words of the stage buffer
+  static constexpr int GL = 16;                  // lanes per member group
   static constexpr int NT = 512;                 // threads
-  static constexpr int GROUPS = NT / WPP;        // 32 member groups
+  static constexpr int NWAVE = NT / 64;
+  static constexpr int LOADS = NPLANE * RA_PAD / 64;   // 64-lane 16-byte loads per stage
+  static constexpr int GROUPS = NT / GL;         // 32 member groups
   static constexpr int SLOTS = 2;                // members per group and round
   static constexpr int CAP = GROUPS * SLOTS;     // members per round
-  static constexpr int ITEMS = RA * 4;           // 16-byte staging loads per stage
-  static constexpr int ITER = (ITEMS + NT - 1) / NT;
-  static constexpr int NWV = (BW * BH + 63) / 64; // waves that test membership
-  static constexpr int LDS_WORDS = RA * WPP + 3 * BW * BH + NWV;
+  static constexpr int NPIX = BW * BH;
+  static constexpr int NWV = (NPIX + 63) / 64;   // waves that test membership
+  static constexpr int LDS_WORDS = BUF + 3 * NPIX + NWV;
 };
 
 template <int R>
@@ -66,11 +78,10 @@ __global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v,
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
   extern __shared__ uint32_t lds[];
-  uint32_t* reg = lds;                             // [RA][16]
-  uint32_t* mpos = lds + G::RA * G::WPP;           // [BW*BH] region pixel of each member
-  uint32_t* mj = mpos + G::BW * G::BH;             // [BW*BH] list slot
-  uint32_t* mb = mj + G::BW * G::BH;               // [BW*BH] partner pixel
-  uint32_t* wcnt = mb + G::BW * G::BH;             // [NWV] members per wave
+  uint32_t* mpos = lds + G::BUF;                   // [NPIX] region pixel of each member
+  uint32_t* mj = mpos + G::NPIX;                   // [NPIX] list slot
+  uint32_t* mb = mj + G::NPIX;                     // [NPIX] partner pixel
+  uint32_t* wcnt = mb + G::NPIX;                   // [NWV] members per wave
   const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint32_t P = v.w * v.h;
   const uint32_t mask = swap_mask(v, kappa);
@@ -79,7 +90,7 @@ __global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v,
   // members of the block, in raster order
   bool in = false;
   uint32_t j = 0, b = 0, pos = 0;
-  if (tid < (uint32_t)(G::BW * G::BH)) {
+  if (tid < (uint32_t)G::NPIX) {
     const uint32_t ly = tid / G::BW, lx = tid % G::BW;
     if (y0 + ly < v.h && x0 + lx < v.w) {
       const uint32_t L = sv.pinv[((y0 + ly) * v.w + x0 + lx) ^ mask];
@@ -105,15 +116,30 @@ __global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v,
     mb[idx] = b;
   }
 
-  // staging plan: item i = (tile i / RA of the stage, region pixel i % RA)
+  // region pixel -> tile pixel (W and H are powers of two for swap problems)
   const uint32_t ys = (y0 + v.h * (R / v.h + 1) - R) % v.h;
   const uint32_t xs = (x0 + v.w * (R / v.w + 1) - R) % v.w;
-  // (items past the end reload the last item and are not stored; W and H
-  // are powers of two for swap problems, so wrapping is a mask)
   const uint32_t wm = v.w - 1, hm = v.h - 1;
-  const bool last_ok = tid + (G::ITER - 1) * G::NT < (uint32_t)G::ITEMS;
+  // the stage at t0: load n covers plane n / (RA_PAD / 64), region pixels
+  // 64 (n mod RA_PAD/64) + lane (padding lanes reload pixel 0)
+  auto issue_stage = [&](uint32_t t0) {
+    for (uint32_t n = wv; n < (uint32_t)G::LOADS; n += G::NWAVE) {
+      const uint32_t plane = n / (G::RA_PAD / 64), pix0 = (n % (G::RA_PAD / 64)) * 64;
+      const uint32_t pix = pix0 + lane;
+      uint32_t gq = 0;
+      if (pix < (uint32_t)G::RA) {
+        const uint32_t rr = pix / G::RW, cc = pix - rr * G::RW;
+        gq = ((ys + rr) & hm) * v.w + ((xs + cc) & wm);
+      }
+      const uint16_t* src = v.cnt + tix(gq, t0 + 8 * plane, P);
+      uint32_t* dst = lds + plane * G::PLANE + 4 * pix0;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                       (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+  };
 
-  const uint32_t grp = tid / G::WPP, k = tid % G::WPP;
+  const uint32_t grp = tid / G::GL, k = tid % G::GL;
+  const uint32_t lane_word = (k >> 1) * G::PLANE + 2 * (k & 1);
   const uint32_t t_begin = blockIdx.z * slen, t_end = min(t_begin + slen, v.tp);
   __syncthreads();
   for (uint32_t base = 0; base < nm; base += G::CAP) {
@@ -131,44 +157,44 @@ __global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v,
 #pragma unroll
       for (int c = 0; c < NCLS; ++c) acc[s][c] = 0;
     }
-    for (uint32_t t0 = t_begin; t0 < t_end; t0 += 32) {
-      u32x4 q[G::ITER];
+    for (uint32_t t0 = t_begin; t0 < t_end; t0 += 64) {
+      // partner counts: integrands t0 + 4k .. +3 (one 8-byte piece of a tile)
+      uint2 pw[G::SLOTS];
 #pragma unroll
-      for (int it = 0; it < G::ITER; ++it) {
-        const uint32_t i = min(tid + it * G::NT, (uint32_t)G::ITEMS - 1u);
-        const uint32_t tile = i / G::RA, pix = i - tile * G::RA;
-        const uint32_t rr = pix / G::RW, cc = pix - rr * G::RW;
-        const uint32_t gq = ((ys + rr) & hm) * v.w + ((xs + cc) & wm);
-        q[it] = *(const u32x4*)(v.cnt + tix(gq, t0 + 8 * tile, P));
-      }
-      uint32_t pw[G::SLOTS];
-#pragma unroll
-      for (int s = 0; s < G::SLOTS; ++s) pw[s] = *(const uint32_t*)(v.cnt + tix(sb[s], t0 + 2 * k, P));
+      for (int s = 0; s < G::SLOTS; ++s) pw[s] = *(const uint2*)(v.cnt + tix(sb[s], t0 + 4 * k, P));
       __syncthreads();
-#pragma unroll
-      for (int it = 0; it < G::ITER; ++it) {
-        const uint32_t i = tid + it * G::NT;
-        const uint32_t tile = i / G::RA, pix = i - tile * G::RA;
-        if (it < G::ITER - 1 || last_ok) *(u32x4*)(reg + pix * G::WPP + 4 * tile) = q[it];
-      }
+      issue_stage(t0);
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
+      const uint32_t* reg = lds + lane_word;
 #pragma unroll
       for (int s = 0; s < G::SLOTS; ++s) {
         if (ok[s]) {
-          const uint32_t* rp = reg + spos[s] * G::WPP + k;
-          const uint32_t own = rp[0];
-          const int d0 = (int)(pw[s] & 0xFFFFu) - (int)(own & 0xFFFFu);
-          const int d1 = (int)(pw[s] >> 16) - (int)(own >> 16);
-          const uint32_t dl = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
-          dd[s] = dot2(dl, dl, dd[s]);
+          const uint32_t* rp = reg + 4 * spos[s];
+          const uint2 own = *(const uint2*)rp;
+          const uint32_t pws[2] = {pw[s].x, pw[s].y}, ows[2] = {own.x, own.y};
+          uint32_t dl[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int d0 = (int)(pws[h] & 0xFFFFu) - (int)(ows[h] & 0xFFFFu);
+            const int d1 = (int)(pws[h] >> 16) - (int)(ows[h] >> 16);
+            dl[h] = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
+            dd[s] = dot2(dl[h], dl[h], dd[s]);
+          }
 #pragma unroll
           for (int mm = 0; mm < W.M; ++mm) {
-            const int disp = (W.oy[mm] * G::RW + W.ox[mm]) * G::WPP;
-            acc[s][W.cls[mm]] = dot2(dl, rp[disp], acc[s][W.cls[mm]]);
+            const int disp = 4 * (W.oy[mm] * G::RW + W.ox[mm]);
+            const uint2 c = *(const uint2*)(rp + disp);
+            int a = acc[s][W.cls[mm]];
+            a = dot2(dl[0], c.x, a);
+            a = dot2(dl[1], c.y, a);
+            acc[s][W.cls[mm]] = a;
           }
         }
       }
     }
+    // all reads of the buffers are done before a next round stages again
+    __syncthreads();
     // members' class sums: reduce over the group's 16 lanes, add to HBM
 #pragma unroll
     for (int s = 0; s < G::SLOTS; ++s) {
@@ -257,17 +283,38 @@ __global__ __launch_bounds__(256) void k_swap_commit(DevView v, SwapView sv) {
 
 }  // namespace
 
+// The staged kernels use more than 64 KiB of LDS per workgroup (gfx950 has
+// 160 KiB per CU); the launch limit is raised once per process.
+hipError_t prepare_swap_kernels() {
+  static hipError_t status = [] {
+    hipError_t e = hipSuccess;
+#define BN_SWAP_ATTR(RR)                                                                               \
+  if (e == hipSuccess)                                                                                 \
+    e = hipFuncSetAttribute((const void*)k_swap_stage<RR>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            (int)(SwapGeom<RR>::LDS_WORDS * 4));
+    BN_SWAP_ATTR(1)
+    BN_SWAP_ATTR(2)
+    BN_SWAP_ATTR(3)
+    BN_SWAP_ATTR(4)
+    BN_SWAP_ATTR(5)
+    BN_SWAP_ATTR(6)
+#undef BN_SWAP_ATTR
+    return e;
+  }();
+  return status;
+}
+
 // Integrand slices: enough workgroups to fill the device, and few enough
 // stages per slice that every per-lane int32 partial sum stays below 2^31.
 hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
-  const uint32_t gx = (v.w + 31) / 32, gy = (v.h + 5) / 6, chunks = v.tp / 32;
+  const uint32_t gx = (v.w + 31) / 32, gy = (v.h + 5) / 6, chunks = v.tp / 64;
   const double n2 = (double)v.n * v.n;
-  const uint32_t smax = (uint32_t)std::max(1.0, std::floor(2147483647.0 / (24.0 * n2)));
+  const uint32_t smax = (uint32_t)std::max(1.0, std::floor(2147483647.0 / (48.0 * n2)));
   uint32_t nz = std::max<uint32_t>(1, std::min<uint32_t>(chunks, (1024 + gx * gy - 1) / (gx * gy)));
   uint32_t per = (chunks + nz - 1) / nz;
   if (per > smax) per = smax;
   nz = (chunks + per - 1) / per;
-  const uint32_t slen = per * 32;
+  const uint32_t slen = per * 64;
   const dim3 grid(gx, gy, nz), block(512);
   switch (v.radius) {
 #define BN_SWAP_STAGE(RR)                                                                           \

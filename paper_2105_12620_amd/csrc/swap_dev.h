@@ -27,6 +27,8 @@ struct SwapView {
 // Pass kappa of the sweep in the device counter: evaluate every couple
 // (delta/accept [M/2], couple pixels into u_new[2i], u_new[2i+1]), then
 // exchange the accepted couples' offsets and count tiles.
+// Once per process, before the first swap launch (not under stream capture).
+hipError_t prepare_swap_kernels();
 hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s);
 hipError_t launch_swap_commit(const DevView& v, const SwapView& sv, hipStream_t s);
 
