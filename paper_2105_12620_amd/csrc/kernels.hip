@@ -669,39 +669,50 @@ __global__ void k_points(DevView v, uint32_t pixel, uint32_t* out) {
 
 // ------------------------------------------------------------------ energy
 // Y_d = sum_{o in class d} sum_p sum_t (c_p - c_{p+o})^2 over the half window
-// (the other half gives the same total); one wave per pixel, atomics on
-// integers only.
+// (the other half gives the same total).  Lanes run over 64 consecutive
+// pixels of a row, so every 16-byte tile load of a wave (8 integrands of 64
+// neighbouring pixels) is one contiguous 1 KiB run; per tile a lane's int32
+// partial sums (at most 12 offsets x 8 integrands x N^2 < 2^31) are widened
+// to 64 bits; atomics on integers only.
 template <int R>
 __global__ __launch_bounds__(256) void k_energy(DevView v, unsigned long long* ysum) {
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t p = wave_id();
-  if (p >= v.w * v.h) return;
-  const uint32_t y = p / v.w, x = p - y * v.w;
+  const uint32_t P = v.w * v.h;
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   long long yd[NCLS];
 #pragma unroll
   for (int c = 0; c < NCLS; ++c) yd[c] = 0;
-  const uint32_t P = v.w * v.h;
-  for (uint32_t base = 0; base < v.tp; base += 128) {
-    const uint32_t t = base + 2 * lane;
-    const uint32_t cp = *(const uint32_t*)(v.cnt + tix(p, t, P));
-    int part = 0;
+  if (p < P) {
+    const uint32_t y = p / v.w, x = p - y * v.w;
+    uint32_t q[W.M];
 #pragma unroll
-    for (int mm = 0; mm < W.M; ++mm) {
-      const bool half = W.oy[mm] > 0 || (W.oy[mm] == 0 && W.ox[mm] > 0);
-      if (half) {
-        const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
-        const uint32_t cq = *(const uint32_t*)(v.cnt + tix(q, t, P));
-        const int d0 = (int)(cp & 0xFFFFu) - (int)(cq & 0xFFFFu);
-        const int d1 = (int)(cp >> 16) - (int)(cq >> 16);
-        const uint32_t dp = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
-        part = dot2(dp, dp, part);
+    for (int mm = 0; mm < W.M; ++mm)
+      q[mm] = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
+    for (uint32_t tt = 0; tt < (v.tp >> 3); ++tt) {
+      const uint4 cp = *(const uint4*)(v.cnt + ((size_t)tt * P + p) * 8);
+      const uint32_t pw[4] = {cp.x, cp.y, cp.z, cp.w};
+      int part[NCLS];
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) part[c] = 0;
+#pragma unroll
+      for (int mm = 0; mm < W.M; ++mm) {
+        if (!(W.oy[mm] > 0 || (W.oy[mm] == 0 && W.ox[mm] > 0))) continue;
+        const uint4 cq = *(const uint4*)(v.cnt + ((size_t)tt * P + q[mm]) * 8);
+        const uint32_t qw[4] = {cq.x, cq.y, cq.z, cq.w};
+        int a = part[W.cls[mm]];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int d0 = (int)(pw[k] & 0xFFFFu) - (int)(qw[k] & 0xFFFFu);
+          const int d1 = (int)(pw[k] >> 16) - (int)(qw[k] >> 16);
+          const uint32_t dp = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
+          a = dot2(dp, dp, a);
+        }
+        part[W.cls[mm]] = a;
       }
-      if (mm == W.M - 1 || W.cls[mm + 1] != W.cls[mm]) {
-        yd[W.cls[mm]] += part;
-        part = 0;
-      }
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) yd[c] += part[c];
     }
   }
 #pragma unroll
@@ -1031,7 +1042,7 @@ hipError_t launch_points(const DevView& v, uint32_t pixel, uint32_t* out, hipStr
 
 hipError_t launch_energy(const DevView& v, unsigned long long* y, hipStream_t s) {
   const uint32_t P = v.w * v.h;
-  const dim3 grid((P + 3) / 4), block(256);
+  const dim3 grid((P + 255) / 256), block(256);
   switch (v.radius) {
     case 1: hipLaunchKernelGGL(k_energy<1>, grid, block, 0, s, v, y); break;
     case 2: hipLaunchKernelGGL(k_energy<2>, grid, block, 0, s, v, y); break;
