@@ -248,6 +248,27 @@ bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* d
  * BN_ESTATE for swap problems and bn_get_swap_pass for redraw problems. */
 bn_status bn_get_swap_pass(bn_problem p, uint32_t* a, uint32_t* b, double* delta, uint8_t* accept);
 
+/* ------------------------------------------------------------ sampler query */
+
+/* The padded screen-space sampler a renderer reads (Sec. 3.1: dimensions are
+ * consumed in pairs, each pair (2d, 2d+1) with its own tile; a 1-D effect
+ * takes one dimension of a pair and discards the other.  Sec. 3.2: sample k
+ * of pixel p is mod(Phi(k) g / N + u_p, 1), Phi the base-2 radical inverse).
+ * pairs[d] is the problem that holds pair d's lattice and offset tile (for
+ * example the members of a batch).  For query j: screen pixel (x[j], y[j]),
+ * any values, wrapped modulo each tile; sample index k[j] in van der Corput
+ * order, taken modulo that pair's N.  out[j * 2 npairs + 2d + a] = component a
+ * of pair d's sample, a float in [0, 1) (exact: the Q0.16 value / 65536).
+ * Every pair must have offsets (bn_init_offsets); the pairs' pending work is
+ * waited for.  bn_sample takes host arrays x, y, k uint32 [m] and host out
+ * float [m][2 npairs]; bn_sample_device takes device arrays and a stream
+ * (NULL: pairs[0]'s stream) and synchronises it.  Both allocate a small
+ * device table per call. */
+bn_status bn_sample(const bn_problem* pairs, uint32_t npairs, const uint32_t* x, const uint32_t* y,
+                    const uint32_t* k, uint32_t m, float* out);
+bn_status bn_sample_device(const bn_problem* pairs, uint32_t npairs, const uint32_t* x, const uint32_t* y,
+                           const uint32_t* k, uint32_t m, float* out, void* stream);
+
 /* ----------------------------------------------------------------- batching */
 
 /* Independent problems (e.g. the dimension pairs of a padded sampler,

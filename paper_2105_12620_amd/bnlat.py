@@ -84,6 +84,8 @@ _SIGNATURES = {
     "bn_phase_advance": [_P],
     "bn_get_phase": [_P, _P, _P, _P, _P],
     "bn_get_swap_pass": [_P, _P, _P, _P, _P],
+    "bn_sample": [_P, C.c_uint32, _P, _P, _P, C.c_uint32, _P],
+    "bn_sample_device": [_P, C.c_uint32, _P, _P, _P, C.c_uint32, _P, _P],
     "bn_create_batch": [_P, C.c_uint32, C.c_char_p, C.POINTER(_P)],
     "bn_batch_sweep": [_P, C.c_uint32],
     "bn_destroy_batch": [_P],
@@ -360,6 +362,20 @@ class Problem:
         acc = np.zeros(half, dtype=np.uint8)
         _call("bn_get_swap_pass", self.handle, _ptr(a), _ptr(b), _ptr(d), _ptr(acc))
         return {"a": a, "b": b, "delta": d, "accept": acc.astype(bool)}
+
+
+def sample(problems, x, y, k) -> np.ndarray:
+    """Padded sampler query: float32 [m, 2 * len(problems)], dimension 2d + a
+    = component a of problems[d]'s scrambled lattice sample k at pixel (x, y)."""
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    y = np.ascontiguousarray(y, dtype=np.uint32)
+    k = np.ascontiguousarray(k, dtype=np.uint32)
+    if not (x.shape == y.shape == k.shape and x.ndim == 1):
+        raise ValueError("x, y, k must be 1-D arrays of one length")
+    out = np.zeros((x.shape[0], 2 * len(problems)), dtype=np.float32)
+    arr = (C.c_void_p * len(problems))(*[p.handle.value for p in problems])
+    _call("bn_sample", arr, len(problems), _ptr(x), _ptr(y), _ptr(k), x.shape[0], _ptr(out))
+    return out
 
 
 class Batch:

@@ -13,6 +13,7 @@
 #include "../../include/bnlat.h"
 #include "bnlat_dev.h"
 #include "swap_dev.h"
+#include "sampler_dev.h"
 
 using namespace bnlat;
 
@@ -1370,6 +1371,64 @@ bn_status bn_set_recount_blocks(bn_problem p, uint32_t blocks) {
   p->pair_graph = nullptr;
   p->pair_failed = false;
   return BN_OK;
+}
+
+bn_status bn_sample_device(const bn_problem* pairs, uint32_t npairs, const uint32_t* x, const uint32_t* y,
+                           const uint32_t* k, uint32_t m, float* out, void* stream) {
+  if (!pairs || !npairs) return fail(BN_EINVAL, "no dimension pairs");
+  if (m && (!x || !y || !k || !out)) return fail(BN_EINVAL, "NULL query or output buffer");
+  std::vector<SamplerPair> tab(npairs);
+  for (uint32_t d = 0; d < npairs; ++d) {
+    const bn_problem p = pairs[d];
+    if (!p) return fail(BN_EINVAL, "pair %u is NULL", d);
+    if (!p->have_offsets) return fail(BN_ESTATE, "pair %u has no offsets", d);
+    tab[d] = SamplerPair{p->v.lat, p->v.U, p->v.w, p->v.h, p->v.n, p->v.log2n};
+    // the pair's own work (sweeps) must be finished before its tile is read
+    bn_status s = sync(p);
+    if (s != BN_OK) return s;
+    if (p->aux) HIPCHK(hipStreamSynchronize(p->aux));
+  }
+  if (!m) return BN_OK;
+  hipStream_t st = stream ? (hipStream_t)stream : pairs[0]->stream;
+  SamplerPair* dtab = nullptr;
+  HIPCHK(hipMalloc((void**)&dtab, npairs * sizeof(SamplerPair)));
+  hipError_t e = hipMemcpyAsync(dtab, tab.data(), npairs * sizeof(SamplerPair), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_sample(dtab, npairs, x, y, k, m, out, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dtab);
+  if (e != hipSuccess) return fail(BN_EHIP, "sampler query: %s", hipGetErrorString(e));
+  return BN_OK;
+}
+
+bn_status bn_sample(const bn_problem* pairs, uint32_t npairs, const uint32_t* x, const uint32_t* y,
+                    const uint32_t* k, uint32_t m, float* out) {
+  if (!pairs || !npairs) return fail(BN_EINVAL, "no dimension pairs");
+  if (m && (!x || !y || !k || !out)) return fail(BN_EINVAL, "NULL query or output buffer");
+  if (!m) return bn_sample_device(pairs, npairs, nullptr, nullptr, nullptr, 0, nullptr, nullptr);
+  uint32_t* dq = nullptr;
+  float* dout = nullptr;
+  const size_t nout = (size_t)m * 2 * npairs;
+  hipError_t e = hipMalloc((void**)&dq, (size_t)3 * m * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&dout, nout * 4);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (dq) (void)hipFree(dq);
+    return fail(BN_ENOMEM, "sampler query buffers: %s", hipGetErrorString(e));
+  }
+  hipStream_t st = pairs[0] ? pairs[0]->stream : nullptr;
+  e = hipMemcpyAsync(dq, x, (size_t)m * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dq + m, y, (size_t)m * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dq + 2 * (size_t)m, k, (size_t)m * 4, hipMemcpyHostToDevice, st);
+  bn_status s = BN_OK;
+  if (e != hipSuccess) s = fail(BN_EHIP, "sampler query upload: %s", hipGetErrorString(e));
+  if (s == BN_OK) s = bn_sample_device(pairs, npairs, dq, dq + m, dq + 2 * (size_t)m, m, dout, st);
+  if (s == BN_OK) {
+    e = hipMemcpy(out, dout, nout * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) s = fail(BN_EHIP, "sampler query download: %s", hipGetErrorString(e));
+  }
+  (void)hipFree(dq);
+  (void)hipFree(dout);
+  return s;
 }
 
 bn_status bn_get_sweep_index(bn_problem p, uint64_t* out) {
