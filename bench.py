@@ -154,8 +154,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="tile256_n256_t1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16,swap,batched",
-                    help="comma list of forms to run: fp32 (headline), bf16, swap, batched")
+    ap.add_argument("--forms", default="fp32,bf16,swap,batched,large",
+                    help="comma list of forms to run: fp32 (headline), bf16, swap, batched, large")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--experiment", choices=["quality"], default=None,
@@ -261,6 +261,40 @@ def main() -> int:
 
     batch = batched() if "batched" in forms else None
 
+    def large() -> dict:
+        """Four 512x512 problems (N = 1024, 3072 Heavisides + 1024 Gaussians,
+        11x11 window) in the BF16 form, batched into one graph."""
+        base = dict(synthgen.WORKLOADS["tile512_n1024_t4096"])
+        probs = []
+        for j in range(4):
+            mw = dict(base, problem_id=j)
+            mi = synthgen.problem_inputs(mw)
+            q = bnlat.create_problem(mw, bnlat.heaviside_array(mi["heaviside"]), stream=stream.cuda_stream,
+                                     gaussians=bnlat.gaussian_array(mi["gauss"]), precision=bnlat.BN_BF16)
+            q.init_offsets(mi["offsets"])
+            q.compute_errors()
+            probs.append(q)
+        b = bnlat.Batch(probs)
+        b.sweep(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        steps = 2
+        e0.record(stream)
+        b.sweep(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        pix = 4 * base["width"] * base["height"]
+        out = {"value": pix * steps / (ms * 1e-3), "unit": "pixel-updates/s", "members": 4,
+               "shape": "512^2, N=1024, 3072 Heavisides + 1024 Gaussians, 11x11, BF16",
+               "sweeps": steps, "ms_per_sweep": ms / steps}
+        b.close()
+        for q in probs:
+            q.close()
+        return out
+
+    big = large() if "large" in forms else None
+
     # algorithmic work per launch of the counting kernel: one sweep-wide recount
     count_ops = 2.0 * P * N * T                       # v_dot2 + compare per (sample, integrand)
     count_tops = count_ops / (avg["recount_per_sweep"] * 1e-3) / 1e12
@@ -302,6 +336,7 @@ def main() -> int:
                            "passes": swap["kernels_ms"]["phases"]},
             "evaluate_hbm_gbs": delta_bytes / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9},
         "batched": batch,
+        "batched_large": big,
         "window_offsets": win,
     }
     if not args.no_cpu_baseline:

@@ -58,9 +58,11 @@ typedef enum {
 
 /* Arithmetic of the energy-change evaluation (the neighbourhood Gram part).
  * BN_FP32: integer hit counts and FP32 error vectors on the vector ALUs.
- * BN_BF16: centred hit counts (c - N/2) in BF16 on the matrix cores with
- *          FP32 accumulation (exact when N <= 256 and T (N/2)^2 <= 2^24);
- *          accepted moves are re-checked with the exact integer form.      */
+ * BN_BF16: hit counts in BF16 on the matrix cores with FP32 accumulation
+ *          (N <= 256, K = 2); a slice whose partial sums could exceed 2^24
+ *          flags its pixels and accepted flagged moves are re-checked with
+ *          the exact integer form.  For N > 256 (counts not exact in BF16)
+ *          the exact integer stencil runs instead.                          */
 typedef enum { BN_FP32 = 0, BN_BF16 = 1 } bn_precision;
 
 /* Mutation.
@@ -276,9 +278,12 @@ bn_status bn_sample_device(const bn_problem* pairs, uint32_t npairs, const uint3
  * variant covers every member (members grouped by samples-per-pixel class for
  * counting and by window radius for the energy change), and a whole sweep of
  * all members is captured once as a HIP graph and replayed k times.  Each
- * member's trajectory equals the one bn_sweep gives it alone.  Requirements:
- * members distinct, created on one stream, bn_compute_errors done, one common
- * colour_k in {1, 2, 4}, FP32 precision.  tune_cache (nullable) names a text
+ * member's trajectory equals the one bn_sweep gives it alone.  Members in the
+ * FP32 form with Heaviside rows only and redraw moves share the grouped
+ * launches; members in the BF16 form, with Gaussian rows or with swap moves
+ * have their own sweep recorded into the same graph.  Requirements: members
+ * distinct, created on one stream, bn_compute_errors done, profiling off, one
+ * common colour_k in {1, 2, 4}.  tune_cache (nullable) names a text
  * file of launch choices keyed by the members' shapes; when the key is absent
  * the tuner times the candidates on the device (propose + evaluate only, no
  * state change) and appends its choice.  Members stay owned by the caller and

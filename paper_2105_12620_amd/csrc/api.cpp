@@ -262,6 +262,9 @@ struct bn_batch_s {
   uint32_t colour_k = 0;
   std::vector<BatchGroup> count_groups, stage_groups;
   BatchGroup finish_all, commit_all;
+  // members outside the grouped FP32 redraw launches (BF16, Gaussian rows or
+  // swap moves): their own sweep is recorded into the same graph
+  std::vector<uint32_t> solo;
   std::vector<void*> allocs;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -710,6 +713,8 @@ bn_status batch_upload(bn_batch b) {
     p->v.slice_target = b->slice_target;
   }
   auto upload = [&](BatchGroup& g, auto blocks_of, bool geo) -> bn_status {
+    g.blocks = 0;
+    if (g.idx.empty()) return BN_OK;
     std::vector<DevView> views;
     std::vector<uint32_t> pre(1, 0), gv;
     for (uint32_t i : g.idx) {
@@ -758,6 +763,7 @@ bn_status batch_upload(bn_batch b) {
 }
 
 bn_status batch_evaluate(bn_batch b, uint32_t kappa) {
+  if (b->finish_all.idx.empty()) return BN_OK;
   for (BatchGroup& g : b->count_groups)
     HIPCHK(launch_count_batch(g.kind, g.d_views, g.d_pre, (uint32_t)g.idx.size(), g.blocks, kappa, b->stream));
   for (BatchGroup& g : b->stage_groups)
@@ -769,13 +775,19 @@ bn_status batch_evaluate(bn_batch b, uint32_t kappa) {
 }
 
 bn_status batch_record_sweep(bn_batch b) {
-  for (uint32_t kappa = 0; kappa < b->colour_k * b->colour_k; ++kappa) {
-    bn_status s = batch_evaluate(b, kappa);
-    if (s != BN_OK) return s;
-    HIPCHK(launch_commit_batch(b->commit_all.d_views, b->commit_all.d_pre, (uint32_t)b->commit_all.idx.size(),
-                               b->commit_all.blocks, kappa, b->stream));
+  bn_status s;
+  if (!b->commit_all.idx.empty()) {
+    for (uint32_t kappa = 0; kappa < b->colour_k * b->colour_k; ++kappa) {
+      if ((s = batch_evaluate(b, kappa)) != BN_OK) return s;
+      HIPCHK(launch_commit_batch(b->commit_all.d_views, b->commit_all.d_pre, (uint32_t)b->commit_all.idx.size(),
+                                 b->commit_all.blocks, kappa, b->stream));
+    }
+    HIPCHK(launch_advance_batch(b->commit_all.d_views, (uint32_t)b->commit_all.idx.size(), b->stream));
   }
-  HIPCHK(launch_advance_batch(b->commit_all.d_views, (uint32_t)b->commit_all.idx.size(), b->stream));
+  for (uint32_t i : b->solo) {
+    bn_problem p = b->members[i];
+    if ((s = p->cfg.move == BN_SWAP ? record_swap_sweep(p) : record_sweep(p)) != BN_OK) return s;
+  }
   return BN_OK;
 }
 
@@ -1537,9 +1549,7 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
     if (!p->have_counts) return fail(BN_ESTATE, "member %u: bn_compute_errors must run first", i);
     if (p->stream != members[0]->stream) return fail(BN_EINVAL, "members must share one stream");
     if (p->cfg.colour_k != members[0]->cfg.colour_k) return fail(BN_EINVAL, "members must share colour_k");
-    if (p->cfg.precision != BN_FP32) return fail(BN_EUNSUPPORTED, "batched members must use FP32 precision");
-    if (p->cfg.move != BN_REDRAW) return fail(BN_EUNSUPPORTED, "batched members must use redraw moves");
-    if (p->cfg.t_gauss) return fail(BN_EUNSUPPORTED, "batched members must have Heaviside integrands only");
+    if (p->profiling) return fail(BN_ESTATE, "member %u has kernel profiling on", i);
     for (uint32_t j = 0; j < i; ++j)
       if (members[j] == p) return fail(BN_EINVAL, "member %u appears twice", i);
   }
@@ -1550,7 +1560,12 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
   b->stream = members[0]->stream;
   b->colour_k = K;
   for (uint32_t i = 0; i < m; ++i) {
-    const DevView& v = members[i]->v;
+    const bn_problem mp = members[i];
+    if (mp->cfg.precision != BN_FP32 || mp->cfg.move != BN_REDRAW || mp->cfg.t_gauss) {
+      b->solo.push_back(i);
+      continue;
+    }
+    const DevView& v = mp->v;
     const int kind = count_kind(v);
     auto cg = std::find_if(b->count_groups.begin(), b->count_groups.end(), [&](const BatchGroup& g) { return g.kind == kind; });
     if (cg == b->count_groups.end()) {

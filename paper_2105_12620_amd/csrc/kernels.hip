@@ -782,9 +782,11 @@ __global__ __launch_bounds__(256) void k_blur_y_sq(DevView v, uint32_t pitch, ui
 // ----------------------------------------------------- Gaussian integrands
 // Low-frequency test integrands (Sec. 3.5): f_t(x) = exp(-|x - mu_t|^2 / (2 s_t^2)).
 // Estimates g = (1/N) sum_k f_t(s_p^k) per pixel, lanes over integrands and
-// wave-uniform samples.  The exponent is formed in FP64 from the exact Q0.16
-// sample (the centres are FP64), exp2 runs in FP32 and the sum accumulates in
-// FP64; the estimate is stored in FP32.
+// wave-uniform samples.  The centre is split into FP32 high and low parts:
+// the Q0.16 sample minus the high part is exact in FP32, so the offset is
+// accurate to one FP32 rounding of its size and the exponent to a relative
+// 2^-22 or so; exp2 runs in FP32 and the sum accumulates in FP64; the
+// estimate is stored in FP32.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, uint32_t m) {
   const uint32_t lane = threadIdx.x & 63;
@@ -803,13 +805,15 @@ __global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, ui
   }
   const uint32_t t = ch * 64 + lane;
   const double2 mu = v.gmu[t];
-  const double a = v.gscale[t];
+  const float mxh = (float)mu.x, myh = (float)mu.y;
+  const float mxl = (float)(mu.x - (double)mxh), myl = (float)(mu.y - (double)myh);
+  const float a = -(float)v.gscale[t];
   double acc = 0.0;
   for (uint32_t i = 0; i < v.n; ++i) {
     const uint32_t sv = wrap_add(v.lat[i], u);
-    const double dx = (double)(sv & 0xFFFFu) * 0x1p-16 - mu.x;
-    const double dy = (double)(sv >> 16) * 0x1p-16 - mu.y;
-    acc += (double)exp2f((float)(-(dx * dx + dy * dy) * a));
+    const float dx = ((float)(sv & 0xFFFFu) * 0x1p-16f - mxh) - mxl;
+    const float dy = ((float)(sv >> 16) * 0x1p-16f - myh) - myl;
+    acc += (double)exp2f(__fmul_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), a));
   }
   out[t] = (float)(acc / (double)v.n);
 }
@@ -991,7 +995,10 @@ hipError_t mfma_launch(const DevView& v, uint32_t kappa, hipStream_t s) {
 }
 
 hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
-  if (mode == MODE_CLASS && v.mfma) {
+  // The matrix-core form only certifies exactness for N <= 256 (counts exact
+  // in BF16); above that every accepted move would be re-checked, so the
+  // exact integer stencil runs directly (same decisions, less work).
+  if (mode == MODE_CLASS && v.mfma && v.n <= 256) {
     switch (v.radius) {
       case 1: return mfma_launch<1>(v, kappa, s);
       case 2: return mfma_launch<2>(v, kappa, s);

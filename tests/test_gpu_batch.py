@@ -117,3 +117,41 @@ def test_batch_validation(stream):
     assert e.value.status == bnlat.BN_EINVAL
     for x in (p, q, other):
         x.close()
+
+
+MIXED = [
+    workload(n=64, g=(1, 19), width=16, height=16, t_heaviside=40, problem_id=10),
+    workload(n=256, g=(1, 79), width=16, height=16, t_heaviside=48, radius=4, precision=1, problem_id=11),
+    workload(n=64, g=(1, 19), width=16, height=16, t_heaviside=20, t_gauss=36, problem_id=12),
+    workload(n=256, g=(1, 79), width=16, height=16, t_heaviside=40, t_gauss=24, radius=4, precision=1,
+             problem_id=13),
+    workload(n=16, g=(1, 7), width=16, height=16, t_heaviside=30, move=1, objective=-1, problem_id=14),
+    workload(n=16, g=(1, 7), width=32, height=16, t_heaviside=12, problem_id=15),
+]
+
+
+def make_any(w, inp, stream):
+    g = bnlat.gaussian_array(inp["gauss"]) if w.get("t_gauss", 0) else None
+    p = bnlat.create_problem(w, bnlat.heaviside_array(inp["heaviside"]), stream=stream.cuda_stream, gaussians=g)
+    p.init_offsets(inp["offsets"])
+    p.compute_errors()
+    return p
+
+
+def test_mixed_forms_in_one_batch(stream):
+    """Members in the BF16 form, with Gaussian rows or with swap moves are
+    recorded into the batch's graph beside the grouped FP32 members; every
+    member's trajectory, counts and energy equal its own sweeps alone."""
+    inps = [synthgen.problem_inputs(w) for w in MIXED]
+    batched = [make_any(w, inp, stream) for w, inp in zip(MIXED, inps)]
+    with bnlat.Batch(batched) as b:
+        b.sweep(3)
+    for w, inp, p in zip(MIXED, inps, batched):
+        say("member", w["problem_id"], w.get("precision", 0), w.get("t_gauss", 0), w.get("move", 0))
+        with make_any(w, inp, stream) as alone:
+            alone.sweep(3)
+            np.testing.assert_array_equal(p.get_offsets(), alone.get_offsets())
+            np.testing.assert_array_equal(p.get_counts(), alone.get_counts())
+            assert p.energy() == alone.energy()
+            assert p.get_sweep_index() == 3
+        p.close()
