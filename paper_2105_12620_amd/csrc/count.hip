@@ -193,9 +193,10 @@ hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
   switch (v.n) {
     case 64: hipLaunchKernelGGL((k_count_points<1, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
     case 128: hipLaunchKernelGGL((k_count_points<2, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
-    case 256: hipLaunchKernelGGL((k_count_points<4, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
-    case 512: hipLaunchKernelGGL((k_count_points<8, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
-    default: hipLaunchKernelGGL((k_count_points<16, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
+    // N >= 256: four samples per lane, N / 256 sample groups (more samples
+    // per lane would keep more compare masks live than the scalar registers
+    // hold, and the spills cost more than the group reloads)
+    default: hipLaunchKernelGGL((k_count_points<4, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
   }
   return hipGetLastError();
 }
@@ -216,9 +217,7 @@ int count_kind(const DevView& v) {
   switch (v.n) {
     case 64: return 1;
     case 128: return 2;
-    case 256: return 4;
-    case 512: return 8;
-    default: return 16;
+    default: return 4;
   }
 }
 
@@ -235,9 +234,7 @@ hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pr
     case 0: hipLaunchKernelGGL(k_count_integrands_batch, grid, block, 0, s, views, pre, nmem, kappa); break;
     case 1: hipLaunchKernelGGL(k_count_points_batch<1>, grid, block, 0, s, views, pre, nmem, kappa); break;
     case 2: hipLaunchKernelGGL(k_count_points_batch<2>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 4: hipLaunchKernelGGL(k_count_points_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 8: hipLaunchKernelGGL(k_count_points_batch<8>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    default: hipLaunchKernelGGL(k_count_points_batch<16>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    default: hipLaunchKernelGGL(k_count_points_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
   }
   return hipGetLastError();
 }
