@@ -782,14 +782,18 @@ __global__ __launch_bounds__(256) void k_blur_y_sq(DevView v, uint32_t pitch, ui
 // ----------------------------------------------------- Gaussian integrands
 // Low-frequency test integrands (Sec. 3.5): f_t(x) = exp(-|x - mu_t|^2 / (2 s_t^2)).
 // Estimates g = (1/N) sum_k f_t(s_p^k) per pixel, lanes over integrands and
-// wave-uniform samples.  The centre is split into FP32 high and low parts:
-// the Q0.16 sample minus the high part is exact in FP32, so the offset is
-// accurate to one FP32 rounding of its size and the exponent to a relative
-// 2^-22 or so; exp2 runs in FP32 and the sum accumulates in FP64; the
-// estimate is stored in FP32.
+// wave-uniform samples.  The wave first writes its pixel's N sample
+// coordinates to LDS as floats (exact: Q0.16 values), then every lane reads
+// them by broadcast.  The centre is split into FP32 high and low parts: the
+// sample minus the high part is exact in FP32, so the offset is accurate to
+// one FP32 rounding of its size and the exponent to a relative 2^-22 or so;
+// exp2 runs in FP32, groups of eight terms are summed in FP32 and the groups
+// in FP64; the estimate is stored in FP32.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, uint32_t m) {
-  const uint32_t lane = threadIdx.x & 63;
+  constexpr uint32_t CH = 1024;                 // samples per LDS chunk
+  __shared__ float2 smp[4][CH];
+  const uint32_t lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
   const uint32_t wave = wave_id();
   const uint32_t nch = v.tgp >> 6;
   const uint32_t j = wave / nch, ch = wave - j * nch;
@@ -803,17 +807,41 @@ __global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, ui
     u = v.u_new[j];
     out = v.g_new + (size_t)j * v.tgp;
   }
+  float2* sw = smp[wl];
   const uint32_t t = ch * 64 + lane;
   const double2 mu = v.gmu[t];
   const float mxh = (float)mu.x, myh = (float)mu.y;
   const float mxl = (float)(mu.x - (double)mxh), myl = (float)(mu.y - (double)myh);
   const float a = -(float)v.gscale[t];
   double acc = 0.0;
-  for (uint32_t i = 0; i < v.n; ++i) {
-    const uint32_t sv = wrap_add(v.lat[i], u);
-    const float dx = ((float)(sv & 0xFFFFu) * 0x1p-16f - mxh) - mxl;
-    const float dy = ((float)(sv >> 16) * 0x1p-16f - myh) - myl;
-    acc += (double)exp2f(__fmul_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), a));
+  for (uint32_t c0 = 0; c0 < v.n; c0 += CH) {
+    const uint32_t cn = min(CH, v.n - c0);
+    // this wave's samples c0 .. c0 + cn - 1 as floats; LDS operations of one
+    // wave complete in order, so the reads below see every lane's writes
+    for (uint32_t i = lane; i < cn; i += 64) {
+      const uint32_t sv = wrap_add(v.lat[c0 + i], u);
+      sw[i] = make_float2((float)(sv & 0xFFFFu) * 0x1p-16f, (float)(sv >> 16) * 0x1p-16f);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // v_exp_f32 directly: terms below 2^-126 flush to zero, far below the
+    // estimate's FP32 resolution
+    auto term = [&](uint32_t i) {
+      const float2 sp = sw[i];
+      const float dx = __fsub_rn(__fsub_rn(sp.x, mxh), mxl);
+      const float dy = __fsub_rn(__fsub_rn(sp.y, myh), myl);
+      return __builtin_amdgcn_exp2f(__fmul_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), a));
+    };
+    uint32_t i0 = 0;
+    for (; i0 + 8 <= cn; i0 += 8) {
+      float part = 0.0f;
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i) part = __fadd_rn(part, term(i0 + i));
+      acc += (double)part;
+    }
+    for (; i0 < cn; ++i0) acc += (double)term(i0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   out[t] = (float)(acc / (double)v.n);
 }

@@ -141,7 +141,8 @@ def make_any(w, inp, stream):
 def test_mixed_forms_in_one_batch(stream):
     """Members in the BF16 form, with Gaussian rows or with swap moves are
     recorded into the batch's graph beside the grouped FP32 members; every
-    member's trajectory, counts and energy equal its own sweeps alone."""
+    member's trajectory and counts equal its own sweeps alone, and so does
+    its energy (to FP64 summation order)."""
     inps = [synthgen.problem_inputs(w) for w in MIXED]
     batched = [make_any(w, inp, stream) for w, inp in zip(MIXED, inps)]
     with bnlat.Batch(batched) as b:
@@ -152,6 +153,8 @@ def test_mixed_forms_in_one_batch(stream):
             alone.sweep(3)
             np.testing.assert_array_equal(p.get_offsets(), alone.get_offsets())
             np.testing.assert_array_equal(p.get_counts(), alone.get_counts())
-            assert p.energy() == alone.energy()
+            # the Gaussian rows' FP64 energy part is summed with atomics, so
+            # its last bits depend on the order
+            assert p.energy() == pytest.approx(alone.energy(), rel=1e-12)
             assert p.get_sweep_index() == 3
         p.close()
