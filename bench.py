@@ -102,7 +102,7 @@ def quality_experiment(sweeps: int) -> dict:
     """The criterion of Sec. 3.3 (Fig. 1c) and the versatility claim of
     Sec. 3.5 on the GPU path: a 128x128 tile at 16 samples per pixel
     (generator (1, 5), the one of Fig. 1a), optimised on 256 Heavisides with
-    each mutation and each direction, then judged by the blurred error of
+    each mutation and each direction, then scored by the blurred error of
     held-out integrands (1024 other Heavisides; 1024 Gaussians) against the
     random tile it started from."""
     from paper_2105_12620_amd import bnlat
@@ -114,7 +114,7 @@ def quality_experiment(sweeps: int) -> dict:
     held_g = bnlat.draw_gaussians(13, 0, 1024)
     u0 = synthgen.offsets(128, 128, seed=14)
 
-    def judge(u):
+    def score(u):
         with bnlat.create_problem(dict(w, t_heaviside=1024), held_h) as q:
             q.init_offsets(u)
             q.compute_errors()
@@ -125,7 +125,7 @@ def quality_experiment(sweeps: int) -> dict:
             qg = q.quality_metric(SIGMAS_B, rows=bnlat.BN_ROWS_GAUSSIAN)
         return qh, qg
 
-    base_h, base_g = judge(u0)
+    base_h, base_g = score(u0)
     out = {"sigmas_b": SIGMAS_B, "sweeps": sweeps,
            "random": {"heaviside": base_h.tolist(), "gaussian": base_g.tolist()}}
     for move, mname in ((bnlat.BN_REDRAW, "redraw"), (bnlat.BN_SWAP, "swap")):
@@ -139,7 +139,7 @@ def quality_experiment(sweeps: int) -> dict:
                 e1 = p.energy()
                 dt = time.perf_counter() - t0
                 u = p.get_offsets()
-            qh, qg = judge(u)
+            qh, qg = score(u)
             out[f"{mname}_{oname}"] = {
                 "energy_before": e0, "energy_after": e1, "accepts": st["accepts"], "seconds": dt,
                 "heaviside": qh.tolist(), "gaussian": qg.tolist(),

@@ -10,7 +10,7 @@
  *     Gaussian-windowed energy of Eq. (1);
  *   - Sec. 3.2: main sequence = 2D rank-1 lattice s^k = mod(Phi(k) g / N, 1),
  *     scrambled per pixel by the toroidal shift mod(s^k + u_p, 1) (Fig. 1a);
- *   - Sec. 3.3: a sampler is judged by the RMSE of its error tile after
+ *   - Sec. 3.3: a sampler is assessed by the RMSE of its error tile after
  *     Gaussian blurs of several sizes (Fig. 1c);
  *   - Sec. 3.4: the optimiser mutates disjoint pixel sets in parallel.
  *
