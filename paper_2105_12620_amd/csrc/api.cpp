@@ -806,7 +806,7 @@ std::string batch_key(bn_batch b) {
 // fastest.  Results do not depend on the choice.
 bn_status batch_tune(bn_batch b) {
   static const uint32_t tchs[] = {64, 128, 256, 512};
-  static const uint32_t slices[] = {256, 512, 1024, 2048};
+  static const uint32_t slices[] = {128, 256, 512, 1024, 2048};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

@@ -80,7 +80,7 @@ hipError_t launch_gauss_energy(const DevView& v, double* gsum, hipStream_t s);
 // batched launches: member i of a group owns blocks pre[i] .. pre[i+1]-1
 int count_kind(const DevView& v);
 uint32_t count_blocks(const DevView& v);
-uint32_t stage_by(uint32_t k);
+uint32_t stage_rows(uint32_t k);
 void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen);
 hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
                               uint32_t blocks, uint32_t kappa, hipStream_t s);

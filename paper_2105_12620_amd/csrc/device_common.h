@@ -14,6 +14,8 @@ namespace bnlat {
 namespace {
 
 typedef short v2i16 __attribute__((ext_vector_type(2)));
+// Native 4 x u32 vector: kept in registers where HIP's uint4 struct is not.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 
 // Philox4x32-10 (Salmon et al., SC 2011): two 32x32->64 products per round,
@@ -65,6 +67,14 @@ __device__ inline uint32_t wave_id() {
   return __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
+// Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8), each
+// with its own L2.  This renumbers them so that every XCD's workgroups form one
+// contiguous range of logical indices: neighbouring work then shares an L2.
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t g) {
+  const uint32_t x = b & 7, i = b >> 3, q = g >> 3, r = g & 7;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 __device__ inline uint32_t class_pixel(const DevView& v, uint32_t kappa, uint32_t j) {
   const uint32_t ky = kappa / v.k, kx = kappa - ky * v.k;
   const uint32_t a = j / v.cw, b = j - a * v.cw;
@@ -86,7 +96,8 @@ struct Window {
   int ox[M], oy[M], cls[M];
   int ncls;
   int d[DMAX + 1], csize[DMAX + 1];
-  constexpr Window() : ox(), oy(), cls(), ncls(0), d(), csize() {
+  int cmap[(2 * R + 1) * (2 * R + 1)];   // group of offset (x, y) at (y + R)(2R + 1) + x + R; -1 at (0, 0)
+  constexpr Window() : ox(), oy(), cls(), ncls(0), d(), csize(), cmap() {
     int idx = 0;
     for (int dd = 1; dd <= DMAX; ++dd) {
       int found = 0;
@@ -96,6 +107,7 @@ struct Window {
             ox[idx] = x;
             oy[idx] = y;
             cls[idx] = ncls;
+            cmap[(y + R) * (2 * R + 1) + x + R] = ncls;
             ++idx;
             ++found;
           }
@@ -105,6 +117,7 @@ struct Window {
         ++ncls;
       }
     }
+    cmap[R * (2 * R + 1) + R] = -1;
   }
 };
 

@@ -98,171 +98,196 @@ __global__ __launch_bounds__(256) void k_delta(DevView v, uint32_t kappa, uint32
 }
 
 // LDS-staged energy change for one colour phase.  A workgroup owns a block of
-// 32 x BY class pixels (one per thread) and a slice of the integrands.  For
-// 16 integrands at a time it stages the counts of the block plus its window
-// halo into LDS (region of RH x RW pixels, one plane per integrand pair), and
-// the class pixels' recounted rows.  Region columns are stored grouped by
-// their residue mod K, so the 32 lanes of a class row read 32 consecutive
-// words for every window offset (no bank conflicts), and every offset is a
-// compile-time displacement from the thread's own word.  The integer class
-// sums of the slice are added into xsum[class][pixel] with 64-bit integer
-// atomics (exact, so the order of the slices does not matter);
-// k_delta_finish takes the decision and clears xsum for the next phase.
-template <int R, int K, int BY, int PAIRS_>
+// 32 x (BY V) class pixels; thread (tx, ty) owns the V class pixels of column
+// tx in class rows ty V .. ty V + V - 1.  Their windows overlap, so each count
+// word the thread reads from LDS serves all of them.  The workgroup also owns
+// a slice of the integrands: for 8 integrands at a time it stages the counts of
+// its block plus the window halo (region of RH x RW pixels, 16 bytes each) and
+// the class pixels' recounted rows in LDS.  Region columns are grouped by
+// residue mod K, so the 32 lanes of a class row read 32 consecutive 16-byte
+// words for every window offset, each with one ds_read_b128 at a compile-time
+// offset from the thread's base.  Where the staging words fit in registers,
+// the next stage's global loads are issued before the current stage is
+// evaluated.  Class sums stay in int32 over a
+// slice: its length is bounded so that |sum_t dc_t c_q,t| < 2^31 for every
+// class; they are added into xsum[class][pixel] with 64-bit integer atomics
+// (exact, so the order of the slices does not matter); k_delta_finish takes
+// the decision and clears xsum.
+template <int R, int K, int BY, int V>
 struct StageGeom {
   static constexpr int BX = 32;
-  static constexpr int RH = K * BY + 2 * R;
-  static constexpr int RW = ((K * BX + 2 * R + K - 1) / K) * K;
+  static constexpr int CR = BY * V;                                // class rows per block
+  static constexpr int RH = K * (CR - 1) + 2 * R + 1;
+  static constexpr int RW = ((K * (BX - 1) + 2 * R + 1 + K - 1) / K) * K;
   static constexpr int RWK = RW / K;
-  static constexpr int RA = RH * RW;           // words per integrand-pair plane
-  static constexpr int PAIRS = PAIRS_;         // integrand pairs per stage (4 or 8)
-  static constexpr int V4 = PAIRS / 4;         // 16-byte loads per pixel per stage
-  static constexpr int NB = BX * BY;           // class pixels per block
-  static constexpr int LDS_WORDS = PAIRS * RA + PAIRS * NB;
-  // word displacement of region position (K*ty + R + oy, K*tx + R + ox) from
-  // that of (K*ty + R, tx) in the residue-grouped layout
-  static constexpr int disp(int ox, int oy) {
-    return oy * RW + ((R + ox) % K) * RWK + (R + ox) / K;
-  }
+  static constexpr int RA = RH * RW;                               // region pixels
+  static constexpr int NB = BX * CR;                               // class pixels per block
+  static constexpr int NT = BX * BY;                               // threads per block
+  static constexpr int DR = K * (V - 1) + 2 * R + 1;               // region rows one thread reads
+  static constexpr int LDS_BYTES = 16 * (RA + NB);
+  // word of region column K tx + R + ox relative to that of column K tx
+  static constexpr int dcol(int ox) { return ((R + ox) % K) * RWK + (R + ox) / K; }
 };
 
-template <int R, int K, int BY, int PAIRS>
+// Block shape of the staged kernel for K colour classes per axis and radius R:
+// class rows per thread (V) and thread rows (BY), within 64 KiB of LDS.
+template <int R, int K>
+struct StageShape {
+  static constexpr int V = (K == 4) ? 1 : 2;
+  static constexpr int BY = (K == 4) ? 2 : 8;
+};
+
+// Largest slice (a multiple of 8 integrands) whose class sums fit int32: every
+// product dc_t c_q,t is at most N^2 in size and a class has at most 12 offsets
+// for radii up to 6.
+inline uint32_t stage_max_slice(uint32_t n) {
+  const uint64_t per = (uint64_t)12 * n * n;
+  uint64_t t = 0x7FFFFFFFull / per;
+  t &= ~(uint64_t)7;
+  return t < 8 ? 8 : (t > 0x40000000u ? 0x40000000u : (uint32_t)t);
+}
+
+// Count changes of a 16-byte count word (8 integrands) as four int16 pairs, and
+// sum_t dc_t (c'_t + c_t) over the word.
+__device__ __forceinline__ int stage_dc(const u32x4 cn, const u32x4 co, uint32_t d[4]) {
+  int z = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int n0 = (int)(cn[k] & 0xFFFFu), n1 = (int)(cn[k] >> 16);
+    const int o0 = (int)(co[k] & 0xFFFFu), o1 = (int)(co[k] >> 16);
+    d[k] = ((uint32_t)(n0 - o0) & 0xFFFFu) | ((uint32_t)(n1 - o1) << 16);
+    z += (n0 - o0) * (n0 + o0) + (n1 - o1) * (n1 + o1);
+  }
+  return z;
+}
+
+template <int R, int K, int BY, int V>
 __device__ __forceinline__ void delta_stage_body(const DevView& v, uint32_t kappa, uint32_t trlen,
                                                  long long* __restrict__ xpart, uint32_t bkx,
                                                  uint32_t bky, uint32_t bkz) {
-  using G = StageGeom<R, K, BY, PAIRS>;
+  using G = StageGeom<R, K, BY, V>;
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
-  extern __shared__ uint32_t lds[];
-  uint32_t* reg = lds;
-  uint32_t* cnb = lds + G::PAIRS * G::RA;
+  constexpr int ITER = (G::RA + G::NT - 1) / G::NT;
+  constexpr bool PREFETCH = ITER <= 16;
+  constexpr int WS = 2 * R + 1;
+  extern __shared__ u32x4 lds4[];
+  u32x4* reg = lds4;                 // [RA] region counts
+  u32x4* cnb = lds4 + G::RA;         // [NB] recounted rows of the class pixels
   const uint32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const uint32_t a0 = bky * BY, b0 = bkx * G::BX;
-  const uint32_t a = a0 + ty, b = b0 + tx;
-  const bool active = (a < v.ch) && (b < v.cw);
+  const uint32_t a0 = bky * G::CR, b0 = bkx * G::BX;
+  const uint32_t b = b0 + tx;
   const uint32_t ky = kappa / K, kx = kappa - ky * K;
   // top-left region pixel, made non-negative modulo the tile
   const uint32_t ys = (ky + K * a0 + v.h * (R / v.h + 1) - R) % v.h;
   const uint32_t xs = (kx + K * b0 + v.w * (R / v.w + 1) - R) % v.w;
-  const int own = (K * ty + R) * G::RW + (R % K) * G::RWK + tx + R / K;
-  const int base = (K * ty + R) * G::RW + tx;
-  const bool small_n = v.n <= 2048;
+  const uint32_t P = v.w * v.h;
 
-  long long z0 = 0;
-  long long zd[NCLS];
+  // staging byte offsets: the region is the same for every stage.  Lanes past
+  // the region load pixel 0 and do not store it.
+  uint32_t poff[ITER], wi[ITER];
 #pragma unroll
-  for (int c = 0; c < NCLS; ++c) zd[c] = 0;
-
-  const uint32_t t_begin = bkz * trlen, t_end = min(t_begin + trlen, v.tp);
-  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 2 * G::PAIRS) {
-    __syncthreads();
-    {
-      // issue every staging load of this thread before the first LDS write
-      constexpr int NT = 32 * BY;
-      constexpr int ITER = (G::V4 * G::RA + NT - 1) / NT;
-      uint4 q[ITER];
-      uint32_t wi[ITER];
-#pragma unroll
-      for (int it = 0; it < ITER; ++it) {
-        const uint32_t i = threadIdx.x + it * NT;
-        wi[it] = 0xFFFFFFFFu;
-        q[it] = make_uint4(0, 0, 0, 0);
-        if (i < (uint32_t)(G::V4 * G::RA)) {
-          const uint32_t pix = G::V4 == 1 ? i : (i >> 1), half = G::V4 == 1 ? 0 : (i & 1);
-          const uint32_t rr = pix / G::RW, cc = pix - rr * G::RW;
-          uint32_t gy = ys + rr, gx = xs + cc;
-          while (gy >= v.h) gy -= v.h;
-          while (gx >= v.w) gx -= v.w;
-          q[it] = *(const uint4*)(v.cnt + tix(gy * v.w + gx, t0 + 8 * half, v.w * v.h));
-          wi[it] = rr * G::RW + (cc % K) * G::RWK + cc / K + 4 * half * G::RA;
-        }
-      }
-      constexpr int ITC = (G::V4 * G::NB + NT - 1) / NT;
-      uint4 qc[ITC];
-#pragma unroll
-      for (int it = 0; it < ITC; ++it) {
-        const uint32_t i = threadIdx.x + it * NT;
-        const uint32_t cp = G::V4 == 1 ? i : (i >> 1), half = G::V4 == 1 ? 0 : (i & 1);
-        const uint32_t aa = a0 + cp / G::BX, bb = b0 + cp % G::BX;
-        qc[it] = make_uint4(0, 0, 0, 0);
-        if (i < (uint32_t)(G::V4 * G::NB) && aa < v.ch && bb < v.cw)
-          qc[it] = *(const uint4*)(v.c_new + tix(aa * v.cw + bb, t0 + 8 * half, v.pc));
-      }
-#pragma unroll
-      for (int it = 0; it < ITER; ++it) {
-        if (wi[it] != 0xFFFFFFFFu) {
-          reg[wi[it]] = q[it].x;
-          reg[wi[it] + G::RA] = q[it].y;
-          reg[wi[it] + 2 * G::RA] = q[it].z;
-          reg[wi[it] + 3 * G::RA] = q[it].w;
-        }
-      }
-#pragma unroll
-      for (int it = 0; it < ITC; ++it) {
-        const uint32_t i = threadIdx.x + it * NT;
-        if (i < (uint32_t)(G::V4 * G::NB)) {
-          const uint32_t cp = G::V4 == 1 ? i : (i >> 1), half = G::V4 == 1 ? 0 : (i & 1);
-          const uint32_t wc = cp + 4 * half * G::NB;
-          cnb[wc] = qc[it].x;
-          cnb[wc + G::NB] = qc[it].y;
-          cnb[wc + 2 * G::NB] = qc[it].z;
-          cnb[wc + 3 * G::NB] = qc[it].w;
-        }
-      }
-    }
-    __syncthreads();
-    if (active) {
-      int z0p = 0;
-      int part[NCLS];
-#pragma unroll
-      for (int c = 0; c < NCLS; ++c) part[c] = 0;
-#pragma unroll
-      for (int tp = 0; tp < G::PAIRS; ++tp) {
-        const uint32_t cn = cnb[tp * G::NB + threadIdx.x];
-        const uint32_t co = reg[tp * G::RA + own];
-        const int n0 = (int)(cn & 0xFFFFu), n1 = (int)(cn >> 16);
-        const int o0 = (int)(co & 0xFFFFu), o1 = (int)(co >> 16);
-        const int dc0 = n0 - o0, dc1 = n1 - o1;
-        const uint32_t dcp = ((uint32_t)dc0 & 0xFFFFu) | ((uint32_t)dc1 << 16);
-        z0p += dc0 * (n0 + o0) + dc1 * (n1 + o1);
-#pragma unroll
-        for (int mm = 0; mm < W.M; ++mm) {
-          const uint32_t cq = reg[tp * G::RA + base + G::disp(W.ox[mm], W.oy[mm])];
-          part[W.cls[mm]] = dot2(dcp, cq, part[W.cls[mm]]);
-        }
-        if (!small_n) {
-#pragma unroll
-          for (int c = 0; c < NCLS; ++c) {
-            zd[c] += part[c];
-            part[c] = 0;
-          }
-          z0 += z0p;
-          z0p = 0;
-        }
-      }
-      z0 += z0p;
-#pragma unroll
-      for (int c = 0; c < NCLS; ++c) zd[c] += part[c];
+  for (int it = 0; it < ITER; ++it) {
+    const uint32_t i = threadIdx.x + it * G::NT;
+    poff[it] = 0;
+    wi[it] = 0xFFFFFFFFu;
+    if (i < (uint32_t)G::RA) {
+      const uint32_t rr = i / G::RW, cc = i - rr * G::RW;
+      uint32_t gy = ys + rr, gx = xs + cc;
+      while (gy >= v.h) gy -= v.h;
+      while (gx >= v.w) gx -= v.w;
+      poff[it] = (gy * v.w + gx) * 16;
+      wi[it] = rr * G::RW + (cc % K) * G::RWK + cc / K;
     }
   }
-  if (active) {
-    const uint32_t j = a * v.cw + b;
+  uint32_t coff[V];
+  bool act[V];
 #pragma unroll
-    for (int c = 0; c < NCLS; ++c)
-      atomicAdd((unsigned long long*)&xpart[(size_t)c * v.pc + j],
-                (unsigned long long)((long long)W.csize[c] * z0 - 2 * zd[c]));
+  for (int vv = 0; vv < V; ++vv) {
+    const uint32_t a = a0 + ty * V + vv;
+    act[vv] = (a < v.ch) && (b < v.cw);
+    coff[vv] = act[vv] ? (a * v.cw + b) * 16 : 0;
+  }
+  const uint32_t top = K * ty * V * G::RW + tx;
+
+  int z0[V];
+  int part[V][NCLS];
+#pragma unroll
+  for (int vv = 0; vv < V; ++vv) {
+    z0[vv] = 0;
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) part[vv][c] = 0;
+  }
+
+  const uint32_t t_begin = bkz * trlen, t_end = min(t_begin + trlen, v.tp);
+  u32x4 q[ITER], qc[V];
+  auto issue = [&](uint32_t t0) {
+    const char* cs = (const char*)(v.cnt + (size_t)(t0 >> 3) * P * 8);
+    const char* ns = (const char*)(v.c_new + (size_t)(t0 >> 3) * v.pc * 8);
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) q[it] = *(const u32x4*)(cs + poff[it]);
+#pragma unroll
+    for (int vv = 0; vv < V; ++vv) qc[vv] = *(const u32x4*)(ns + coff[vv]);
+  };
+  if (PREFETCH && t_begin < t_end) issue(t_begin);
+  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 8) {
+    __syncthreads();
+    if (!PREFETCH) issue(t0);
+#pragma unroll
+    for (int it = 0; it < ITER; ++it)
+      if (wi[it] != 0xFFFFFFFFu) reg[wi[it]] = q[it];
+#pragma unroll
+    for (int vv = 0; vv < V; ++vv) cnb[(ty * V + vv) * G::BX + tx] = qc[vv];
+    __syncthreads();
+    if (PREFETCH && t0 + 8 < t_end) issue(t0 + 8);
+    uint32_t d[V][4];
+#pragma unroll
+    for (int vv = 0; vv < V; ++vv)
+      z0[vv] += stage_dc(cnb[(ty * V + vv) * G::BX + tx], reg[top + (R + K * vv) * G::RW + G::dcol(0)], d[vv]);
+#pragma unroll
+    for (int dr = 0; dr < G::DR; ++dr) {
+      // a row's words are loaded together, so their LDS latencies overlap
+      u32x4 row[WS];
+#pragma unroll
+      for (int ox = -R; ox <= R; ++ox) row[ox + R] = reg[top + dr * G::RW + G::dcol(ox)];
+#pragma unroll
+      for (int ox = -R; ox <= R; ++ox) {
+        const u32x4 cq = row[ox + R];
+#pragma unroll
+        for (int vv = 0; vv < V; ++vv) {
+          const int oy = dr - R - K * vv;
+          if (oy < -R || oy > R || (ox == 0 && oy == 0)) continue;
+          const int c = W.cmap[(oy + R) * WS + ox + R];
+          int x = part[vv][c];
+          x = dot2(d[vv][0], cq[0], x);
+          x = dot2(d[vv][1], cq[1], x);
+          x = dot2(d[vv][2], cq[2], x);
+          part[vv][c] = dot2(d[vv][3], cq[3], x);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int vv = 0; vv < V; ++vv) {
+    if (act[vv]) {
+      const uint32_t j = (a0 + ty * V + vv) * v.cw + b;
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c)
+        atomicAdd((unsigned long long*)&xpart[(size_t)c * v.pc + j],
+                  (unsigned long long)((long long)W.csize[c] * z0[vv] - 2 * (long long)part[vv][c]));
+    }
   }
 }
 
-template <int R, int K, int BY, int PAIRS>
+template <int R, int K, int BY, int V>
 __global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kappa, uint32_t trlen,
                                                          long long* __restrict__ xpart) {
-  delta_stage_body<R, K, BY, PAIRS>(v, kappa, trlen, xpart, blockIdx.x, blockIdx.y, blockIdx.z);
+  delta_stage_body<R, K, BY, V>(v, kappa, trlen, xpart, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Batched form: member i owns blocks pre[i] .. pre[i+1]-1, laid out as its own
 // (x, y, slice) grid; its slice length is in trl[i].
-template <int R, int K, int BY, int PAIRS>
+template <int R, int K, int BY, int V>
 __global__ __launch_bounds__(32 * BY) void k_delta_stage_batch(const DevView* __restrict__ views,
                                                                const uint32_t* __restrict__ pre,
                                                                const uint32_t* __restrict__ geo,
@@ -271,7 +296,7 @@ __global__ __launch_bounds__(32 * BY) void k_delta_stage_batch(const DevView* __
   const DevView v = views[i];
   const uint32_t lb = blockIdx.x - pre[i];
   const uint32_t gx = geo[3 * i], gy = geo[3 * i + 1], trlen = geo[3 * i + 2];
-  delta_stage_body<R, K, BY, PAIRS>(v, kappa, trlen, v.xpart, lb % gx, (lb / gx) % gy, lb / (gx * gy));
+  delta_stage_body<R, K, BY, V>(v, kappa, trlen, v.xpart, lb % gx, (lb / gx) % gy, lb / (gx * gy));
 }
 
 // Decide from the summed class sums (one thread per pixel) and clear them.
@@ -848,14 +873,15 @@ __global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, ui
 
 // Gaussian rows' part of a move's energy change (plain form of Eq. (1) over
 // the window, FP64 arithmetic on the FP32 estimates); one wave per moved
-// pixel, lanes over integrands.  Written to gdelta[j]; the decision adds it to
-// the exact Heaviside part.
+// pixel, lanes over integrands, workgroups renumbered per XCD so that moved
+// pixels whose windows overlap read the shared rows through one L2.  Written
+// to gdelta[j]; the decision adds it to the exact Heaviside part.
 template <int R, int MODE>
 __global__ __launch_bounds__(256) void k_delta_gauss(DevView v, uint32_t kappa, uint32_t m) {
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t j = wave_id();
+  const uint32_t j = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
   if (j >= m) return;
   const uint32_t p = (MODE == MODE_CLASS) ? class_pixel(v, kappa, j) : v.pix_list[j];
   const uint32_t y = p / v.w, x = p - y * v.w;
@@ -951,32 +977,38 @@ hipError_t delta_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
   return hipGetLastError();
 }
 
-// Integrand slices for the staged kernel: enough workgroups to fill the chip.
-// Integrand slices: about 512 workgroups in total, each slice a whole number
-// of 16-integrand stages.
-inline uint32_t stage_slices(const DevView& v, uint32_t blocks, uint32_t* trlen) {
-  const uint32_t chunks = v.tp / 16;
+// Integrand slices of a staged launch: about slice_target workgroups in total
+// (512 by default), each slice a whole number of stages of `gran` integrands
+// (8 for the integer stencil, 16 for the matrix-core form), at least `min_len`
+// integrands long where the rows have that many and at most `cap` long.
+inline uint32_t stage_slices(const DevView& v, uint32_t blocks, uint32_t* trlen, uint32_t gran = 8,
+                             uint32_t cap = 0xFFFFFFFFu, uint32_t min_len = 0) {
+  const uint32_t chunks = v.tp / gran;
   const uint32_t target = v.slice_target ? v.slice_target : 512;
   uint32_t want = (target + blocks - 1) / blocks;
   if (want > chunks) want = chunks;
-  const uint32_t per = (chunks + want - 1) / want;
-  *trlen = per * 16;
+  uint32_t per = (chunks + want - 1) / want;
+  const uint32_t min_per = min(chunks, min_len / gran);
+  if (per < min_per) per = min_per;
+  const uint32_t cap_stages = cap / gran ? cap / gran : 1;
+  if (per > cap_stages) per = cap_stages;
+  *trlen = per * gran;
   return (chunks + per - 1) / per;
 }
 
-template <int R, int K, int BY>
+template <int R, int K>
 hipError_t stage_launch(const DevView& v, uint32_t kappa, long long* xpart, hipStream_t s) {
-  // 4 integrand pairs per stage: about 32 KiB of LDS per block, so several
-  // blocks share a CU and one block's staging overlaps another's compute
-  using G = StageGeom<R, K, BY, 4>;
-  static_assert(G::LDS_WORDS * 4 <= 65536, "staged block exceeds 64 KiB of LDS");
+  using S = StageShape<R, K>;
+  using G = StageGeom<R, K, S::BY, S::V>;
+  static_assert(G::LDS_BYTES <= 65536, "staged block exceeds 64 KiB of LDS");
   uint32_t trlen = 0;
-  const uint32_t blocks = ((v.cw + G::BX - 1) / G::BX) * ((v.ch + BY - 1) / BY);
-  const uint32_t ns = stage_slices(v, blocks, &trlen);
-  const dim3 grid((v.cw + G::BX - 1) / G::BX, (v.ch + BY - 1) / BY, ns);
-  const size_t lds = (size_t)G::LDS_WORDS * 4;
-  hipLaunchKernelGGL((k_delta_stage<R, K, BY, G::PAIRS>), grid, dim3(32 * BY), lds, s, v, kappa, trlen,
-                     xpart);
+  const uint32_t blocks = ((v.cw + G::BX - 1) / G::BX) * ((v.ch + G::CR - 1) / G::CR);
+  // slices of at least 64 integrands: each adds its class sums with atomics
+  // and restages the window halo
+  const uint32_t ns = stage_slices(v, blocks, &trlen, 8, stage_max_slice(v.n), 64);
+  const dim3 grid((v.cw + G::BX - 1) / G::BX, (v.ch + G::CR - 1) / G::CR, ns);
+  hipLaunchKernelGGL((k_delta_stage<R, K, S::BY, S::V>), grid, dim3(G::NT), (size_t)G::LDS_BYTES, s, v, kappa,
+                     trlen, xpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_delta_finish, dim3((v.pc + 255) / 256), dim3(256), 0, s, v, xpart);
@@ -986,9 +1018,9 @@ hipError_t stage_launch(const DevView& v, uint32_t kappa, long long* xpart, hipS
 template <int R>
 hipError_t stage_by_k(const DevView& v, uint32_t kappa, long long* xpart, hipStream_t s) {
   switch (v.k) {
-    case 1: return stage_launch<R, 1, 8>(v, kappa, xpart, s);
-    case 2: return stage_launch<R, 2, 8>(v, kappa, xpart, s);
-    case 4: return stage_launch<R, 4, 2>(v, kappa, xpart, s);
+    case 1: return stage_launch<R, 1>(v, kappa, xpart, s);
+    case 2: return stage_launch<R, 2>(v, kappa, xpart, s);
+    case 4: return stage_launch<R, 4>(v, kappa, xpart, s);
     default: return delta_dispatch<MODE_CLASS>(v, kappa, v.pc, s);
   }
 }
@@ -1009,7 +1041,7 @@ hipError_t mfma_launch(const DevView& v, uint32_t kappa, hipStream_t s) {
   using G = MfmaGeom<R, 4>;
   const uint32_t bx = (v.cw + G::BXC - 1) / G::BXC, by = (v.ch + G::BYC - 1) / G::BYC;
   uint32_t trlen = 0;
-  const uint32_t ns = stage_slices(v, bx * by, &trlen);
+  const uint32_t ns = stage_slices(v, bx * by, &trlen, 16);
   const size_t lds = (size_t)G::LDS_BYTES;
   hipLaunchKernelGGL((k_delta_mfma<R, G::BYC>), dim3(bx, by, ns), dim3(64 * G::BYC), lds, s, v, kappa, trlen,
                      v.xpart, v.unsure);
@@ -1172,13 +1204,14 @@ hipError_t launch_gauss_energy(const DevView& v, double* gsum, hipStream_t s) {
 
 // ------------------------------------------------------------------ batches
 
-uint32_t stage_by(uint32_t k) { return k == 4 ? 2 : 8; }
+uint32_t stage_rows(uint32_t k) { return k == 4 ? StageShape<1, 4>::BY * StageShape<1, 4>::V
+                                                : StageShape<1, 2>::BY * StageShape<1, 2>::V; }
 
 void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen) {
-  const uint32_t by = stage_by(v.k);
+  const uint32_t cr = stage_rows(v.k);
   *gx = (v.cw + 31) / 32;
-  *gy = (v.ch + by - 1) / by;
-  *gz = stage_slices(v, *gx * *gy, trlen);
+  *gy = (v.ch + cr - 1) / cr;
+  *gz = stage_slices(v, *gx * *gy, trlen, 8, stage_max_slice(v.n), 64);
 }
 
 
@@ -1186,9 +1219,12 @@ namespace {
 template <int R, int K>
 hipError_t stage_batch_rk(const DevView* views, const uint32_t* pre, const uint32_t* geo, uint32_t nmem,
                           uint32_t blocks, uint32_t kappa, hipStream_t s) {
-  constexpr int BY = K == 4 ? 2 : 8;
-  using G = StageGeom<R, K, BY, 4>;
-  hipLaunchKernelGGL((k_delta_stage_batch<R, K, BY, 4>), dim3(blocks), dim3(32 * BY), (size_t)G::LDS_WORDS * 4, s,
+  using S = StageShape<R, K>;
+  using G = StageGeom<R, K, S::BY, S::V>;
+  static_assert(G::CR == (K == 4 ? StageShape<1, 4>::BY * StageShape<1, 4>::V
+                                 : StageShape<1, 2>::BY * StageShape<1, 2>::V),
+                "batched geometry assumes one block shape per K");
+  hipLaunchKernelGGL((k_delta_stage_batch<R, K, S::BY, S::V>), dim3(blocks), dim3(G::NT), (size_t)G::LDS_BYTES, s,
                      views, pre, geo, nmem, kappa);
   return hipGetLastError();
 }

@@ -48,7 +48,6 @@ __device__ inline uint32_t swap_mask(const DevView& v, uint32_t kappa) {
 // in exact int64 atomics; per-lane int32 partial sums stay below 2^31 because
 // the host bounds a slice to S stages with S * 48 N^2 < 2^31 (at most 12
 // offsets per distance class, 4 integrands per lane per stage).
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <int R>
 struct SwapGeom {
