@@ -1047,28 +1047,30 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   v.ihp = ihp_d;
   v.area = area_d;
   v.wd = wd_d;
-  std::vector<double2> gmu(v.tgp, make_double2(0.0, 0.0));
-  std::vector<double> gscale(v.tgp, 0.0), gintp(v.tgp, 0.0);
+  // Gaussian t as exponent coefficients (base 2): with g = log2(e) / (2 s^2),
+  // -g |x - mu|^2 = a |x|^2 + bx x + by y + c, a = -g, (bx, by) = 2 g mu,
+  // c = -g |mu|^2.  Padding rows are all zero (estimate 1, integral 0).
+  std::vector<double> gcoef((size_t)v.tgp * 4, 0.0), gintp(v.tgp, 0.0);
   for (uint32_t t = 0; t < v.tg; ++t) {
-    gmu[t] = make_double2(gauss[t].mx, gauss[t].my);
-    gscale[t] = M_LOG2E / (2.0 * gauss[t].s * gauss[t].s);
+    const double g = M_LOG2E / (2.0 * gauss[t].s * gauss[t].s);
+    gcoef[4 * t] = -g;
+    gcoef[4 * t + 1] = 2.0 * g * gauss[t].mx;
+    gcoef[4 * t + 2] = 2.0 * g * gauss[t].my;
+    gcoef[4 * t + 3] = -g * (gauss[t].mx * gauss[t].mx + gauss[t].my * gauss[t].my);
     gintp[t] = gint[t];
   }
   if (v.tgp) {
-    double2* gmu_d;
-    double *gscale_d, *gint_d;
-    if ((s = p->alloc(&gmu_d, v.tgp)) != BN_OK || (s = p->alloc(&gscale_d, v.tgp)) != BN_OK ||
-        (s = p->alloc(&gint_d, v.tgp)) != BN_OK || (s = p->alloc(&v.gest, P * v.tgp)) != BN_OK ||
-        (s = p->alloc(&v.gerr, P * v.tgp)) != BN_OK || (s = p->alloc(&v.g_new, (size_t)v.pc * v.tgp)) != BN_OK ||
-        (s = p->alloc(&v.gdelta, v.pc)) != BN_OK || (s = p->alloc(&p->gsum, v.ncls)) != BN_OK) {
+    double *gcoef_d, *gint_d;
+    if ((s = p->alloc(&gcoef_d, (size_t)v.tgp * 4)) != BN_OK || (s = p->alloc(&gint_d, v.tgp)) != BN_OK ||
+        (s = p->alloc(&v.gest, P * v.tgp)) != BN_OK || (s = p->alloc(&v.gerr, P * v.tgp)) != BN_OK ||
+        (s = p->alloc(&v.g_new, (size_t)v.pc * v.tgp)) != BN_OK || (s = p->alloc(&v.gdelta, v.pc)) != BN_OK ||
+        (s = p->alloc(&p->gsum, v.ncls)) != BN_OK) {
       delete p;
       return s;
     }
-    v.gmu = gmu_d;
-    v.gscale = gscale_d;
+    v.gcoef = gcoef_d;
     v.gint = gint_d;
-    hipError_t ge = hipMemcpyAsync(gmu_d, gmu.data(), v.tgp * sizeof(double2), hipMemcpyHostToDevice, p->stream);
-    if (ge == hipSuccess) ge = hipMemcpyAsync(gscale_d, gscale.data(), v.tgp * 8, hipMemcpyHostToDevice, p->stream);
+    hipError_t ge = hipMemcpyAsync(gcoef_d, gcoef.data(), (size_t)v.tgp * 32, hipMemcpyHostToDevice, p->stream);
     if (ge == hipSuccess) ge = hipMemcpyAsync(gint_d, gintp.data(), v.tgp * 8, hipMemcpyHostToDevice, p->stream);
     if (ge != hipSuccess) {
       delete p;

@@ -49,8 +49,7 @@ struct DevView {
   uint32_t count_cap;        // workgroup cap of the sweep-wide recount launch (0: none)
   // Gaussian integrands (tgp = 0 when there are none)
   uint32_t tg, tgp;          // count, padded to 64
-  const double2* gmu;        // [tgp] centres
-  const double* gscale;      // [tgp] log2(e) / (2 s^2)  (0 for padding)
+  const double* gcoef;       // [tgp][4] exponent coefficients a, bx, by, c (base 2; 0 for padding)
   const double* gint;        // [tgp] exact integrals
   float* gest;               // [P][tgp] estimates
   float* gerr;               // [P][tgp] errors g - I (refreshed on demand)

@@ -806,22 +806,62 @@ __global__ __launch_bounds__(256) void k_blur_y_sq(DevView v, uint32_t pitch, ui
 
 // ----------------------------------------------------- Gaussian integrands
 // Low-frequency test integrands (Sec. 3.5): f_t(x) = exp(-|x - mu_t|^2 / (2 s_t^2)).
-// Estimates g = (1/N) sum_k f_t(s_p^k) per pixel, lanes over integrands and
-// wave-uniform samples.  The wave first writes its pixel's N sample
-// coordinates to LDS as floats (exact: Q0.16 values), then every lane reads
-// them by broadcast.  The centre is split into FP32 high and low parts: the
-// sample minus the high part is exact in FP32, so the offset is accurate to
-// one FP32 rounding of its size and the exponent to a relative 2^-22 or so;
-// exp2 runs in FP32, groups of eight terms are summed in FP32 and the groups
-// in FP64; the estimate is stored in FP32.
+// Estimates g = (1/N) sum_k f_t(s_p^k) per pixel.  A wave owns one pixel and
+// 16 Gaussians; its lanes hold the samples (8 per lane at a time, as FP64
+// x, y and |x|^2, all exact: Q0.16 coordinates) and the Gaussians' exponent
+// coefficients come from scalar registers, so a term costs three FP64 FMAs
+// (a |x|^2 + bx x + by y + c, the base-2 exponent -log2(e) |x - mu|^2 / (2 s^2),
+// accurate to FP64 rounding of terms below 600), one conversion to FP32,
+// v_exp_f32 (results below 2^-126 flush to zero, far below the estimate's
+// resolution) and one FP32 add.  Each lane sums its 8 terms of a Gaussian in
+// FP32 and the groups in FP64; the lanes' sums are added in FP64 through LDS.
+// The estimate is stored in FP32.
+template <bool CHECK>
+__device__ __forceinline__ void gauss_chunk(const DevView& v, uint32_t u, uint32_t c0, uint32_t lane,
+                                            const double* __restrict__ gc, double acc[16]) {
+  constexpr int SC = 8;
+  double sx[SC], sy[SC], s2[SC];
+  bool ok[SC];
+#pragma unroll
+  for (int k = 0; k < SC; ++k) {
+    const uint32_t i = c0 + 64 * k + lane;
+    ok[k] = !CHECK || i < v.n;
+    const uint32_t sv = wrap_add(v.lat[ok[k] ? i : 0], u);
+    sx[k] = (double)(sv & 0xFFFFu) * 0x1p-16;
+    sy[k] = (double)(sv >> 16) * 0x1p-16;
+    s2[k] = __fma_rn(sx[k], sx[k], sy[k] * sy[k]);
+  }
+  // two halves of 8 Gaussians: their 32 coefficients fit the scalar registers
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const double* gh = gc + 32 * h;
+    double cf[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) cf[i] = gh[i];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      const double a = cf[4 * g], bx = cf[4 * g + 1], by = cf[4 * g + 2], c = cf[4 * g + 3];
+      float part = 0.0f;
+#pragma unroll
+      for (int k = 0; k < SC; ++k) {
+        const double e = __fma_rn(a, s2[k], __fma_rn(bx, sx[k], __fma_rn(by, sy[k], c)));
+        const float f = __builtin_amdgcn_exp2f((float)e);
+        part = __fadd_rn(part, CHECK && !ok[k] ? 0.0f : f);
+      }
+      acc[8 * h + g] = __dadd_rn(acc[8 * h + g], (double)part);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, uint32_t m) {
-  constexpr uint32_t CH = 1024;                 // samples per LDS chunk
-  __shared__ float2 smp[4][CH];
+  constexpr uint32_t GB = 16, CH = 512;         // Gaussians per wave, samples per chunk
+  __shared__ double red[4][GB][65];
   const uint32_t lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
   const uint32_t wave = wave_id();
-  const uint32_t nch = v.tgp >> 6;
-  const uint32_t j = wave / nch, ch = wave - j * nch;
+  const uint32_t ngb = v.tgp / GB;
+  const uint32_t j = wave / ngb, gb = wave - j * ngb;
   if (j >= m) return;
   uint32_t u;
   float* out;
@@ -832,43 +872,26 @@ __global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, ui
     u = v.u_new[j];
     out = v.g_new + (size_t)j * v.tgp;
   }
-  float2* sw = smp[wl];
-  const uint32_t t = ch * 64 + lane;
-  const double2 mu = v.gmu[t];
-  const float mxh = (float)mu.x, myh = (float)mu.y;
-  const float mxl = (float)(mu.x - (double)mxh), myl = (float)(mu.y - (double)myh);
-  const float a = -(float)v.gscale[t];
-  double acc = 0.0;
-  for (uint32_t c0 = 0; c0 < v.n; c0 += CH) {
-    const uint32_t cn = min(CH, v.n - c0);
-    // this wave's samples c0 .. c0 + cn - 1 as floats; LDS operations of one
-    // wave complete in order, so the reads below see every lane's writes
-    for (uint32_t i = lane; i < cn; i += 64) {
-      const uint32_t sv = wrap_add(v.lat[c0 + i], u);
-      sw[i] = make_float2((float)(sv & 0xFFFFu) * 0x1p-16f, (float)(sv >> 16) * 0x1p-16f);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // v_exp_f32 directly: terms below 2^-126 flush to zero, far below the
-    // estimate's FP32 resolution
-    auto term = [&](uint32_t i) {
-      const float2 sp = sw[i];
-      const float dx = __fsub_rn(__fsub_rn(sp.x, mxh), mxl);
-      const float dy = __fsub_rn(__fsub_rn(sp.y, myh), myl);
-      return __builtin_amdgcn_exp2f(__fmul_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), a));
-    };
-    uint32_t i0 = 0;
-    for (; i0 + 8 <= cn; i0 += 8) {
-      float part = 0.0f;
+  const double* gc = v.gcoef + (size_t)gb * GB * 4;
+  double acc[GB];
 #pragma unroll
-      for (uint32_t i = 0; i < 8; ++i) part = __fadd_rn(part, term(i0 + i));
-      acc += (double)part;
-    }
-    for (; i0 < cn; ++i0) acc += (double)term(i0);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  }
-  out[t] = (float)(acc / (double)v.n);
+  for (uint32_t g = 0; g < GB; ++g) acc[g] = 0.0;
+  uint32_t c0 = 0;
+  for (; c0 + CH <= v.n; c0 += CH) gauss_chunk<false>(v, u, c0, lane, gc, acc);
+  if (c0 < v.n) gauss_chunk<true>(v, u, c0, lane, gc, acc);
+  // lane sums -> per-Gaussian totals: lane l adds 16 of Gaussian l % 16's
+  // lane sums, then the four quarters are added across lanes
+#pragma unroll
+  for (uint32_t g = 0; g < GB; ++g) red[wl][g][lane] = acc[g];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t g = lane & 15, q = lane >> 4;
+  double t = 0.0;
+#pragma unroll
+  for (uint32_t k = 0; k < 16; ++k) t = __dadd_rn(t, red[wl][g][16 * q + k]);
+  t = __dadd_rn(t, __shfl_xor(t, 16));
+  t = __dadd_rn(t, __shfl_xor(t, 32));
+  if (lane < GB) out[gb * GB + g] = (float)(t / (double)v.n);
 }
 
 // Gaussian rows' part of a move's energy change (plain form of Eq. (1) over
@@ -898,6 +921,88 @@ __global__ __launch_bounds__(256) void k_delta_gauss(DevView v, uint32_t kappa, 
       cs[W.cls[mm]] += d * (sm - 2.0 * (double)v.gest[(size_t)q * v.tgp + t]);
     }
   }
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) {
+    double xv = cs[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
+    acc += v.wd[c] * xv;
+  }
+  if (lane == 0) v.gdelta[j] = 2.0 * acc;
+}
+
+// Colour-phase form of the same sum: a workgroup owns 4 x 2 class pixels (one
+// wave each) and, for 64 Gaussians at a time, stages the estimate rows of
+// their window region ((K + 2r + 1) x (3K + 2r + 1) pixels) in LDS, so that
+// each row is read from memory once per workgroup rather than once per moved
+// pixel.  Same arithmetic and summation order as k_delta_gauss.
+template <int R, int K>
+struct GaussStage {
+  static constexpr int BCX = 4, BCY = 2, NW = BCX * BCY;
+  static constexpr int RH = K * (BCY - 1) + 2 * R + 1;
+  static constexpr int RW = K * (BCX - 1) + 2 * R + 1;
+  static constexpr int RA = RH * RW;
+  static constexpr int LDS_BYTES = RA * 64 * 4;
+};
+
+template <int R, int K>
+__global__ __launch_bounds__(512) void k_delta_gauss_stage(DevView v, uint32_t kappa) {
+  using G = GaussStage<R, K>;
+  constexpr Window<R> W = WinConst<R>::w;
+  constexpr int NCLS = WinConst<R>::NCLS;
+  constexpr int NT = 64 * G::NW;
+  constexpr int ITER = (G::RA * 16 + NT - 1) / NT;
+  extern __shared__ float gl[];                  // [RA][64] estimates of the region
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t a0 = blockIdx.y * G::BCY, b0 = blockIdx.x * G::BCX;
+  const uint32_t cy = w / G::BCX, cx = w - cy * G::BCX;
+  const uint32_t a = a0 + cy, b = b0 + cx;
+  const bool act = (a < v.ch) && (b < v.cw);
+  const uint32_t j = act ? a * v.cw + b : 0;
+  const uint32_t ky = kappa / K, kx = kappa - ky * K;
+  const uint32_t ys = (ky + K * a0 + v.h * (R / v.h + 1) - R) % v.h;
+  const uint32_t xs = (kx + K * b0 + v.w * (R / v.w + 1) - R) % v.w;
+  // staging: float4 it of a thread is quad (idx & 15) of region pixel idx >> 4
+  // (threads past the region reload its last pixel and do not store it)
+  uint32_t goff[ITER];
+#pragma unroll
+  for (int it = 0; it < ITER; ++it) {
+    const uint32_t idx = threadIdx.x + it * NT;
+    const uint32_t r = min(idx >> 4, (uint32_t)G::RA - 1);
+    const uint32_t rr = r / G::RW, cc = r - rr * G::RW;
+    uint32_t gy = ys + rr, gx = xs + cc;
+    while (gy >= v.h) gy -= v.h;
+    while (gx >= v.w) gx -= v.w;
+    goff[it] = gy * v.w + gx;
+  }
+  const int own = (K * cy + R) * G::RW + K * cx + R;
+  double cs[NCLS];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) cs[c] = 0.0;
+  for (uint32_t base = 0; base < v.tgp; base += 64) {
+    f32x4 q[ITER];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it)
+      q[it] = *(const f32x4*)(v.gest + (size_t)goff[it] * v.tgp + base + 4 * ((threadIdx.x + it * NT) & 15));
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const uint32_t idx = threadIdx.x + it * NT;
+      if (idx < (uint32_t)G::RA * 16) *(f32x4*)&gl[idx * 4] = q[it];
+    }
+    __syncthreads();
+    if (act) {
+      const double gn = v.g_new[(size_t)j * v.tgp + base + lane], go = gl[own * 64 + lane];
+      const double d = gn - go, sm = gn + go;
+#pragma unroll
+      for (int mm = 0; mm < W.M; ++mm) {
+        const int q = own + W.oy[mm] * G::RW + W.ox[mm];
+        cs[W.cls[mm]] += d * (sm - 2.0 * (double)gl[q * 64 + lane]);
+      }
+    }
+  }
+  if (!act) return;
   double acc = 0.0;
 #pragma unroll
   for (int c = 0; c < NCLS; ++c) {
@@ -1142,7 +1247,7 @@ hipError_t launch_blur(const DevView& v, const float* field, uint32_t pitch, uin
 
 hipError_t launch_gauss_est(const DevView& v, int mode, uint32_t m, hipStream_t s) {
   if (!v.tgp || m == 0) return hipSuccess;
-  const uint64_t waves = (uint64_t)m * (v.tgp >> 6);
+  const uint64_t waves = (uint64_t)m * (v.tgp >> 4);
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
   if (mode == MODE_ALL) hipLaunchKernelGGL(k_gauss_est<MODE_ALL>, grid, block, 0, s, v, 0u, m);
   else hipLaunchKernelGGL(k_gauss_est<MODE_CLASS>, grid, block, 0, s, v, 0u, m);
@@ -1164,10 +1269,43 @@ hipError_t gauss_delta_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hi
   }
   return hipGetLastError();
 }
+
+template <int R, int K>
+hipError_t gauss_stage_launch(const DevView& v, uint32_t kappa, hipStream_t s) {
+  using G = GaussStage<R, K>;
+  if constexpr (G::LDS_BYTES > 65536) {
+    return gauss_delta_dispatch<MODE_CLASS>(v, kappa, v.pc, s);
+  } else {
+    const dim3 grid((v.cw + G::BCX - 1) / G::BCX, (v.ch + G::BCY - 1) / G::BCY);
+    hipLaunchKernelGGL((k_delta_gauss_stage<R, K>), grid, dim3(64 * G::NW), (size_t)G::LDS_BYTES, s, v, kappa);
+    return hipGetLastError();
+  }
+}
+
+template <int R>
+hipError_t gauss_stage_by_k(const DevView& v, uint32_t kappa, hipStream_t s) {
+  switch (v.k) {
+    case 1: return gauss_stage_launch<R, 1>(v, kappa, s);
+    case 2: return gauss_stage_launch<R, 2>(v, kappa, s);
+    case 4: return gauss_stage_launch<R, 4>(v, kappa, s);
+    default: return gauss_delta_dispatch<MODE_CLASS>(v, kappa, v.pc, s);
+  }
+}
 }  // namespace
 
 hipError_t launch_gauss_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
   if (!v.tgp || m == 0) return hipSuccess;
+  if (mode == MODE_CLASS) {
+    switch (v.radius) {
+      case 1: return gauss_stage_by_k<1>(v, kappa, s);
+      case 2: return gauss_stage_by_k<2>(v, kappa, s);
+      case 3: return gauss_stage_by_k<3>(v, kappa, s);
+      case 4: return gauss_stage_by_k<4>(v, kappa, s);
+      case 5: return gauss_stage_by_k<5>(v, kappa, s);
+      case 6: return gauss_stage_by_k<6>(v, kappa, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   return mode == MODE_CLASS ? gauss_delta_dispatch<MODE_CLASS>(v, kappa, m, s)
                             : gauss_delta_dispatch<MODE_LIST>(v, kappa, m, s);
 }

@@ -21,6 +21,14 @@ MIX = {
     "mix_n256_bf16": workload(n=256, g=(1, 79), width=16, height=16, t_heaviside=48, t_gauss=64, radius=4,
                               precision=1),
     "mix_ascend": workload(n=64, g=(1, 19), width=16, height=8, t_heaviside=16, t_gauss=24, objective=-1),
+    # several LDS-staged workgroups, ragged Gaussian rows (130 of 192)
+    "mix_r5_wide": workload(n=64, g=(1, 19), width=64, height=32, t_heaviside=16, t_gauss=130, radius=5),
+    # region too large for the staged Gaussian kernel: per-pixel form
+    "mix_k4_r6": workload(n=64, g=(1, 19), width=16, height=16, t_heaviside=8, t_gauss=20, radius=6,
+                          colour_k=4),
+    "mix_k1": workload(n=16, g=(1, 7), width=8, height=8, t_heaviside=6, t_gauss=12, radius=2, colour_k=1),
+    # estimates over whole 512-sample chunks (smaller N take the masked tail)
+    "mix_n1024": workload(n=1024, g=(1, 381), width=8, height=8, t_heaviside=8, t_gauss=40, radius=2),
 }
 
 
