@@ -141,48 +141,83 @@ __global__ __launch_bounds__(256) void k_count_points_batch(const DevView* __res
   count_points_body<PPL, MODE_CLASS>(v, v.ihp, kappa, v.pc, v.tch, blockIdx.x - pre[i]);
 }
 
-// k_count_integrands (N < 64): lanes hold 64 integrands of one pixel and walk
-// the N samples, which are wave-uniform.
-template <int MODE>
-__device__ __forceinline__ void count_integrands_body(const DevView& v, uint32_t kappa, uint32_t m,
-                                                      uint32_t blk) {
+// k_count_pixels (N < 64): lanes hold 64 consecutive work items (pixels or
+// proposals), each with its N samples in registers; a wave walks 64
+// integrands with wave-uniform parameters from scalar loads and, per 8
+// integrands, stores each lane's 8 counts as one 16-byte tile piece.  Per
+// (sample, integrand): one v_dot2, one compare and one add.
+template <int NS, int MODE>
+__device__ __forceinline__ void count_pixels_body(const DevView& v, uint32_t kappa, uint32_t m, uint32_t blk) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
   const uint32_t nch = v.tp >> 6;
-  const uint32_t j = wave / nch, ch = wave - j * nch;
-  if (j >= m) return;
+  const uint32_t jg = wave / nch, ch = wave - jg * nch;
+  const uint32_t j = jg * 64 + lane;
+  if (jg * 64 >= m || j >= m) return;
   uint32_t p, u, row, rows;
   uint16_t* buf;
   count_target<MODE>(v, kappa, j, m, p, u, buf, row, rows);
-  if ((MODE == MODE_CLASS || MODE == MODE_SWEEP) && ch == 0 && lane == 0) v.u_new[j] = u;
-  const uint32_t t = ch * 64 + lane;
-  const int2 q = v.ihp[t];
-  int c = 0;
-  for (uint32_t i = 0; i < v.n; ++i) c += dot2((uint32_t)q.x, centre(wrap_add(v.lat[i], u)), 0) > q.y;
-  buf[tix(row, t, rows)] = (uint16_t)c;
-  if (MODE == MODE_ALL) v.err[(size_t)p * v.tp + t] = (float)c * (1.0f / (float)v.n) - v.area[t];
+  if ((MODE == MODE_CLASS || MODE == MODE_SWEEP) && ch == 0) v.u_new[j] = u;
+  uint32_t sp[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) sp[k] = centre(wrap_add(v.lat[k], u));
+  const float inv_n = 1.0f / (float)NS;
+  const int4* ip = (const int4*)(v.ihp + ch * 64);
+#pragma unroll 1
+  for (int tt = 0; tt < 8; ++tt) {
+    const int4 q0 = ip[4 * tt], q1 = ip[4 * tt + 1], q2 = ip[4 * tt + 2], q3 = ip[4 * tt + 3];
+    const int nn[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
+    const int dd[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+    uint32_t c[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      uint32_t x = 0;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) x += dot2((uint32_t)nn[i], sp[k], 0) > dd[i] ? 1u : 0u;
+      c[i] = x;
+    }
+    const uint32_t t = ch * 64 + 8 * tt;
+    *(uint4*)(buf + tix(row, t, rows)) =
+        make_uint4(c[0] | (c[1] << 16), c[2] | (c[3] << 16), c[4] | (c[5] << 16), c[6] | (c[7] << 16));
+    if (MODE == MODE_ALL) {
+      float* e = v.err + (size_t)p * v.tp + t;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) e[i] = (float)c[i] * inv_n - v.area[t + i];
+    }
+  }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_count_integrands(DevView v, uint32_t kappa, uint32_t m) {
-  count_integrands_body<MODE>(v, kappa, m, blockIdx.x);
+template <int NS, int MODE>
+__global__ __launch_bounds__(256) void k_count_pixels(DevView v, uint32_t kappa, uint32_t m) {
+  count_pixels_body<NS, MODE>(v, kappa, m, blockIdx.x);
 }
 
-__global__ __launch_bounds__(256) void k_count_integrands_batch(const DevView* __restrict__ views,
-                                                                const uint32_t* __restrict__ pre,
-                                                                uint32_t nmem, uint32_t kappa) {
+template <int NS>
+__global__ __launch_bounds__(256) void k_count_pixels_batch(const DevView* __restrict__ views,
+                                                            const uint32_t* __restrict__ pre, uint32_t nmem,
+                                                            uint32_t kappa) {
   const uint32_t i = batch_member(pre, nmem, blockIdx.x);
   const DevView v = views[i];
-  count_integrands_body<MODE_CLASS>(v, kappa, v.pc, blockIdx.x - pre[i]);
+  count_pixels_body<NS, MODE_CLASS>(v, kappa, v.pc, blockIdx.x - pre[i]);
 }
+
+// waves of a k_count_pixels launch over m work items
+inline uint64_t count_pixel_waves(const DevView& v, uint32_t m) { return (uint64_t)((m + 63) / 64) * (v.tp >> 6); }
 
 template <int MODE>
 hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStream_t s) {
   if (m == 0) return hipSuccess;
   if (v.n < 64) {
-    const uint64_t waves = (uint64_t)m * (v.tp >> 6);
-    hipLaunchKernelGGL(k_count_integrands<MODE>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s,
-                       v, kappa, m);
+    const dim3 g((unsigned)((count_pixel_waves(v, m) + 3) / 4)), b(256);
+    switch (v.n) {
+      case 1: hipLaunchKernelGGL((k_count_pixels<1, MODE>), g, b, 0, s, v, kappa, m); break;
+      case 2: hipLaunchKernelGGL((k_count_pixels<2, MODE>), g, b, 0, s, v, kappa, m); break;
+      case 4: hipLaunchKernelGGL((k_count_pixels<4, MODE>), g, b, 0, s, v, kappa, m); break;
+      case 8: hipLaunchKernelGGL((k_count_pixels<8, MODE>), g, b, 0, s, v, kappa, m); break;
+      case 16: hipLaunchKernelGGL((k_count_pixels<16, MODE>), g, b, 0, s, v, kappa, m); break;
+      case 32: hipLaunchKernelGGL((k_count_pixels<32, MODE>), g, b, 0, s, v, kappa, m); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   const uint32_t tch = v.tch;
@@ -212,17 +247,19 @@ hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
   }
 }
 
+// Launch kind of a batch member's recount: N itself below 64 (one kernel per
+// N), 64 + samples per lane from 64 on.
 int count_kind(const DevView& v) {
-  if (v.n < 64) return 0;
+  if (v.n < 64) return (int)v.n;
   switch (v.n) {
-    case 64: return 1;
-    case 128: return 2;
-    default: return 4;
+    case 64: return 65;
+    case 128: return 66;
+    default: return 68;
   }
 }
 
 uint32_t count_blocks(const DevView& v) {
-  if (v.n < 64) return (uint32_t)(((uint64_t)v.pc * (v.tp >> 6) + 3) / 4);
+  if (v.n < 64) return (uint32_t)((count_pixel_waves(v, v.pc) + 3) / 4);
   const uint64_t waves = (uint64_t)v.pc * ((v.tp + v.tch - 1) / v.tch);
   return (uint32_t)((waves + 3) / 4);
 }
@@ -231,10 +268,16 @@ hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pr
                               uint32_t blocks, uint32_t kappa, hipStream_t s) {
   const dim3 grid(blocks), block(256);
   switch (kind) {
-    case 0: hipLaunchKernelGGL(k_count_integrands_batch, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 1: hipLaunchKernelGGL(k_count_points_batch<1>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 2: hipLaunchKernelGGL(k_count_points_batch<2>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    default: hipLaunchKernelGGL(k_count_points_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 1: hipLaunchKernelGGL(k_count_pixels_batch<1>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 2: hipLaunchKernelGGL(k_count_pixels_batch<2>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 4: hipLaunchKernelGGL(k_count_pixels_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 8: hipLaunchKernelGGL(k_count_pixels_batch<8>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 16: hipLaunchKernelGGL(k_count_pixels_batch<16>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 32: hipLaunchKernelGGL(k_count_pixels_batch<32>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 65: hipLaunchKernelGGL(k_count_points_batch<1>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 66: hipLaunchKernelGGL(k_count_points_batch<2>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 68: hipLaunchKernelGGL(k_count_points_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
