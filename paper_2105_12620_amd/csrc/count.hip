@@ -56,7 +56,7 @@ __device__ inline void count_target(const DevView& v, uint32_t kappa, uint32_t j
 // Estimator of the test-integrand map (Sec. 2): c[p][t] = number of the N
 // scrambled samples on the hit side of Heaviside t.
 //
-// k_count_points (N >= 64): the 64 lanes of a wave hold 64*PPL samples of one
+// k_count_points (N >= 128): the 64 lanes of a wave hold 64*PPL samples of one
 // pixel (PPL per lane); the wave walks integrands with wave-uniform
 // parameters in scalar registers.  Per (sample, integrand): one v_dot2 and
 // one v_cmp; the 64 predicate bits of a compare are counted with a scalar
@@ -141,11 +141,12 @@ __global__ __launch_bounds__(256) void k_count_points_batch(const DevView* __res
   count_points_body<PPL, MODE_CLASS>(v, v.ihp, kappa, v.pc, v.tch, blockIdx.x - pre[i]);
 }
 
-// k_count_pixels (N < 64): lanes hold 64 consecutive work items (pixels or
+// k_count_pixels (N <= 64): lanes hold 64 consecutive work items (pixels or
 // proposals), each with its N samples in registers; a wave walks 64
 // integrands with wave-uniform parameters from scalar loads and, per 8
 // integrands, stores each lane's 8 counts as one 16-byte tile piece.  Per
-// (sample, integrand): one v_dot2, one compare and one add.
+// two (sample, integrand) pairs: two v_dot2 (threshold folded in), two shifts
+// and one three-way add.
 template <int NS, int MODE>
 __device__ __forceinline__ void count_pixels_body(const DevView& v, uint32_t kappa, uint32_t m, uint32_t blk) {
   const uint32_t lane = threadIdx.x & 63;
@@ -168,13 +169,20 @@ __device__ __forceinline__ void count_pixels_body(const DevView& v, uint32_t kap
     const int4 q0 = ip[4 * tt], q1 = ip[4 * tt + 1], q2 = ip[4 * tt + 2], q3 = ip[4 * tt + 3];
     const int nn[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
     const int dd[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+    // n.s > D' exactly when r = n.s - D' - 1 >= 0 (|n.s|, |D'| <= 2^30, so r
+    // never overflows): misses are the sign bits, summed three at a time
     uint32_t c[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      uint32_t x = 0;
+      const int thr = -dd[i] - 1;
+      uint32_t miss = 0;
 #pragma unroll
-      for (int k = 0; k < NS; ++k) x += dot2((uint32_t)nn[i], sp[k], 0) > dd[i] ? 1u : 0u;
-      c[i] = x;
+      for (int k = 0; k < NS; k += 2) {
+        const uint32_t r0 = (uint32_t)dot2((uint32_t)nn[i], sp[k], thr) >> 31;
+        const uint32_t r1 = k + 1 < NS ? (uint32_t)dot2((uint32_t)nn[i], sp[k + 1], thr) >> 31 : 0u;
+        miss = miss + r0 + r1;
+      }
+      c[i] = NS - miss;
     }
     const uint32_t t = ch * 64 + 8 * tt;
     *(uint4*)(buf + tix(row, t, rows)) =
@@ -207,7 +215,7 @@ inline uint64_t count_pixel_waves(const DevView& v, uint32_t m) { return (uint64
 template <int MODE>
 hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  if (v.n < 64) {
+  if (v.n <= 64) {
     const dim3 g((unsigned)((count_pixel_waves(v, m) + 3) / 4)), b(256);
     switch (v.n) {
       case 1: hipLaunchKernelGGL((k_count_pixels<1, MODE>), g, b, 0, s, v, kappa, m); break;
@@ -216,6 +224,7 @@ hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
       case 8: hipLaunchKernelGGL((k_count_pixels<8, MODE>), g, b, 0, s, v, kappa, m); break;
       case 16: hipLaunchKernelGGL((k_count_pixels<16, MODE>), g, b, 0, s, v, kappa, m); break;
       case 32: hipLaunchKernelGGL((k_count_pixels<32, MODE>), g, b, 0, s, v, kappa, m); break;
+      case 64: hipLaunchKernelGGL((k_count_pixels<64, MODE>), g, b, 0, s, v, kappa, m); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -226,7 +235,6 @@ hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
   const uint32_t nb = (MODE == MODE_SWEEP && v.count_cap) ? std::min(vb, v.count_cap) : vb;
   const dim3 grid(nb), block(256);
   switch (v.n) {
-    case 64: hipLaunchKernelGGL((k_count_points<1, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
     case 128: hipLaunchKernelGGL((k_count_points<2, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
     // N >= 256: four samples per lane, N / 256 sample groups (more samples
     // per lane would keep more compare masks live than the scalar registers
@@ -247,19 +255,15 @@ hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
   }
 }
 
-// Launch kind of a batch member's recount: N itself below 64 (one kernel per
-// N), 64 + samples per lane from 64 on.
+// Launch kind of a batch member's recount: N itself up to 64 (one kernel per
+// N), 64 + samples per lane above.
 int count_kind(const DevView& v) {
-  if (v.n < 64) return (int)v.n;
-  switch (v.n) {
-    case 64: return 65;
-    case 128: return 66;
-    default: return 68;
-  }
+  if (v.n <= 64) return (int)v.n;
+  return v.n == 128 ? 66 : 68;
 }
 
 uint32_t count_blocks(const DevView& v) {
-  if (v.n < 64) return (uint32_t)((count_pixel_waves(v, v.pc) + 3) / 4);
+  if (v.n <= 64) return (uint32_t)((count_pixel_waves(v, v.pc) + 3) / 4);
   const uint64_t waves = (uint64_t)v.pc * ((v.tp + v.tch - 1) / v.tch);
   return (uint32_t)((waves + 3) / 4);
 }
@@ -274,7 +278,7 @@ hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pr
     case 8: hipLaunchKernelGGL(k_count_pixels_batch<8>, grid, block, 0, s, views, pre, nmem, kappa); break;
     case 16: hipLaunchKernelGGL(k_count_pixels_batch<16>, grid, block, 0, s, views, pre, nmem, kappa); break;
     case 32: hipLaunchKernelGGL(k_count_pixels_batch<32>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 65: hipLaunchKernelGGL(k_count_points_batch<1>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 64: hipLaunchKernelGGL(k_count_pixels_batch<64>, grid, block, 0, s, views, pre, nmem, kappa); break;
     case 66: hipLaunchKernelGGL(k_count_points_batch<2>, grid, block, 0, s, views, pre, nmem, kappa); break;
     case 68: hipLaunchKernelGGL(k_count_points_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
     default: return hipErrorInvalidValue;
