@@ -758,7 +758,7 @@ bn_status batch_upload(bn_batch b) {
   for (BatchGroup& g : b->stage_groups)
     if ((s = upload(g, [](const DevView&) { return 0u; }, true)) != BN_OK) return s;
   if ((s = upload(b->finish_all, [](const DevView& v) { return (v.pc + 255) / 256; }, false)) != BN_OK) return s;
-  if ((s = upload(b->commit_all, [](const DevView& v) { return (v.pc + 3) / 4; }, false)) != BN_OK) return s;
+  if ((s = upload(b->commit_all, [](const DevView& v) { return commit_blocks(v); }, false)) != BN_OK) return s;
   return BN_OK;
 }
 

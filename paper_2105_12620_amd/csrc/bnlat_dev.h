@@ -62,6 +62,7 @@ hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
 hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s);
 uint32_t xpart_words(const DevView& v);
 hipError_t launch_commit(const DevView& v, uint32_t kappa, hipStream_t s);
+uint32_t commit_blocks(const DevView& v);
 hipError_t launch_errors(const DevView& v, hipStream_t s);
 hipError_t launch_advance(const DevView& v, hipStream_t s);
 hipError_t launch_points(const DevView& v, uint32_t pixel, uint32_t* out, hipStream_t s);
