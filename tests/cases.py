@@ -19,7 +19,9 @@ def workload(name=None, **kw):
 
 EDGE = {
     "n1": workload(n=1, g=(1, 1), t_heaviside=5),
+    "n2": workload(n=2, g=(1, 1), t_heaviside=33),
     "n4_ragged": workload(n=4, g=(1, 3), t_heaviside=70),
+    "n8": workload(n=8, g=(1, 3), t_heaviside=70, radius=2),
     "n32": workload(n=32, g=(1, 13), t_heaviside=40),
     "n128": workload(n=128, g=(1, 45), t_heaviside=130, width=8, height=8, radius=2),
     "n256_r4": workload(n=256, g=(1, 79), t_heaviside=200, width=12, height=12, radius=4),
