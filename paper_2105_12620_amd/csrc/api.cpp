@@ -996,7 +996,7 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   v.objective = cfg->objective;
   v.radius = cfg->radius;
   v.ncls = (uint32_t)p->cls_d.size();
-  v.tch = std::min<uint32_t>(256, v.tp);
+  v.tch = std::min<uint32_t>(1024, v.tp);   // integrands per counting wave (fewer for small launches)
   v.slice_target = 512;
   // The BF16 colour phases share the CUs with the sweep-wide recount; capping
   // the recount at six workgroups per CU (24 of 32 wave slots) measured 13 %

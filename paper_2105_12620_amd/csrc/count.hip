@@ -235,7 +235,11 @@ hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
     }
     return hipGetLastError();
   }
-  const uint32_t tch = v.tch;
+  // integrands per wave: v.tch (whole rows at T <= 1024 by default: the
+  // proposal and samples are set up once per wave), halved while the launch
+  // would hold fewer than 8192 waves
+  uint32_t tch = v.tch;
+  while (tch > 64 && (uint64_t)m * ((v.tp + tch - 1) / tch) < 8192) tch >>= 1;
   const uint64_t waves = (uint64_t)m * ((v.tp + tch - 1) / tch);
   const uint32_t vb = (uint32_t)((waves + 3) / 4);
   const uint32_t nb = (MODE == MODE_SWEEP && v.count_cap) ? std::min(vb, v.count_cap) : vb;
