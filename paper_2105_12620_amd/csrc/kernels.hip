@@ -620,21 +620,26 @@ __global__ __launch_bounds__(256) void k_delta_recheck(DevView v, uint32_t kappa
 // ------------------------------------------------------------------ commit
 // Accepted moves of the phase become the state (Sec. 3.4): offset and hit
 // counts of the pixel (error vectors are refreshed from the counts on
-// demand).  One thread per (8-integrand tile, class pixel), pixels fastest,
-// so that the proposal rows are read coalesced.
+// demand).  A thread copies CT consecutive 8-integrand tiles of one class
+// pixel; pixels are fastest across the threads, so every tile's proposal rows
+// are read coalesced.
+constexpr uint32_t CT = 8;
 __device__ __forceinline__ void commit_body(const DevView& v, uint32_t kappa, uint32_t blk) {
-  const uint64_t ntt = v.tp >> 3;
+  const uint32_t ngrp = ((v.tp >> 3) + CT - 1) / CT;
   const uint64_t i = (uint64_t)blk * 256 + threadIdx.x;
-  const bool in = i < (uint64_t)v.pc * ntt;
-  const uint32_t tt = in ? (uint32_t)(i / v.pc) : 0, j = in ? (uint32_t)(i - (uint64_t)tt * v.pc) : 0;
+  const bool in = i < (uint64_t)v.pc * ngrp;
+  const uint32_t g = in ? (uint32_t)(i / v.pc) : 0, j = in ? (uint32_t)(i - (uint64_t)g * v.pc) : 0;
   const bool acc = in && v.accept[j];
-  // one counter update per wave for the accepted pixels it holds at tile 0
-  const unsigned long long first = __ballot(acc && tt == 0);
+  // one counter update per wave for the accepted pixels it holds in group 0
+  const unsigned long long first = __ballot(acc && g == 0);
   if ((threadIdx.x & 63) == 0 && first) atomicAdd(&v.ctr[1], (unsigned long long)__popcll(first));
   if (!acc) return;
   const uint32_t p = class_pixel(v, kappa, j);
-  if (tt == 0) v.U[p] = v.u_new[j];
-  *(uint4*)(v.cnt + ((size_t)tt * v.w * v.h + p) * 8) = *(const uint4*)(v.c_new + ((size_t)tt * v.pc + j) * 8);
+  if (g == 0) v.U[p] = v.u_new[j];
+  const uint32_t t0 = g * CT, t1 = min(t0 + CT, v.tp >> 3);
+  const size_t P = (size_t)v.w * v.h;
+  for (uint32_t tt = t0; tt < t1; ++tt)
+    *(uint4*)(v.cnt + (tt * P + p) * 8) = *(const uint4*)(v.c_new + ((size_t)tt * v.pc + j) * 8);
 }
 
 // FP32 error vectors e = c/N - A_t of every pixel from the exact counts
@@ -1194,7 +1199,9 @@ hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
 
 uint32_t xpart_words(const DevView& v) { return v.ncls * v.pc; }
 
-uint32_t commit_blocks(const DevView& v) { return (uint32_t)(((uint64_t)v.pc * (v.tp >> 3) + 255) / 256); }
+uint32_t commit_blocks(const DevView& v) {
+  return (uint32_t)(((uint64_t)v.pc * (((v.tp >> 3) + CT - 1) / CT) + 255) / 256);
+}
 
 hipError_t launch_commit(const DevView& v, uint32_t kappa, hipStream_t s) {
   hipLaunchKernelGGL(k_commit, dim3(commit_blocks(v)), dim3(256), 0, s, v, kappa);
