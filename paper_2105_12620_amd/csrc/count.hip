@@ -136,9 +136,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 }
 
 template <int PPL>
-__global__ __launch_bounds__(256) void k_count_points_batch(const DevView* __restrict__ views,
-                                                            const uint32_t* __restrict__ pre,
-                                                            uint32_t nmem, uint32_t kappa) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_points_batch(
+    const DevView* __restrict__ views, const uint32_t* __restrict__ pre, uint32_t nmem, uint32_t kappa) {
   const uint32_t i = batch_member(pre, nmem, blockIdx.x);
   const DevView v = views[i];
   count_points_body<PPL, MODE_CLASS>(v, v.ihp, kappa, v.pc, v.tch, blockIdx.x - pre[i]);
