@@ -158,3 +158,30 @@ def test_mixed_forms_in_one_batch(stream):
             assert p.energy() == pytest.approx(alone.energy(), rel=1e-12)
             assert p.get_sweep_index() == 3
         p.close()
+
+
+def test_benchmark_batch_full_size(stream):
+    """The benchmark's 32 dimension-pair members (tiles 64^2 to 256^2, N from 4
+    to 256, T = 256, 7x7 window) batched with the launch tuner, one sweep: the
+    offsets of every 64^2 member equal the oracle's sweep, and the larger
+    members equal their own sweeps outside the batch."""
+    members = synthgen.dimension_pair_batch()
+    inps = [synthgen.problem_inputs(mw) for mw in members]
+    probs = [make(mw, mi, stream) for mw, mi in zip(members, inps)]
+    try:
+        with bnlat.Batch(probs) as b:
+            b.sweep(1)
+            say("tuning", b.tuning())
+        got = [q.get_offsets() for q in probs]
+    finally:
+        for q in probs:
+            q.close()
+    for j, (mw, mi) in enumerate(zip(members, inps)):
+        if mw["width"] == 64:
+            ref = oracle_problem(mw, mi)
+            st = osw.run(ref, osw.initial_state(ref, mi["offsets"]), 1)
+            np.testing.assert_array_equal(got[j], st.u, err_msg=f"member {j} vs oracle")
+        elif j % 4 == 0:
+            with make(mw, mi, stream) as alone:
+                alone.sweep(1)
+                np.testing.assert_array_equal(got[j], alone.get_offsets(), err_msg=f"member {j} vs solo")
