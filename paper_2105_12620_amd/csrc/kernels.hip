@@ -865,7 +865,7 @@ __device__ __forceinline__ void gauss_chunk(const DevView& v, uint32_t u, uint32
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, uint32_t m) {
   constexpr uint32_t GB = 16, CH = 512;         // Gaussians per wave, samples per chunk
-  __shared__ double red[4][GB][65];
+  __shared__ double red[4][GB / 2][65];
   const uint32_t lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
   const uint32_t wave = wave_id();
   const uint32_t ngb = v.tgp / GB;
@@ -887,19 +887,26 @@ __global__ __launch_bounds__(256) void k_gauss_est(DevView v, uint32_t kappa, ui
   uint32_t c0 = 0;
   for (; c0 + CH <= v.n; c0 += CH) gauss_chunk<false>(v, u, c0, lane, gc, acc);
   if (c0 < v.n) gauss_chunk<true>(v, u, c0, lane, gc, acc);
-  // lane sums -> per-Gaussian totals: lane l adds 16 of Gaussian l % 16's
-  // lane sums, then the four quarters are added across lanes
+  // lane sums -> per-Gaussian totals, eight Gaussians at a time: lane l adds
+  // 8 of Gaussian l % 8's lane sums, then the eight groups are added across
+  // lanes
 #pragma unroll
-  for (uint32_t g = 0; g < GB; ++g) red[wl][g][lane] = acc[g];
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  const uint32_t g = lane & 15, q = lane >> 4;
-  double t = 0.0;
+  for (uint32_t h = 0; h < 2; ++h) {
 #pragma unroll
-  for (uint32_t k = 0; k < 16; ++k) t = __dadd_rn(t, red[wl][g][16 * q + k]);
-  t = __dadd_rn(t, __shfl_xor(t, 16));
-  t = __dadd_rn(t, __shfl_xor(t, 32));
-  if (lane < GB) out[gb * GB + g] = (float)(t / (double)v.n);
+    for (uint32_t g = 0; g < GB / 2; ++g) red[wl][g][lane] = acc[8 * h + g];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t g = lane & 7, q = lane >> 3;
+    double t = 0.0;
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) t = __dadd_rn(t, red[wl][g][8 * q + k]);
+    t = __dadd_rn(t, __shfl_xor(t, 8));
+    t = __dadd_rn(t, __shfl_xor(t, 16));
+    t = __dadd_rn(t, __shfl_xor(t, 32));
+    if (lane < GB / 2) out[gb * GB + 8 * h + g] = (float)(t / (double)v.n);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
 }
 
 // Gaussian rows' part of a move's energy change (plain form of Eq. (1) over
