@@ -207,6 +207,20 @@ def main() -> int:
         g1.record(stream)
         torch.cuda.synchronize()
         graph_ms = g0.elapsed_time(g1)
+        alone_ms = None
+        if move == bnlat.BN_REDRAW:
+            # the colour-phase evaluation measured alone (no recount beside it):
+            # propose class 0 once, then time five evaluations of it
+            prob.phase_propose(0)
+            prob.phase_evaluate(0)
+            torch.cuda.synchronize()
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            for _ in range(5):
+                prob.phase_evaluate(0)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            alone_ms = a0.elapsed_time(a1) / 5
         energy = prob.energy()
         quality = prob.quality_metric([1.0, 4.0, 16.0]).tolist()
         prob.close()
@@ -215,7 +229,7 @@ def main() -> int:
                    "commit_per_phase": prof["commit_ms"] / max(1, prof["phases"]),
                    "recount_launches": prof["recount_launches"], "phases": prof["phases"]}
         return {"total_ms": total_ms, "kernels_ms": kernels, "graph_ms": graph_ms, "energy": energy,
-                "quality_sigma_1_4_16": quality}
+                "quality_sigma_1_4_16": quality, "evaluate_alone_ms": alone_ms}
 
     if args.copy_calibration:
         # a plain copy kernel of known size: 1 GiB read, 1 GiB written
@@ -318,12 +332,16 @@ def main() -> int:
         "kernels_ms": avg,
         "evaluate_hbm_gbs": delta_bytes / (avg["evaluate_per_phase"] * 1e-3) / 1e9,
         "evaluate_hbm_frac": delta_bytes / (avg["evaluate_per_phase"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "evaluate_alone": {"ms_per_phase": fp32["evaluate_alone_ms"],
+                           "hbm_gbs": delta_bytes / (fp32["evaluate_alone_ms"] * 1e-3) / 1e9,
+                           "frac": delta_bytes / (fp32["evaluate_alone_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "graph_value": P * args.steps / (fp32["graph_ms"] * 1e-3),
         "bf16": None if bf16 is None else {
             "value": P * args.steps / (bf16["total_ms"] * 1e-3),
             "graph_value": P * args.steps / (bf16["graph_ms"] * 1e-3),
             "kernels_ms": bf16["kernels_ms"],
             "evaluate_hbm_gbs": delta_bytes / (bf16["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9,
+            "evaluate_alone_ms_per_phase": bf16["evaluate_alone_ms"],
             "energy_rel_diff_vs_fp32": abs(bf16["energy"] - fp32["energy"]) / abs(fp32["energy"]),
             "quality_rel_diff_vs_fp32": max(abs(a - b) / b for a, b in zip(bf16["quality_sigma_1_4_16"],
                                                                             fp32["quality_sigma_1_4_16"]))},
