@@ -64,7 +64,7 @@ def measured_traffic():
     return None
 
 
-def cpu_baseline(w: dict, inp: dict, sweeps: int = 16, row_pixels: int = 128) -> dict:
+def cpu_baseline(w: dict, inp: dict, sweeps: int = 128, row_pixels: int = 128) -> dict:
     """The oracle timed on a band of class-0 pixels (one class row) of the same
     workload: proposals, recount, energy change and commit, repeated over
     ``sweeps`` sweeps.  The window state of the band is computed first (not
