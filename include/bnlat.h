@@ -85,14 +85,14 @@ typedef enum { BN_REDRAW = 0, BN_SWAP = 1 } bn_move;
 
 /* Problem description (Eq. (1) window, Sec. 3.2 lattice, Sec. 3.4 classes). */
 typedef struct {
-  uint32_t n;            /* samples per pixel N = 2^m, 1 <= N <= 32768           */
+  uint32_t n;            /* samples per pixel N = 2^m, 1 <= N <= 32768 (N > 4096: BN_EUNSUPPORTED) */
   uint32_t g[2];         /* lattice generator; each component odd (coprime to N) */
   uint32_t width;        /* toroidal tile width W  (multiple of colour_k)        */
   uint32_t height;       /* toroidal tile height H (multiple of colour_k)        */
   uint32_t t_heaviside;  /* number T of Heaviside test integrands, >= 1          */
   uint32_t t_gauss;      /* number of Gaussian integrands (Sec. 3.5), >= 0      */
   double sigma;          /* energy weight w_o = exp(-|o|^2 / sigma^2), > 0       */
-  uint32_t radius;       /* window offsets o in [-r, r]^2 \ {0}; 1 <= r < min(W,H), r <= 8 */
+  uint32_t radius;       /* window offsets o in [-r, r]^2 \ {0}; 1 <= r < min(W,H), r <= 8 (r > 6: BN_EUNSUPPORTED) */
   uint32_t colour_k;     /* colour modulus K: K*K classes (y mod K) K + (x mod K) */
   int32_t objective;     /* +1: accept dE < 0 (descend Eq. (1)); -1: accept dE > 0 */
   uint64_t seed;         /* Philox key (low, high 32 bits)                       */
