@@ -310,7 +310,9 @@ def main() -> int:
     big = large() if "large" in forms else None
 
     # algorithmic work per launch of the counting kernel: one sweep-wide recount
-    count_ops = 2.0 * P * N * T                       # v_dot2 + compare per (sample, integrand)
+    # per (sample, integrand): one v_dot2, half a v_perm_b32 (two integrands'
+    # sign bits per word) and a quarter of a v_add3_u32 (two words per add)
+    count_ops = 1.75 * P * N * T
     count_tops = count_ops / (avg["recount_per_sweep"] * 1e-3) / 1e12
     win = (2 * w["radius"] + 1) ** 2 - 1
     # evaluation of a phase: the tile's counts once (2 B each) plus the moved
@@ -325,10 +327,10 @@ def main() -> int:
         "config": {"workload": args.workload, "tile": f"{w['width']}x{w['height']}", "n": N, "t": T,
                    "window": f"{2 * w['radius'] + 1}x{2 * w['radius'] + 1}", "colour_classes": K2,
                    "precision": "fp32", "mutation": "redraw"},
-        "roofline": {"bound": "alu", "kernel": "k_count_points<4, 3> (sweep-wide proposal recount)",
+        "roofline": {"bound": "alu", "kernel": "k_count<64, 4, 3> (sweep-wide proposal recount)",
                      "achieved": count_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": count_tops / VALU_PEAK_TOPS, "traffic": measured_traffic(),
-                     "work_per_launch": f"{P} pixels x {N} samples x {T} integrands x 2 lane-ops"},
+                     "work_per_launch": f"{P} pixels x {N} samples x {T} integrands x 1.75 lane-ops"},
         "kernels_ms": avg,
         "evaluate_hbm_gbs": delta_bytes / (avg["evaluate_per_phase"] * 1e-3) / 1e9,
         "evaluate_hbm_frac": delta_bytes / (avg["evaluate_per_phase"] * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -56,68 +56,110 @@ __device__ inline void count_target(const DevView& v, uint32_t kappa, uint32_t j
 // Estimator of the test-integrand map (Sec. 2): c[p][t] = number of the N
 // scrambled samples on the hit side of Heaviside t.
 //
-// k_count_points (N >= 128): the 64 lanes of a wave hold 64*PPL samples of one
-// pixel (PPL per lane); the wave walks integrands with wave-uniform
-// parameters in scalar registers.  Per (sample, integrand): one v_dot2 and
-// one v_cmp; the 64 predicate bits of a compare are counted with a scalar
-// popcount.  Counts for 64 consecutive integrands are gathered one per lane
-// and stored as one coalesced 128-byte row segment.  N > 64*PPL is handled
-// in groups of 64*PPL samples.
-template <int PPL, int MODE>
-__device__ __forceinline__ void count_points_body(const DevView& v, const int2* __restrict__ ihp,
-                                                  uint32_t kappa, uint32_t m, uint32_t tch,
-                                                  uint32_t blk) {
+// k_count: every lane holds NS samples of one work item (a pixel, or a
+// proposal), and L = N / NS consecutive lanes share the item (NS = N up to 64,
+// else 64).  A wave walks a chunk of integrands with wave-uniform parameters
+// from scalar loads, two integrands at a time.  Per (sample, integrand) the
+// only vector work is one v_dot2 with the threshold folded in (n.s > D'
+// exactly when r = n.s - D' - 1 >= 0; |n.s|, |D'| <= 2^30, so r never
+// overflows); per sample one v_perm_b32 turns the sign bits of the two
+// integrands' residues into 0x00/0xFF bytes in the two 16-bit halves of a
+// word, and per two such words one v_add3_u32 sums them.  A lane's halves then
+// hold 255 x its misses of integrands i and i + 1 (at most 255 * 64, so no
+// carry crosses the halves); they become miss counts, the L lanes of an item
+// add them with DPP / lane shuffles, and N - misses is the item's pair of
+// counts, already packed as the tile layout stores them.
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Sign bytes of a sample's residues for two integrands: byte 0 is 0xFF when
+// lo < 0 and byte 2 is 0xFF when hi < 0 (v_perm_b32 selectors 9 and 11 repeat
+// bit 31 of the second and of the first operand; selector 12 is a zero byte).
+__device__ inline uint32_t sign_bytes(int lo, int hi) {
+  return __builtin_amdgcn_perm((uint32_t)hi, (uint32_t)lo, 0x0C0B0C09u);
+}
+
+// Per 16-bit half, x = 255 m with 0 <= m <= 255 becomes m:
+// floor(255 (m + 1) / 256) = m, so m = (x + 255) >> 8.
+__device__ inline uint32_t halves_div255(uint32_t x) {
+  const u16x2 h = __builtin_bit_cast(u16x2, x);
+  return __builtin_bit_cast(uint32_t, (u16x2)((h + (u16x2){255, 255}) >> (u16x2){8, 8}));
+}
+
+// Sum of x over each aligned group of L consecutive lanes, in every lane of
+// the group.
+template <int L>
+__device__ inline uint32_t lane_group_sum(uint32_t x) {
+  if (L >= 2) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+  if (L >= 4) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+#pragma unroll
+  for (int o = 4; o < L; o <<= 1) x += (uint32_t)__shfl_xor((int)x, o);
+  return x;
+}
+
+template <int NS, int L, int MODE>
+__device__ __forceinline__ void count_lanes_body(const DevView& v, const int2* __restrict__ ihp, uint32_t kappa,
+                                                 uint32_t m, uint32_t tch, uint32_t blk) {
+  constexpr uint32_t IPW = 64 / L;  // work items per wave
+  constexpr uint32_t N = NS * L;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
   const uint32_t nch = (v.tp + tch - 1) / tch;
-  const uint32_t j = wave / nch, ch = wave - j * nch;
-  if (j >= m) return;
+  const uint32_t jg = wave / nch, ch = wave - jg * nch;
+  if (jg * IPW >= m) return;
+  const uint32_t slot = lane % L, j0 = jg * IPW + lane / L;
+  // lanes past the last item repeat it (the group sums need whole lane
+  // groups) and store nothing
+  const bool live = j0 < m;
+  const uint32_t j = live ? j0 : m - 1;
   uint32_t p, u, row, rows;
   uint16_t* buf;
   count_target<MODE>(v, kappa, j, m, p, u, buf, row, rows);
-  if ((MODE == MODE_CLASS || MODE == MODE_SWEEP) && ch == 0 && lane == 0) v.u_new[j] = u;
-
-  const uint32_t groups = v.n / (64u * PPL);
-  uint32_t sp[PPL];
+  if ((MODE == MODE_CLASS || MODE == MODE_SWEEP) && ch == 0 && slot == 0 && live) v.u_new[j] = u;
+  uint32_t sp[NS];
 #pragma unroll
-  for (int k = 0; k < PPL; ++k) sp[k] = centre(wrap_add(v.lat[lane + 64 * k], u));
-  const float inv_n = 1.0f / (float)v.n;
+  for (int k = 0; k < NS; ++k) sp[k] = centre(wrap_add(v.lat[slot * NS + k], u));
+  const float inv_n = 1.0f / (float)N;
   const uint32_t t0 = ch * tch, t1 = min(t0 + tch, v.tp);
-  for (uint32_t tb = t0; tb < t1; tb += 64) {
-    int total = 0;
-    if (tb < v.t) {
-      for (uint32_t g = 0; g < groups; ++g) {
-        if (groups > 1) {
-#pragma unroll
-          for (int k = 0; k < PPL; ++k)
-            sp[k] = centre(wrap_add(v.lat[g * 64 * PPL + lane + 64 * k], u));
-        }
-        // one integrand per step: PPL dot products and compares on the
-        // vector ALU, popcounts and adds on the scalar ALU, and the count
-        // written into lane tt
-        int myc = 0;
-        const int4* ip = (const int4*)(ihp + tb);
+  const int4* ip = (const int4*)(ihp + t0);
 #pragma unroll 1
-        for (int blk = 0; blk < 8; ++blk) {
-          // eight integrands' parameters in one scalar load
-          const int4 q0 = ip[4 * blk], q1 = ip[4 * blk + 1], q2 = ip[4 * blk + 2], q3 = ip[4 * blk + 3];
-          const int nn[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
-          const int dd[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+  for (uint32_t t = t0; t < t1; t += 8, ip += 4) {
+    // eight integrands' parameters in one scalar load
+    const int4 q0 = ip[0], q1 = ip[1], q2 = ip[2], q3 = ip[3];
+    const int nn[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
+    const int dd[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+    uint32_t c[4];
 #pragma unroll
-          for (int k8 = 0; k8 < 8; ++k8) {
-            int c = 0;
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t n0 = (uint32_t)nn[2 * i], n1 = (uint32_t)nn[2 * i + 1];
+      const int thr0 = -dd[2 * i] - 1, thr1 = -dd[2 * i + 1] - 1;
+      uint32_t a = 0;
+      // four samples' residues first, then their sign words: a v_perm then
+      // reads a v_dot2 result several instructions after it
+      constexpr int G = NS < 4 ? NS : 4;
 #pragma unroll
-            for (int k = 0; k < PPL; ++k)
-              c += __popcll(__ballot(dot2((uint32_t)nn[k8], sp[k], 0) > dd[k8]));
-            myc = bnlat_writelane_i32(c, 8 * blk + k8, myc);
-          }
-        }
-        total += myc;
+      for (int k = 0; k < NS; k += G) {
+        int r0[4], r1[4];
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < G; ++e) r0[e] = dot2(n0, sp[k + e], thr0), r1[e] = dot2(n1, sp[k + e], thr1);
+#pragma unroll
+        for (int e = 0; e < G; ++e) w[e] = sign_bytes(r0[e], r1[e]);
+        if (G == 4) a = a + w[0] + w[1], a = a + w[2] + w[3];
+        else if (G == 2) a = a + w[0] + w[1];
+        else a += w[0];
+      }
+      // misses per half: at most 64 per lane, N per item (no carry)
+      c[i] = (N | (N << 16)) - lane_group_sum<L>(halves_div255(a));
+    }
+    if (slot == 0 && live) {
+      *(uint4*)(buf + tix(row, t, rows)) = make_uint4(c[0], c[1], c[2], c[3]);
+      if (MODE == MODE_ALL) {
+        float* e = v.err + (size_t)p * v.tp + t;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) e[i] = (float)((c[i >> 1] >> (16 * (i & 1))) & 0xFFFFu) * inv_n - v.area[t + i];
       }
     }
-    buf[tix(row, tb + lane, rows)] = (uint16_t)total;
-    if (MODE == MODE_ALL)
-      v.err[(size_t)p * v.tp + tb + lane] = (float)total * inv_n - v.area[tb + lane];
   }
 }
 
@@ -125,128 +167,63 @@ __device__ __forceinline__ void count_points_body(const DevView& v, const int2* 
 // sweep-wide recount of the overlapped schedule is capped so that it leaves
 // room on every CU for the colour phases running beside it): workgroups then
 // stride over the virtual blocks.
-//
-// Eight waves per SIMD: the compiler then keeps the compare masks in VCC and
-// a few scalar registers (72 instead of 100, which allowed seven waves); the
-// sweep-wide recount measured 11 % faster so.
-template <int PPL, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_points(
-    DevView v, const int2* __restrict__ ihp, uint32_t kappa, uint32_t m, uint32_t tch, uint32_t vblocks) {
-  for (uint32_t b = blockIdx.x; b < vblocks; b += gridDim.x) count_points_body<PPL, MODE>(v, ihp, kappa, m, tch, b);
+template <int NS, int L, int MODE>
+__global__ __launch_bounds__(256) void k_count(DevView v, const int2* __restrict__ ihp, uint32_t kappa, uint32_t m,
+                                               uint32_t tch, uint32_t vblocks) {
+  for (uint32_t b = blockIdx.x; b < vblocks; b += gridDim.x) count_lanes_body<NS, L, MODE>(v, ihp, kappa, m, tch, b);
 }
 
-template <int PPL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_points_batch(
-    const DevView* __restrict__ views, const uint32_t* __restrict__ pre, uint32_t nmem, uint32_t kappa) {
+template <int NS, int L>
+__global__ __launch_bounds__(256) void k_count_batch(const DevView* __restrict__ views,
+                                                     const uint32_t* __restrict__ pre, uint32_t nmem,
+                                                     uint32_t kappa) {
   const uint32_t i = batch_member(pre, nmem, blockIdx.x);
   const DevView v = views[i];
-  count_points_body<PPL, MODE_CLASS>(v, v.ihp, kappa, v.pc, v.tch, blockIdx.x - pre[i]);
+  count_lanes_body<NS, L, MODE_CLASS>(v, v.ihp, kappa, v.pc, L == 1 ? 64u : v.tch, blockIdx.x - pre[i]);
 }
 
-// k_count_pixels (N <= 64): lanes hold 64 consecutive work items (pixels or
-// proposals), each with its N samples in registers; a wave walks 64
-// integrands with wave-uniform parameters from scalar loads and, per 8
-// integrands, stores each lane's 8 counts as one 16-byte tile piece.  Per
-// two (sample, integrand) pairs: two v_dot2 (threshold folded in), two shifts
-// and one three-way add.
-template <int NS, int MODE>
-__device__ __forceinline__ void count_pixels_body(const DevView& v, uint32_t kappa, uint32_t m, uint32_t blk) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
-  const uint32_t nch = v.tp >> 6;
-  const uint32_t jg = wave / nch, ch = wave - jg * nch;
-  const uint32_t j = jg * 64 + lane;
-  if (jg * 64 >= m || j >= m) return;
-  uint32_t p, u, row, rows;
-  uint16_t* buf;
-  count_target<MODE>(v, kappa, j, m, p, u, buf, row, rows);
-  if ((MODE == MODE_CLASS || MODE == MODE_SWEEP) && ch == 0) v.u_new[j] = u;
-  uint32_t sp[NS];
-#pragma unroll
-  for (int k = 0; k < NS; ++k) sp[k] = centre(wrap_add(v.lat[k], u));
-  const float inv_n = 1.0f / (float)NS;
-  const int4* ip = (const int4*)(v.ihp + ch * 64);
-#pragma unroll 1
-  for (int tt = 0; tt < 8; ++tt) {
-    const int4 q0 = ip[4 * tt], q1 = ip[4 * tt + 1], q2 = ip[4 * tt + 2], q3 = ip[4 * tt + 3];
-    const int nn[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
-    const int dd[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
-    // n.s > D' exactly when r = n.s - D' - 1 >= 0 (|n.s|, |D'| <= 2^30, so r
-    // never overflows): misses are the sign bits, summed three at a time
-    uint32_t c[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int thr = -dd[i] - 1;
-      uint32_t miss = 0;
-#pragma unroll
-      for (int k = 0; k < NS; k += 2) {
-        const uint32_t r0 = (uint32_t)dot2((uint32_t)nn[i], sp[k], thr) >> 31;
-        const uint32_t r1 = k + 1 < NS ? (uint32_t)dot2((uint32_t)nn[i], sp[k + 1], thr) >> 31 : 0u;
-        miss = miss + r0 + r1;
-      }
-      c[i] = NS - miss;
-    }
-    const uint32_t t = ch * 64 + 8 * tt;
-    *(uint4*)(buf + tix(row, t, rows)) =
-        make_uint4(c[0] | (c[1] << 16), c[2] | (c[3] << 16), c[4] | (c[5] << 16), c[6] | (c[7] << 16));
-    if (MODE == MODE_ALL) {
-      float* e = v.err + (size_t)p * v.tp + t;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) e[i] = (float)c[i] * inv_n - v.area[t + i];
-    }
-  }
+// Lanes per work item (N / 64 above N = 64) and the integrand chunk of a wave:
+// 64 integrands up to N = 64, else v.tch (whole rows at T <= 1024 by
+// default), halved while a launch over m items would hold under 8192 waves.
+inline uint32_t count_lanes(uint32_t n) { return n <= 64 ? 1u : n / 64; }
+
+inline uint32_t count_chunk(const DevView& v, uint32_t m, uint32_t tch) {
+  if (v.n <= 64) return 64;
+  const uint64_t groups = (m + 64 / count_lanes(v.n) - 1) / (64 / count_lanes(v.n));
+  while (tch > 64 && groups * ((v.tp + tch - 1) / tch) < 8192) tch >>= 1;
+  return tch;
 }
 
-template <int NS, int MODE>
-__global__ __launch_bounds__(256) void k_count_pixels(DevView v, uint32_t kappa, uint32_t m) {
-  count_pixels_body<NS, MODE>(v, kappa, m, blockIdx.x);
+inline uint64_t count_waves(const DevView& v, uint32_t m, uint32_t tch) {
+  const uint32_t ipw = 64 / count_lanes(v.n);
+  return (uint64_t)((m + ipw - 1) / ipw) * ((v.tp + tch - 1) / tch);
 }
-
-template <int NS>
-__global__ __launch_bounds__(256) void k_count_pixels_batch(const DevView* __restrict__ views,
-                                                            const uint32_t* __restrict__ pre, uint32_t nmem,
-                                                            uint32_t kappa) {
-  const uint32_t i = batch_member(pre, nmem, blockIdx.x);
-  const DevView v = views[i];
-  count_pixels_body<NS, MODE_CLASS>(v, kappa, v.pc, blockIdx.x - pre[i]);
-}
-
-// waves of a k_count_pixels launch over m work items
-inline uint64_t count_pixel_waves(const DevView& v, uint32_t m) { return (uint64_t)((m + 63) / 64) * (v.tp >> 6); }
 
 template <int MODE>
 hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStream_t s) {
   if (m == 0) return hipSuccess;
-  if (v.n <= 64) {
-    const dim3 g((unsigned)((count_pixel_waves(v, m) + 3) / 4)), b(256);
-    switch (v.n) {
-      case 1: hipLaunchKernelGGL((k_count_pixels<1, MODE>), g, b, 0, s, v, kappa, m); break;
-      case 2: hipLaunchKernelGGL((k_count_pixels<2, MODE>), g, b, 0, s, v, kappa, m); break;
-      case 4: hipLaunchKernelGGL((k_count_pixels<4, MODE>), g, b, 0, s, v, kappa, m); break;
-      case 8: hipLaunchKernelGGL((k_count_pixels<8, MODE>), g, b, 0, s, v, kappa, m); break;
-      case 16: hipLaunchKernelGGL((k_count_pixels<16, MODE>), g, b, 0, s, v, kappa, m); break;
-      case 32: hipLaunchKernelGGL((k_count_pixels<32, MODE>), g, b, 0, s, v, kappa, m); break;
-      case 64: hipLaunchKernelGGL((k_count_pixels<64, MODE>), g, b, 0, s, v, kappa, m); break;
-      default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  }
-  // integrands per wave: v.tch (whole rows at T <= 1024 by default: the
-  // proposal and samples are set up once per wave), halved while the launch
-  // would hold fewer than 8192 waves
-  uint32_t tch = v.tch;
-  while (tch > 64 && (uint64_t)m * ((v.tp + tch - 1) / tch) < 8192) tch >>= 1;
-  const uint64_t waves = (uint64_t)m * ((v.tp + tch - 1) / tch);
-  const uint32_t vb = (uint32_t)((waves + 3) / 4);
+  const uint32_t tch = count_chunk(v, m, v.tch);
+  const uint32_t vb = (uint32_t)((count_waves(v, m, tch) + 3) / 4);
   const uint32_t nb = (MODE == MODE_SWEEP && v.count_cap) ? std::min(vb, v.count_cap) : vb;
-  const dim3 grid(nb), block(256);
+  const dim3 g(nb), b(256);
+#define BN_COUNT(NS, L) hipLaunchKernelGGL((k_count<NS, L, MODE>), g, b, 0, s, v, v.ihp, kappa, m, tch, vb); break
   switch (v.n) {
-    case 128: hipLaunchKernelGGL((k_count_points<2, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
-    // N >= 256: four samples per lane, N / 256 sample groups (more samples
-    // per lane would keep more compare masks live than the scalar registers
-    // hold, and the spills cost more than the group reloads)
-    default: hipLaunchKernelGGL((k_count_points<4, MODE>), grid, block, 0, s, v, v.ihp, kappa, m, tch, vb); break;
+    case 1: BN_COUNT(1, 1);
+    case 2: BN_COUNT(2, 1);
+    case 4: BN_COUNT(4, 1);
+    case 8: BN_COUNT(8, 1);
+    case 16: BN_COUNT(16, 1);
+    case 32: BN_COUNT(32, 1);
+    case 64: BN_COUNT(64, 1);
+    case 128: BN_COUNT(64, 2);
+    case 256: BN_COUNT(64, 4);
+    case 512: BN_COUNT(64, 8);
+    case 1024: BN_COUNT(64, 16);
+    case 2048: BN_COUNT(64, 32);
+    case 4096: BN_COUNT(64, 64);
+    default: return hipErrorInvalidValue;
   }
+#undef BN_COUNT
   return hipGetLastError();
 }
 
@@ -261,34 +238,35 @@ hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
   }
 }
 
-// Launch kind of a batch member's recount: N itself up to 64 (one kernel per
-// N), 64 + samples per lane above.
-int count_kind(const DevView& v) {
-  if (v.n <= 64) return (int)v.n;
-  return v.n == 128 ? 66 : 68;
-}
+// Launch kind of a batch member's recount: N itself up to 64, else 64 + the
+// lanes per work item (one kernel per N either way).
+int count_kind(const DevView& v) { return v.n <= 64 ? (int)v.n : 64 + (int)count_lanes(v.n); }
 
 uint32_t count_blocks(const DevView& v) {
-  if (v.n <= 64) return (uint32_t)((count_pixel_waves(v, v.pc) + 3) / 4);
-  const uint64_t waves = (uint64_t)v.pc * ((v.tp + v.tch - 1) / v.tch);
-  return (uint32_t)((waves + 3) / 4);
+  return (uint32_t)((count_waves(v, v.pc, v.n <= 64 ? 64u : v.tch) + 3) / 4);
 }
 
 hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
                               uint32_t blocks, uint32_t kappa, hipStream_t s) {
-  const dim3 grid(blocks), block(256);
+  const dim3 g(blocks), b(256);
+#define BN_COUNT(NS, L) hipLaunchKernelGGL((k_count_batch<NS, L>), g, b, 0, s, views, pre, nmem, kappa); break
   switch (kind) {
-    case 1: hipLaunchKernelGGL(k_count_pixels_batch<1>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 2: hipLaunchKernelGGL(k_count_pixels_batch<2>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 4: hipLaunchKernelGGL(k_count_pixels_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 8: hipLaunchKernelGGL(k_count_pixels_batch<8>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 16: hipLaunchKernelGGL(k_count_pixels_batch<16>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 32: hipLaunchKernelGGL(k_count_pixels_batch<32>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 64: hipLaunchKernelGGL(k_count_pixels_batch<64>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 66: hipLaunchKernelGGL(k_count_points_batch<2>, grid, block, 0, s, views, pre, nmem, kappa); break;
-    case 68: hipLaunchKernelGGL(k_count_points_batch<4>, grid, block, 0, s, views, pre, nmem, kappa); break;
+    case 1: BN_COUNT(1, 1);
+    case 2: BN_COUNT(2, 1);
+    case 4: BN_COUNT(4, 1);
+    case 8: BN_COUNT(8, 1);
+    case 16: BN_COUNT(16, 1);
+    case 32: BN_COUNT(32, 1);
+    case 64: BN_COUNT(64, 1);
+    case 66: BN_COUNT(64, 2);
+    case 68: BN_COUNT(64, 4);
+    case 72: BN_COUNT(64, 8);
+    case 80: BN_COUNT(64, 16);
+    case 96: BN_COUNT(64, 32);
+    case 128: BN_COUNT(64, 64);
     default: return hipErrorInvalidValue;
   }
+#undef BN_COUNT
   return hipGetLastError();
 }
 
