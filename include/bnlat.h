@@ -224,8 +224,10 @@ bn_status bn_set_profiling(bn_problem p, int enable);
 /* Launch shape of the sweep-wide recount in bn_sweep's overlapped schedule:
  * at most `blocks` workgroups of 256 threads, each striding over the work, so
  * that the recount leaves room on every CU for the colour phases running
- * beside it; 0 removes the cap.  Applies for N >= 128 (the N <= 64 kernel is
- * not capped).  Results do not depend on it.  Synchronises. */
+ * beside it (rounded down to the workgroup count that gives every workgroup
+ * the same number of blocks); 0 removes the cap.  Default: two workgroups per
+ * CU for BN_FP32, one for BN_BF16.  Results do not depend on it.
+ * Synchronises. */
 bn_status bn_set_recount_blocks(bn_problem p, uint32_t blocks);
 bn_status bn_get_profile(bn_problem p, bn_profile_stats* out);
 

@@ -204,7 +204,14 @@ hipError_t count_dispatch(const DevView& v, uint32_t kappa, uint32_t m, hipStrea
   if (m == 0) return hipSuccess;
   const uint32_t tch = count_chunk(v, m, v.tch);
   const uint32_t vb = (uint32_t)((count_waves(v, m, tch) + 3) / 4);
-  const uint32_t nb = (MODE == MODE_SWEEP && v.count_cap) ? std::min(vb, v.count_cap) : vb;
+  // a capped launch gets the fewest rounds the cap allows and as few
+  // workgroups as those rounds need, so that every workgroup strides over the
+  // same number of blocks
+  uint32_t nb = vb;
+  if (MODE == MODE_SWEEP && v.count_cap && vb > v.count_cap) {
+    const uint32_t rounds = (vb + v.count_cap - 1) / v.count_cap;
+    nb = (vb + rounds - 1) / rounds;
+  }
   const dim3 g(nb), b(256);
 #define BN_COUNT(NS, L) hipLaunchKernelGGL((k_count<NS, L, MODE>), g, b, 0, s, v, v.ihp, kappa, m, tch, vb); break
   switch (v.n) {
