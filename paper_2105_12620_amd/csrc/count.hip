@@ -90,8 +90,8 @@ __device__ inline uint32_t halves_div255(uint32_t x) {
 // the group.
 template <int L>
 __device__ inline uint32_t lane_group_sum(uint32_t x) {
-  if (L >= 2) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
-  if (L >= 4) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+  if (L >= 2) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, true);  // quad_perm 1,0,3,2
+  if (L >= 4) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, true);  // quad_perm 2,3,0,1
 #pragma unroll
   for (int o = 4; o < L; o <<= 1) x += (uint32_t)__shfl_xor((int)x, o);
   return x;
@@ -152,6 +152,9 @@ __device__ __forceinline__ void count_lanes_body(const DevView& v, const int2* _
       // misses per half: at most 64 per lane, N per item (no carry)
       c[i] = (N | (N << 16)) - lane_group_sum<L>(halves_div255(a));
     }
+    // computed in every lane (an empty asm consumes them): otherwise, with
+    // one lane per item, the counting would move under the store's branch
+    asm volatile("" : : "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
     if (slot == 0 && live) {
       *(uint4*)(buf + tix(row, t, rows)) = make_uint4(c[0], c[1], c[2], c[3]);
       if (MODE == MODE_ALL) {
@@ -167,9 +170,13 @@ __device__ __forceinline__ void count_lanes_body(const DevView& v, const int2* _
 // sweep-wide recount of the overlapped schedule is capped so that it leaves
 // room on every CU for the colour phases running beside it): workgroups then
 // stride over the virtual blocks.
+//
+// Occupancy target four waves per SIMD: aiming higher, the compiler fed each
+// v_perm from the v_dot2 just before it and padded the pair with s_nop (about
+// 250 per eight integrands at N = 64).
 template <int NS, int L, int MODE>
-__global__ __launch_bounds__(256) void k_count(DevView v, const int2* __restrict__ ihp, uint32_t kappa, uint32_t m,
-                                               uint32_t tch, uint32_t vblocks) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_count(
+    DevView v, const int2* __restrict__ ihp, uint32_t kappa, uint32_t m, uint32_t tch, uint32_t vblocks) {
   for (uint32_t b = blockIdx.x; b < vblocks; b += gridDim.x) count_lanes_body<NS, L, MODE>(v, ihp, kappa, m, tch, b);
 }
 
