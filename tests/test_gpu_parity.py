@@ -167,6 +167,35 @@ def test_full_size_tile256_sampled():
         assert bool(ph["accept"][j]) == bool(d[0] < 0)
 
 
+def test_full_size_tile256_sweeps_sampled():
+    """The benchmark's own schedule at full size (256x256, N=256, T=1024, two
+    graph-replayed overlapped sweeps with the capped sweep-wide recount):
+    every sampled pixel's offset is its initial one or the oracle's proposal
+    for one of the two sweeps, its counts are the oracle's estimator at that
+    offset, and the energy fell."""
+    w = workload("tile256_n256_t1024")
+    inp = synthgen.problem_inputs(w)
+    W = w["width"]
+    ref = oracle_problem(w, inp)
+    u0 = inp["offsets"].reshape(-1, 2).astype(np.int64)
+    with gpu_problem(w, inp) as p:
+        e0 = p.energy()
+        p.sweep(2)
+        u = p.get_offsets().reshape(-1, 2).astype(np.int64)
+        c = p.get_counts()
+        e2 = p.energy()
+    assert e2 < e0
+    moved = np.any(u != u0, axis=1)
+    assert 0.01 < moved.mean() < 0.99
+    sample = synthgen.pixel_sample(W * w["height"], 64, seed=5)
+    ys, xs = sample // W, sample % W
+    props = [osw.proposals(ref, ys, xs, s).astype(np.int64) for s in (0, 1)]
+    for i, q in enumerate(sample):
+        assert (np.array_equal(u[q], u0[q]) or np.array_equal(u[q], props[0][i])
+                or np.array_equal(u[q], props[1][i])), q
+    np.testing.assert_array_equal(c[sample], estimator.hit_counts(w["n"], w["g"], u[sample], inp["heaviside"]))
+
+
 def test_rerun_and_resume_are_bit_identical():
     w = EDGE["n256_r4"]
     inp = synthgen.problem_inputs(w)
