@@ -247,7 +247,7 @@ struct bn_problem_s {
 
 // A group of batch members served by one launch of one kernel variant.
 struct BatchGroup {
-  int kind = 0;               // counting-kernel variant (count_kind: N below 64, else 64 + samples per lane)
+  int kind = 0;               // counting-kernel variant (count_kind: N up to 64, else 64 + lanes per item)
   uint32_t radius = 0, k = 0; // staged energy-change variant
   std::vector<uint32_t> idx;  // member indices
   DevView* d_views = nullptr;
