@@ -282,6 +282,10 @@ __device__ __forceinline__ void delta_stage_body(const DevView& v, uint32_t kapp
 template <int R, int K, int BY, int V>
 __global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kappa, uint32_t trlen,
                                                          long long* __restrict__ xpart) {
+  // the colour phases' waves issue ahead of the sweep-wide recount running
+  // beside them (k_delta_finish and k_commit likewise), which fills the
+  // remaining issue slots
+  __builtin_amdgcn_s_setprio(2);
   delta_stage_body<R, K, BY, V>(v, kappa, trlen, xpart, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
@@ -317,6 +321,7 @@ __device__ __forceinline__ void delta_finish_body(const DevView& v, long long* _
 }
 
 __global__ __launch_bounds__(256) void k_delta_finish(DevView v, long long* __restrict__ xsum) {
+  __builtin_amdgcn_s_setprio(2);
   delta_finish_body(v, xsum, blockIdx.x);
 }
 
@@ -667,7 +672,10 @@ __global__ __launch_bounds__(256) void k_errors(DevView v) {
   *(float4*)(e + 4) = hi;
 }
 
-__global__ __launch_bounds__(256) void k_commit(DevView v, uint32_t kappa) { commit_body(v, kappa, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_commit(DevView v, uint32_t kappa) {
+  __builtin_amdgcn_s_setprio(2);
+  commit_body(v, kappa, blockIdx.x);
+}
 
 __global__ __launch_bounds__(256) void k_commit_batch(const DevView* __restrict__ views,
                                                       const uint32_t* __restrict__ pre, uint32_t nmem,
