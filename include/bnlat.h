@@ -226,7 +226,7 @@ bn_status bn_set_profiling(bn_problem p, int enable);
  * that the recount leaves room on every CU for the colour phases running
  * beside it (rounded down to the workgroup count that gives every workgroup
  * the same number of blocks); 0 removes the cap.  Default: four workgroups per
- * CU for BN_FP32, one for BN_BF16.  Results do not depend on it.
+ * CU.  Results do not depend on it.
  * Synchronises. */
 bn_status bn_set_recount_blocks(bn_problem p, uint32_t blocks);
 bn_status bn_get_profile(bn_problem p, bn_profile_stats* out);

@@ -999,18 +999,16 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   v.tch = std::min<uint32_t>(1024, v.tp);   // integrands per counting wave (fewer for small launches)
   v.slice_target = 512;
   // The colour phases share the CUs with the sweep-wide recount, which keeps
-  // the vector ALU busy with two waves per SIMD. With the FP32 phase kernels
-  // at raised wave priority, a cap of four workgroups per CU gave the fastest
-  // sweeps at 256^2, N = 256, T = 1024 (14 % faster than uncapped without
-  // the priority, 2.5 % faster than two per CU); the BF16 form (MFMA phases
-  // holding more of each CU) is fastest at one per CU, 24 % faster than
-  // uncapped.
+  // the vector ALU busy with two waves per SIMD. With the phase kernels at
+  // raised wave priority, a cap of four workgroups per CU gave the fastest
+  // event-timed sweeps at 256^2, N = 256, T = 1024 in both forms (FP32: 2.5 %
+  // faster than two per CU; BF16: 6 % faster than one per CU).
   v.count_cap = 0;
   {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      v.count_cap = (cfg->precision == BN_BF16 ? 1u : 4u) * (uint32_t)cus;
+      v.count_cap = 4u * (uint32_t)cus;
   }
   v.tg = cfg->t_gauss;
   v.tgp = round_up(v.tg, 64);

@@ -283,8 +283,8 @@ template <int R, int K, int BY, int V>
 __global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kappa, uint32_t trlen,
                                                          long long* __restrict__ xpart) {
   // the colour phases' waves issue ahead of the sweep-wide recount running
-  // beside them (k_delta_finish and k_commit likewise), which fills the
-  // remaining issue slots
+  // beside them (k_delta_finish, k_commit and the BF16 form's k_delta_mfma
+  // and k_delta_recheck likewise), which fills the remaining issue slots
   __builtin_amdgcn_s_setprio(2);
   delta_stage_body<R, K, BY, V>(v, kappa, trlen, xpart, blockIdx.x, blockIdx.y, blockIdx.z);
 }
@@ -385,6 +385,8 @@ template <int R, int BYC>
 __global__ __launch_bounds__(64 * BYC) void k_delta_mfma(DevView v, uint32_t kappa, uint32_t trlen,
                                                     long long* __restrict__ xsum,
                                                     uint32_t* __restrict__ unsure) {
+  // raised issue priority beside the sweep-wide recount, as in k_delta_stage
+  __builtin_amdgcn_s_setprio(2);
   using G = MfmaGeom<R, BYC>;
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
@@ -570,6 +572,7 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_mfma(DevView v, uint32_t kap
 template <int R>
 __global__ __launch_bounds__(256) void k_delta_recheck(DevView v, uint32_t kappa,
                                                        uint32_t* __restrict__ unsure) {
+  __builtin_amdgcn_s_setprio(2);
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
   const uint32_t lane = threadIdx.x & 63;
