@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <iterator>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -694,6 +695,16 @@ bn_status build_graph(bn_problem p) {
 }
 
 
+// Candidates of the launch-shape tuner: integrands per counting wave and the
+// workgroup target of the staged energy-change launch.
+const uint32_t kTuneTch[] = {64, 128, 256, 512};
+const uint32_t kTuneSlices[] = {128, 256, 512, 1024, 2048};
+
+bool tune_choice_valid(uint32_t tch, uint32_t slices) {
+  return std::find(std::begin(kTuneTch), std::end(kTuneTch), tch) != std::end(kTuneTch) &&
+         std::find(std::begin(kTuneSlices), std::end(kTuneSlices), slices) != std::end(kTuneSlices);
+}
+
 // (Re)build the per-group device tables from the members' current launch
 // choices.  Invalidates any captured graph.
 bn_status batch_upload(bn_batch b) {
@@ -705,6 +716,9 @@ bn_status batch_upload(bn_batch b) {
     (void)hipGraphDestroy(b->graph);
     b->graph = nullptr;
   }
+  if (!tune_choice_valid(b->tch, b->slice_target))
+    return fail(BN_EINVAL, "launch choice tch=%u slices=%u is not one of the tuner's candidates", b->tch,
+                b->slice_target);
   HIPCHK(hipStreamSynchronize(b->stream));
   for (void* q : b->allocs) (void)hipFree(q);
   b->allocs.clear();
@@ -805,16 +819,17 @@ std::string batch_key(bn_batch b) {
 // so the optimisation state is untouched) for each candidate and keeps the
 // fastest.  Results do not depend on the choice.
 bn_status batch_tune(bn_batch b) {
-  static const uint32_t tchs[] = {64, 128, 256, 512};
-  static const uint32_t slices[] = {128, 256, 512, 1024, 2048};
+  const uint32_t* tchs = kTuneTch;
+  const uint32_t* slices = kTuneSlices;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   float best = 1e30f;
   uint32_t bt = b->tch, bs = b->slice_target;
   bn_status s = BN_OK;
-  for (uint32_t tc : tchs) {
-    for (uint32_t sl : slices) {
+  for (uint32_t ti = 0; ti < std::size(kTuneTch); ++ti) {
+    for (uint32_t si = 0; si < std::size(kTuneSlices); ++si) {
+      const uint32_t tc = tchs[ti], sl = slices[si];
       b->tch = tc;
       b->slice_target = sl;
       if ((s = batch_upload(b)) != BN_OK) break;
@@ -1598,7 +1613,11 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
       while (std::fgets(line, sizeof line, f)) {
         char k[4096];
         unsigned tc = 0, sl = 0;
-        if (std::sscanf(line, "%4095s tch=%u slices=%u", k, &tc, &sl) == 3 && key == k && tc && sl) {
+        if (std::sscanf(line, "%4095s tch=%u slices=%u", k, &tc, &sl) == 3 && key == k) {
+          // only the tuner's own candidates are trusted: a chunk that is not
+          // a multiple of 64 integrands would make the counting waves' tiles
+          // overlap
+          if (!tune_choice_valid(tc, sl)) continue;
           b->tch = tc;
           b->slice_target = sl;
           cached = true;

@@ -539,7 +539,12 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_mfma(DevView v, uint32_t kap
     for (int ct = 0; ct < 3; ++ct)
 #pragma unroll
       for (int i = 0; i < 4; ++i) gsh[(4 * (lane >> 4) + i) * G::RCOLS + ct * 16 + (lane & 15)] = acc[oy][ct][i];
-    __builtin_amdgcn_s_barrier();   // wave-local: only this wave touches its gsh
+    // Only this wave touches its gsh: the lanes' LDS stores are ordered
+    // before the cross-lane reads below by a wavefront-scope release/acquire
+    // pair around a wave barrier (no workgroup barrier is needed).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane < 16) {
 #pragma unroll
       for (int ox = -R; ox <= R; ++ox) {
@@ -552,7 +557,10 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_mfma(DevView v, uint32_t kap
         zd[cidx] += (long long)gsh[b * G::RCOLS + 2 * b + R + ox];
       }
     }
-    __builtin_amdgcn_s_barrier();
+    // the reads are done before the next row's stores overwrite gsh
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   const uint32_t a = a0 + w, bb = b0 + b;
   if (lane < 16 && a < v.ch && bb < v.cw) {

@@ -81,6 +81,34 @@ def test_tune_cache_round_trip(stream, tmp_path):
         p.close()
 
 
+def test_tune_cache_rejects_foreign_choices(stream, tmp_path):
+    """A cache line for the members' key whose chunk is not one of the tuner's
+    candidates (100 integrands per counting wave would make the waves' 16-byte
+    count tiles overlap) is ignored: the tuner runs again, its valid choice is
+    appended and the batched sweep still follows the members' own sweeps."""
+    inps = [synthgen.problem_inputs(w) for w in MEMBERS[:3]]
+    probs = [make(w, inp, stream) for w, inp in zip(MEMBERS[:3], inps)]
+    probe = str(tmp_path / "probe.txt")
+    with bnlat.Batch(probs, tune_cache=probe) as b:
+        pass
+    key = open(probe).read().split()[0]
+    bad = str(tmp_path / "bad.txt")
+    with open(bad, "w") as f:
+        f.write(f"{key} tch=100 slices=2048\n{key} tch=256 slices=7\n")
+    with bnlat.Batch(probs, tune_cache=bad) as b:
+        got = b.tuning()
+        assert got["tch"] in (64, 128, 256, 512)
+        assert got["slice_target"] in (128, 256, 512, 1024, 2048)
+        b.sweep(1)
+    lines = open(bad).read().splitlines()
+    assert len(lines) == 3 and lines[2].startswith(key)
+    for w, inp, p in zip(MEMBERS[:3], inps, probs):
+        with make(w, inp, stream) as alone:
+            alone.sweep(1)
+            np.testing.assert_array_equal(p.get_offsets(), alone.get_offsets())
+        p.close()
+
+
 def test_dimension_pair_batch_equals_members_alone(stream):
     """Uneven batch shaped like the padded-sampler workload (tiles 64-256,
     N in {4, 16, 64, 256}, T = 256, 7x7 window): one batched sweep equals

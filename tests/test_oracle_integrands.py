@@ -126,3 +126,78 @@ def test_philox_heaviside_table_distribution():
     hist, _ = np.histogram(ang, bins=8, range=(-np.pi, np.pi))
     assert hist.min() > 400 and hist.max() < 600
     assert abs(t["cx"].astype(float).mean() / Q16 - 0.5) < 0.02
+
+
+def _one_point(mx, my, s, ux, uy):
+    """Estimate of one Gaussian with N = 1: the single lattice point is the
+    origin, so the only sample sits at the offset (ux, uy) / 2**16."""
+    t = {"mx": np.array([mx]), "my": np.array([my]), "s": np.array([s])}
+    return estimator.gauss_estimates(1, (1, 1), np.array([[ux, uy]]), t)[0, 0]
+
+
+def test_gaussian_estimate_off_centre_levels():
+    """Levels of an isotropic normal profile relative to its peak (Sec. 3.5's
+    Gaussians have peak 1): one standard deviation away along an axis it is
+    e^{-1/2}, two away e^{-2}, one along both axes e^{-1}, and at the half
+    maximum radius s sqrt(2 ln 2) it is one half.  Centre (0.25, 0.5) and
+    s = 1/16 are exact in Q0.16, so the sample distances are exact."""
+    mx, my, s = 0.25, 0.5, 0.0625
+    ux, uy, step = 16384, 32768, 4096          # Q0.16 of mx, my and of s
+    assert _one_point(mx, my, s, ux + step, uy) == pytest.approx(0.6065306597126334, rel=1e-14)
+    assert _one_point(mx, my, s, ux, uy - step) == pytest.approx(0.6065306597126334, rel=1e-14)
+    assert _one_point(mx, my, s, ux + 2 * step, uy) == pytest.approx(0.1353352832366127, rel=1e-14)
+    assert _one_point(mx, my, s, ux - step, uy + step) == pytest.approx(0.36787944117144233, rel=1e-14)
+    # half maximum: distance 1/8 exactly, width chosen so that 1/8 is its HWHM
+    s_half = 0.125 / math.sqrt(2.0 * math.log(2.0))
+    assert _one_point(mx, my, s_half, ux + 8192, uy) == pytest.approx(0.5, rel=1e-13)
+
+
+def test_gaussian_estimates_midpoint_grid_identity():
+    """Shifting the N = 16 lattice by every offset of the midpoint grid
+    ((a + 1/2) / G, (b + 1/2) / G), G = 512 a multiple of N, visits every
+    point of that grid exactly N times (the lattice is a subgroup of the
+    grid), so the mean estimate over those offsets is the midpoint rule of the
+    integrand, within (h^2 / 24) (sup|f_xx| + sup|f_yy|) = 1 / (12 G^2 s^2) of
+    the exact erf integral."""
+    G = 512
+    h = (1 << 16) // G
+    a = np.arange(G) * h + h // 2
+    ux, uy = np.meshgrid(a, a, indexing="xy")
+    u = np.stack([ux.ravel(), uy.ravel()], axis=1)
+    t = {"mx": np.array([0.5, 0.3, 0.8, 0.05]), "my": np.array([0.5, 0.6, 0.15, 0.9]),
+         "s": np.array([0.1, 0.2, 0.3, 0.12])}
+    est = estimator.gauss_estimates(16, (1, 7), u, t, chunk=8192).mean(axis=0)
+    for k in range(4):
+        exact = integrands.gaussian_integral(t["mx"][k], t["my"][k], t["s"][k])
+        bound = 1.0 / (12.0 * G * G * t["s"][k] ** 2)
+        assert abs(est[k] - exact) <= bound, (k, est[k], exact, bound)
+
+
+def test_gaussian_estimates_unbiased_over_random_offsets():
+    """Under a uniformly random shift every lattice point is uniform in the
+    unit square, so the mean estimate over random offsets is the integral
+    (checked to five standard errors of the sample mean)."""
+    t = synthgen.gaussian_table(6, seed=21)
+    u = synthgen.offsets(64, 64, seed=22).reshape(-1, 2)
+    est = estimator.gauss_estimates(16, (1, 7), u, t)
+    exact = integrands.gaussian_integrals(t)
+    se = est.std(axis=0, ddof=1) / math.sqrt(est.shape[0])
+    assert np.all(np.abs(est.mean(axis=0) - exact) <= 5.0 * se + 1e-12)
+
+
+def test_philox_gaussian_table_distribution():
+    """Drawn Gaussians (the config with 25 % Gaussians): centres uniform in
+    [0, 1)^2, standard deviations uniform in [0.05, 0.3]."""
+    t = integrands.gaussian_table_philox(20000, seed=5)
+    for k in ("mx", "my"):
+        assert t[k].min() >= 0.0 and t[k].max() < 1.0
+        assert abs(t[k].mean() - 0.5) < 0.01
+    s = t["s"]
+    assert s.min() >= 0.05 and s.max() <= 0.3
+    assert s.min() < 0.0501 and s.max() > 0.2999
+    assert abs(s.mean() - 0.175) < 0.002
+    hist, _ = np.histogram(s, bins=5, range=(0.05, 0.3))
+    assert hist.min() > 3700 and hist.max() < 4300
+    # the three parameters come from different words: no linear dependence
+    assert abs(np.corrcoef(t["mx"], s)[0, 1]) < 0.03
+    assert abs(np.corrcoef(t["mx"], t["my"])[0, 1]) < 0.03
