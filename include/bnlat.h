@@ -203,6 +203,23 @@ bn_status bn_get_points(bn_problem p, uint32_t pixel, uint16_t* host);
  * (nullable): uint16 [m][T] recounted hits.  m <= H*W.  Synchronises. */
 bn_status bn_delta_energy(bn_problem p, const uint32_t* pixels, const uint16_t* proposals,
                           uint32_t m, double* out_de, uint16_t* out_counts);
+/* Allocation-free variant of bn_delta_energy, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * bn_delta_energy; its list buffers (pixels, proposals, recounted hits,
+ * energy changes, decisions, Gaussian estimates and, when out_counts is
+ * given, the hits in row layout) live in a fixed 32 MiB scratch array that
+ * the library holds on each GPU until the process ends, instead of buffers
+ * the problem allocates.  It calls no hipMalloc/hipFree.  A call whose lists
+ * do not fit returns BN_EINVAL before any device work: each pixel takes about
+ * 2 Tp + 4 TGp + 25 bytes (Tp = T rounded up to 128, TGp = T_G rounded up to
+ * 64) plus 2 T with out_counts, e.g. about 8000 pixels at T = 1024.  Every
+ * call on a GPU shares that GPU's array and leaves its contents behind
+ * (nothing in it has to start at zero); calls that overlap in time on one GPU
+ * (from several host threads or streams) race and must be serialised by the
+ * caller.  Synchronises the problem's stream. */
+bn_status bn_delta_energy_noalloc(bn_problem p, const uint32_t* pixels, const uint16_t* proposals,
+                                  uint32_t m, double* out_de, uint16_t* out_counts);
 bn_status bn_get_sweep_index(bn_problem p, uint64_t* out);
 bn_status bn_set_sweep_index(bn_problem p, uint64_t sweep);
 

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "bn_get_integrands": [_P, _P, _P, _P, _P],
     "bn_get_points": [_P, C.c_uint32, _P],
     "bn_delta_energy": [_P, _P, _P, C.c_uint32, _P, _P],
+    "bn_delta_energy_noalloc": [_P, _P, _P, C.c_uint32, _P, _P],
     "bn_get_sweep_index": [_P, C.POINTER(C.c_uint64)],
     "bn_set_sweep_index": [_P, C.c_uint64],
     "bn_set_profiling": [_P, C.c_int],
@@ -311,6 +312,17 @@ class Problem:
         de = np.zeros(m, dtype=np.float64)
         cn = np.zeros((m, self.T), dtype=np.uint16) if counts else None
         _call("bn_delta_energy", self.handle, _ptr(px), _ptr(pr), m, _ptr(de), _ptr(cn))
+        return (de, cn) if counts else de
+
+    def delta_energy_noalloc(self, pixels, proposals, counts: bool = False):
+        """bn_delta_energy_noalloc: the same as delta_energy, with its list
+        buffers in the library's fixed per-GPU scratch array."""
+        px = np.ascontiguousarray(pixels, dtype=np.uint32)
+        pr = np.ascontiguousarray(proposals, dtype=np.uint16).reshape(-1, 2)
+        m = px.shape[0]
+        de = np.zeros(m, dtype=np.float64)
+        cn = np.zeros((m, self.T), dtype=np.uint16) if counts else None
+        _call("bn_delta_energy_noalloc", self.handle, _ptr(px), _ptr(pr), m, _ptr(de), _ptr(cn))
         return (de, cn) if counts else de
 
     def get_sweep_index(self) -> int:

@@ -165,6 +165,7 @@ struct bn_problem_s {
   bn_config cfg{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int device = 0;   // the GPU the problem's buffers live on
   DevView v{};
   std::vector<bn_heaviside> heav;
   std::vector<double> area64;
@@ -364,6 +365,35 @@ bn_status ensure_list(bn_problem p, uint32_t m) {
   if ((s = p->alloc(&p->list_gdelta, m)) != BN_OK) return s;
   p->list_cap = m;
   return BN_OK;
+}
+
+// Regions of one pixel list carved from a fixed scratch area (256-byte
+// aligned); with a null base it only measures.
+struct Carve {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* r = (T*)(base + off);
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return r;
+  }
+};
+
+// The list buffers of a delta-energy call over m pixels (and, when untiled
+// counts are returned, their row layout) in scratch area c.
+DevView list_view_in(bn_problem p, Carve& c, uint32_t m, bool counts, uint16_t** rows) {
+  DevView lv = p->v;
+  lv.pix_list = c.take<uint32_t>(m);
+  lv.u_new = c.take<uint32_t>(m);
+  lv.c_new = c.take<uint16_t>((size_t)m * p->v.tp);
+  lv.delta = c.take<double>(m);
+  lv.accept = c.take<uint8_t>(m);
+  lv.g_new = c.take<float>((size_t)m * std::max<uint32_t>(p->v.tgp, 1));
+  lv.gdelta = c.take<double>(m);
+  *rows = counts ? c.take<uint16_t>((size_t)m * p->v.t) : nullptr;
+  return lv;
 }
 
 // Bring the FP32 error vectors up to date with the counts.
@@ -976,6 +1006,11 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
 
   bn_problem p = new bn_problem_s();
   p->cfg = *cfg;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return fail(BN_EHIP, "hipGetDevice failed");
+  }
   p->heav = heav;
   p->area64 = area;
   p->gauss = gauss;
@@ -1350,6 +1385,40 @@ bn_status bn_delta_energy(bn_problem p, const uint32_t* pixels, const uint16_t* 
   HIPCHK(launch_delta(lv, MODE_LIST, 0, m, p->stream));
   HIPCHK(hipMemcpyAsync(out_de, p->list_delta, (size_t)m * 8, hipMemcpyDeviceToHost, p->stream));
   if (out_counts) return untile_counts(p, p->list_cnt, m, out_counts);
+  return sync(p);
+}
+
+bn_status bn_delta_energy_noalloc(bn_problem p, const uint32_t* pixels, const uint16_t* proposals, uint32_t m,
+                                  double* out_de, uint16_t* out_counts) {
+  if (!p || (m && (!pixels || !proposals || !out_de))) return fail(BN_EINVAL, "NULL argument");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  const uint32_t P = p->v.w * p->v.h;
+  if (m > P) return fail(BN_EINVAL, "m=%u exceeds the pixel count", m);
+  for (uint32_t i = 0; i < m; ++i)
+    if (pixels[i] >= P) return fail(BN_EINVAL, "pixel %u out of range", pixels[i]);
+  if (m == 0) return BN_OK;
+  uint16_t* rows = nullptr;
+  Carve measure;
+  (void)list_view_in(p, measure, m, out_counts != nullptr, &rows);
+  if (measure.off > NOALLOC_SCRATCH_BYTES)
+    return fail(BN_EINVAL, "%u pixels need %zu bytes of scratch; the allocation-free entry point holds %zu",
+                m, measure.off, NOALLOC_SCRATCH_BYTES);
+  void* base = nullptr;
+  HIPCHK(noalloc_scratch(p->device, &base));
+  Carve c;
+  c.base = (char*)base;
+  const DevView lv = list_view_in(p, c, m, out_counts != nullptr, &rows);
+  HIPCHK(hipMemcpyAsync((void*)lv.pix_list, pixels, (size_t)m * 4, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(lv.u_new, proposals, (size_t)m * 4, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(launch_count(lv, MODE_LIST, 0, m, p->stream));
+  HIPCHK(launch_gauss_est(lv, MODE_LIST, m, p->stream));
+  HIPCHK(launch_gauss_delta(lv, MODE_LIST, 0, m, p->stream));
+  HIPCHK(launch_delta(lv, MODE_LIST, 0, m, p->stream));
+  HIPCHK(hipMemcpyAsync(out_de, lv.delta, (size_t)m * 8, hipMemcpyDeviceToHost, p->stream));
+  if (out_counts) {
+    HIPCHK(launch_untile_counts(lv.c_new, m, p->v.t, rows, p->stream));
+    HIPCHK(hipMemcpyAsync(out_counts, rows, (size_t)m * p->v.t * 2, hipMemcpyDeviceToHost, p->stream));
+  }
   return sync(p);
 }
 

@@ -16,6 +16,8 @@ constexpr uint32_t S_PROP = 0xC;
 constexpr uint32_t T_ALIGN = 128;
 constexpr uint32_t MAX_RADIUS = 8;
 constexpr uint32_t MAX_N = 4096;
+// Size of the per-GPU scratch array of the allocation-free entry point.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)32 << 20;
 
 // MODE_SWEEP: proposals of every pixel of a sweep, rows grouped by colour
 // class ([class][class pixel]); the kernel argument kappa is then the sweep
@@ -92,5 +94,10 @@ hipError_t launch_finish_batch(const DevView* views, const uint32_t* pre, uint32
 hipError_t launch_commit_batch(const DevView* views, const uint32_t* pre, uint32_t nmem, uint32_t blocks,
                                uint32_t kappa, hipStream_t s);
 hipError_t launch_advance_batch(const DevView* views, uint32_t nmem, hipStream_t s);
+
+// allocation-free entry point: device address of the scratch array on
+// `device` (located once per device), and tiled counts -> host row layout
+hipError_t noalloc_scratch(int device, void** ptr);
+hipError_t launch_untile_counts(const uint16_t* tiled, uint32_t rows, uint32_t t, uint16_t* out, hipStream_t s);
 
 }  // namespace bnlat
