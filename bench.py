@@ -31,6 +31,8 @@ METRIC = "pixel-updates/sec at 256² tile, T=1024, N=256; HBM GB/s vs peak; BF16
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit vector lane-operations per second
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# dense BF16 matrix-core peak (vendor), TFLOP/s
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tile256_n256_t1024_fp32.md")
@@ -64,35 +66,77 @@ def measured_traffic():
     return None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_POOL = {}
+
+
+def _pool_init(n, g, table):
+    _POOL.update(n=n, g=g, table=table)
+
+
+def _pool_counts(u):
+    from oracle import estimator
+    return estimator.hit_counts(_POOL["n"], _POOL["g"], u, _POOL["table"])
+
+
 def cpu_baseline(w: dict, inp: dict, sweeps: int = 128, row_pixels: int = 128) -> dict:
     """The oracle timed on a band of class-0 pixels (one class row) of the same
     workload: proposals, recount, energy change and commit, repeated over
-    ``sweeps`` sweeps.  The window state of the band is computed first (not
-    timed)."""
+    ``sweeps`` sweeps, once on one core and once with the recounts of each
+    sweep's pixels spread over a pool of worker processes (the class pixels of
+    a phase are independent: snapshot semantics).  The window state of the
+    band is computed first (not timed).  Runs before the GPU is initialised,
+    so the pool's processes are plain forks of a CPU-only process."""
+    import multiprocessing as mp
     from oracle import energy, estimator, sweep as osw
 
     W, H, T, r = w["width"], w["height"], w["t_heaviside"], w["radius"]
     ref = osw.Problem(n=w["n"], g=w["g"], width=W, height=H, radius=r, sigma=w["sigma"],
                       colour_k=w["colour_k"], seed=w["seed"], problem_id=0, table=inp["heaviside"])
     u0 = inp["offsets"].reshape(-1, 2).astype(np.int64)
-    c = np.zeros((H, W, T), dtype=np.int16)
+    c0 = np.zeros((H, W, T), dtype=np.int16)
     rows = [(y + H) % H for y in range(-r, r + 1)]
     for y in rows:
-        c[y] = estimator.hit_counts(w["n"], w["g"], u0[y * W:(y + 1) * W], inp["heaviside"])
+        c0[y] = estimator.hit_counts(w["n"], w["g"], u0[y * W:(y + 1) * W], inp["heaviside"])
     xs = np.arange(0, W, w["colour_k"])[:row_pixels]
     ys = np.zeros_like(xs)
-    t0 = time.perf_counter()
-    for s in range(sweeps):
-        u_new = osw.proposals(ref, ys, xs, s).astype(np.int64)
-        c_new = estimator.hit_counts(w["n"], w["g"], u_new, inp["heaviside"])
-        d = energy.weighted_class_sum(energy.delta_class_sums(c, ys, xs, c_new, r), r, w["sigma"])
-        acc = d < 0.0
-        c[ys[acc], xs[acc]] = c_new[acc]
-    dt = time.perf_counter() - t0
-    return {"value": sweeps * len(xs) / dt, "unit": "pixel-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sweeps} sweeps x {len(xs)} class-0 pixels of one row (recount N*T predicates "
-                      f"+ exact energy change + commit), numpy FP64/int64 oracle, single thread",
-            "seconds": dt}
+
+    def run(recount):
+        c = c0.copy()
+        t0 = time.perf_counter()
+        for s in range(sweeps):
+            u_new = osw.proposals(ref, ys, xs, s).astype(np.int64)
+            c_new = recount(u_new)
+            d = energy.weighted_class_sum(energy.delta_class_sums(c, ys, xs, c_new, r), r, w["sigma"])
+            acc = d < 0.0
+            c[ys[acc], xs[acc]] = c_new[acc]
+        return time.perf_counter() - t0, c
+
+    dt1, c1 = run(lambda u: estimator.hit_counts(w["n"], w["g"], u, inp["heaviside"]))
+    cores = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(cores, initializer=_pool_init,
+                                     initargs=(w["n"], w["g"], inp["heaviside"])) as pool:
+        pool.map(_pool_counts, np.array_split(u0[:cores], cores))   # workers up
+        dtn, cn = run(lambda u: np.concatenate(pool.map(_pool_counts, np.array_split(u, cores))))
+    assert np.array_equal(c1, cn)
+    sample = (f"{sweeps} sweeps x {len(xs)} class-0 pixels of one row (recount N*T predicates "
+              f"+ exact energy change + commit), numpy FP64/int64 oracle")
+    return {"value": sweeps * len(xs) / dt1, "unit": "pixel-updates/s", "cores": 1, "kind": "oracle",
+            "sample": sample + ", single thread", "seconds": dt1, "cpu_model": cpu_model(),
+            "nproc": os.cpu_count(),
+            "all_cores": {"value": sweeps * len(xs) / dtn, "unit": "pixel-updates/s", "cores": cores,
+                          "kind": "oracle", "seconds": dtn,
+                          "sample": sample + f", recounts spread over {cores} worker processes, "
+                                             "energy changes and commits in the parent"}}
 
 
 SIGMAS_B = [0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 20.0]
@@ -168,6 +212,16 @@ def main() -> int:
                                    "and multi-tile sharding is not built for several GPUs", "n_gpus": args.gpus}))
         return 2
 
+    w = dict(synthgen.WORKLOADS[args.workload])
+    inp = synthgen.problem_inputs(w)
+    # the CPU baseline runs first: its worker pool forks a process that has
+    # not initialised the GPU
+    cpu = None
+    if not args.no_cpu_baseline and args.experiment is None:
+        cpu = cpu_baseline(w, inp)
+        print(f"cpu baseline: {cpu['value']:.1f} pixel-updates/s on 1 core, "
+              f"{cpu['all_cores']['value']:.1f} on {cpu['all_cores']['cores']}", file=sys.stderr, flush=True)
+
     import torch
     from paper_2105_12620_amd import bnlat
 
@@ -175,8 +229,11 @@ def main() -> int:
     if args.experiment == "quality":
         print(json.dumps(quality_experiment(args.sweeps)), flush=True)
         return 0
-    w = dict(synthgen.WORKLOADS[args.workload])
-    inp = synthgen.problem_inputs(w)
+    # this GPU's attainable peaks: a 4 GiB device copy, v_dot2 chains, BF16 MFMA chains
+    peaks = {"hbm_gbs": bnlat.measure_peak(bnlat.BN_PEAK_HBM_COPY, 4 << 30, 5) / 1e9,
+             "valu_tops": bnlat.measure_peak(bnlat.BN_PEAK_VALU_DOT2, 0, 5) / 1e12,
+             "mfma_bf16_tflops": bnlat.measure_peak(bnlat.BN_PEAK_MFMA_BF16, 0, 5) / 1e12}
+    print(f"measured peaks: {peaks}", file=sys.stderr, flush=True)
     stream = torch.cuda.Stream()
     K2 = w["colour_k"] ** 2
     P, T, N = w["width"] * w["height"], w["t_heaviside"], w["n"]
@@ -265,7 +322,9 @@ def main() -> int:
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         pix = sum(mw["width"] * mw["height"] for mw in members)
+        ops = sum(2.0 * mw["width"] * mw["height"] * mw["n"] * mw["t_heaviside"] for mw in members)
         out = {"value": pix * steps / (ms * 1e-3), "unit": "pixel-updates/s", "members": len(members),
+               "count_lane_ops_per_sweep": ops,
                "pixels": pix, "sweeps": steps, "ms_per_sweep": ms / steps, "tuning": b.tuning(),
                "shapes": [f"{mw['width']}^2/N{mw['n']}" for mw in members]}
         b.close()
@@ -309,15 +368,27 @@ def main() -> int:
 
     big = large() if "large" in forms else None
 
-    # algorithmic work per launch of the counting kernel: one sweep-wide recount
-    # per (sample, integrand): one v_dot2, half a v_perm_b32 (two integrands'
-    # sign bits per word) and a quarter of a v_add3_u32 (two words per add)
-    count_ops = 1.75 * P * N * T
+    # Algorithmic work per launch of the counting kernel (one sweep-wide
+    # recount): N*T predicates per proposal at two vector lane-operations each
+    # (int16 dot product + sign test).  The kernel's own instruction count is
+    # 1.75 per predicate (one v_dot2, half a v_perm_b32, a quarter of a
+    # v_add3_u32), reported beside it.
+    count_ops = 2.0 * P * N * T
     count_tops = count_ops / (avg["recount_per_sweep"] * 1e-3) / 1e12
     win = (2 * w["radius"] + 1) ** 2 - 1
     # evaluation of a phase: the tile's counts once (2 B each) plus the moved
     # pixels' proposal rows, and the decisions
     delta_bytes = 2.0 * T * (P + M) + 9.0 * M
+    # a swap pass reads the tile's counts once
+    swap_bytes = 2.0 * T * P
+
+    def roof(bound, achieved, unit, kernel, work):
+        vendor = {"hbm": HBM_PEAK_GBS, "alu": VALU_PEAK_TOPS, "mfma": MFMA_BF16_PEAK_TFLOPS}[bound]
+        meas = {"hbm": peaks["hbm_gbs"], "alu": peaks["valu_tops"], "mfma": peaks["mfma_bf16_tflops"]}[bound]
+        return {"bound": bound, "kernel": kernel, "achieved": achieved, "peak": vendor, "unit": unit,
+                "frac": achieved / vendor, "peak_measured": meas, "frac_measured": achieved / meas,
+                "work_per_launch": work}
+
     value = P * args.steps / (total_ms * 1e-3)
     out = {
         "metric": METRIC, "value": value, "unit": "pixel-updates/s", "n_gpus": 1,
@@ -327,16 +398,20 @@ def main() -> int:
         "config": {"workload": args.workload, "tile": f"{w['width']}x{w['height']}", "n": N, "t": T,
                    "window": f"{2 * w['radius'] + 1}x{2 * w['radius'] + 1}", "colour_classes": K2,
                    "precision": "fp32", "mutation": "redraw"},
-        "roofline": {"bound": "alu", "kernel": "k_count<64, 4, 3> (sweep-wide proposal recount)",
-                     "achieved": count_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": count_tops / VALU_PEAK_TOPS, "traffic": measured_traffic(),
-                     "work_per_launch": f"{P} pixels x {N} samples x {T} integrands x 1.75 lane-ops"},
+        "roofline": dict(roof("alu", count_tops, "TOP/s", "k_count<64, 4, 3> (sweep-wide proposal recount)",
+                              f"{P} pixels x {N} samples x {T} integrands x 2 lane-ops"),
+                         traffic=measured_traffic(),
+                         frac_at_instruction_count=0.875 * count_tops / VALU_PEAK_TOPS),
+        "measured_peaks": peaks,
         "kernels_ms": avg,
         "evaluate_hbm_gbs": delta_bytes / (avg["evaluate_per_phase"] * 1e-3) / 1e9,
         "evaluate_hbm_frac": delta_bytes / (avg["evaluate_per_phase"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "evaluate_alone": {"ms_per_phase": fp32["evaluate_alone_ms"],
                            "hbm_gbs": delta_bytes / (fp32["evaluate_alone_ms"] * 1e-3) / 1e9,
-                           "frac": delta_bytes / (fp32["evaluate_alone_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                           "frac": delta_bytes / (fp32["evaluate_alone_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "roofline": roof("hbm", delta_bytes / (fp32["evaluate_alone_ms"] * 1e-3) / 1e9,
+                                            "GB/s", "k_delta_stage + k_delta_finish (one colour phase, alone)",
+                                            f"tile counts once + {M} proposal rows, 2 B per integrand")},
         "graph_value": P * args.steps / (fp32["graph_ms"] * 1e-3),
         "bf16": None if bf16 is None else {
             "value": P * args.steps / (bf16["total_ms"] * 1e-3),
@@ -344,6 +419,10 @@ def main() -> int:
             "kernels_ms": bf16["kernels_ms"],
             "evaluate_hbm_gbs": delta_bytes / (bf16["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9,
             "evaluate_alone_ms_per_phase": bf16["evaluate_alone_ms"],
+            "roofline": roof("hbm", delta_bytes / (bf16["evaluate_alone_ms"] * 1e-3) / 1e9, "GB/s",
+                             "BF16 matrix-core energy change of one colour phase, run alone",
+                             f"tile counts once + {M} proposal rows, 2 B per integrand"),
+            "mfma_useful_tflops": 2.0 * win * T * M / (bf16["evaluate_alone_ms"] * 1e-3) / 1e12,
             "energy_rel_diff_vs_fp32": abs(bf16["energy"] - fp32["energy"]) / abs(fp32["energy"]),
             "quality_rel_diff_vs_fp32": max(abs(a - b) / b for a, b in zip(bf16["quality_sigma_1_4_16"],
                                                                             fp32["quality_sigma_1_4_16"]))},
@@ -354,13 +433,19 @@ def main() -> int:
             "kernels_ms": {"evaluate_per_pass": swap["kernels_ms"]["evaluate_per_phase"],
                            "commit_per_pass": swap["kernels_ms"]["commit_per_phase"],
                            "passes": swap["kernels_ms"]["phases"]},
-            "evaluate_hbm_gbs": delta_bytes / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9},
-        "batched": batch,
+            "evaluate_hbm_gbs": swap_bytes / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9,
+            "roofline": roof("hbm", swap_bytes / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9, "GB/s",
+                             "k_swap_stage + k_swap_finish (one swap pass)",
+                             f"tile counts once ({P} pixels x {T} integrands x 2 B)")},
+        "batched": None if batch is None else dict(batch, roofline=roof(
+            "alu", batch["count_lane_ops_per_sweep"] / (batch["ms_per_sweep"] * 1e-3) / 1e12, "TOP/s",
+            "whole batched sweep (recounts of every member's proposals over the sweep time)",
+            "sum over members of P N T x 2 lane-ops")),
         "batched_large": big,
         "window_offsets": win,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, inp)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 

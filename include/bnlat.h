@@ -270,6 +270,26 @@ bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* d
  * BN_ESTATE for swap problems and bn_get_swap_pass for redraw problems. */
 bn_status bn_get_swap_pass(bn_problem p, uint32_t* a, uint32_t* b, double* delta, uint8_t* accept);
 
+/* -------------------------------------------------------------- measurement */
+
+/* Attainable device peaks, the denominators of measured roofline fractions
+ * (measurement infrastructure, not part of the method).  Each kind times a
+ * plain loop on the current device and returns the best of `reps` launches
+ * (1..1000) in *out:
+ *   BN_PEAK_HBM_COPY   device-to-device copy of `bytes` (a multiple of 16,
+ *                      >= 1 MiB; the library allocates and frees two buffers
+ *                      of that size), by the library's copy kernel and by the
+ *                      runtime's hipMemcpyAsync in alternate repetitions (the
+ *                      better rate is returned): bytes read + written per
+ *                      second;
+ *   BN_PEAK_VALU_DOT2  independent chains of v_dot2_i32_i16 in eight
+ *                      workgroups of 256 threads per CU: lane-operations per
+ *                      second (`bytes` ignored);
+ *   BN_PEAK_MFMA_BF16  independent v_mfma_f32_32x32x16_bf16 accumulations,
+ *                      same launch: dense BF16 flops per second. */
+typedef enum { BN_PEAK_HBM_COPY = 0, BN_PEAK_VALU_DOT2 = 1, BN_PEAK_MFMA_BF16 = 2 } bn_peak;
+bn_status bn_measure_peak(bn_peak kind, uint64_t bytes, uint32_t reps, double* out);
+
 /* ------------------------------------------------------------ sampler query */
 
 /* The padded screen-space sampler a renderer reads (Sec. 3.1: dimensions are

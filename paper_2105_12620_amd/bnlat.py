@@ -20,6 +20,7 @@ BN_OK, BN_EINVAL, BN_ENOMEM, BN_EHIP, BN_ESTATE, BN_EUNSUPPORTED, BN_ENUMERIC = 
 BN_FP32, BN_BF16 = 0, 1
 BN_REDRAW, BN_SWAP = 0, 1
 BN_ROWS_ALL, BN_ROWS_HEAVISIDE, BN_ROWS_GAUSSIAN = 0, 1, 2
+BN_PEAK_HBM_COPY, BN_PEAK_VALU_DOT2, BN_PEAK_MFMA_BF16 = 0, 1, 2
 
 
 class BnlatError(RuntimeError):
@@ -98,6 +99,7 @@ _SIGNATURES = {
     "bn_draw_heavisides": [C.c_uint64, C.c_uint32, C.c_uint32, _P],
     "bn_draw_gaussians": [C.c_uint64, C.c_uint32, C.c_uint32, _P],
     "bn_gaussian_integral": [C.POINTER(Gaussian), C.POINTER(C.c_double)],
+    "bn_measure_peak": [C.c_int, C.c_uint64, C.c_uint32, C.POINTER(C.c_double)],
 }
 
 _lib = None
@@ -203,6 +205,13 @@ def gaussian_integral(mx, my, s) -> float:
     g = Gaussian(float(mx), float(my), float(s))
     out = C.c_double()
     _call("bn_gaussian_integral", C.byref(g), C.byref(out))
+    return out.value
+
+
+def measure_peak(kind: int, nbytes: int = 0, reps: int = 5) -> float:
+    """Best rate of a plain device loop: bytes/s (copy), lane-ops/s (dot2) or flop/s (BF16 MFMA)."""
+    out = C.c_double()
+    _call("bn_measure_peak", kind, nbytes, reps, C.byref(out))
     return out.value
 
 

@@ -1422,6 +1422,68 @@ bn_status bn_delta_energy_noalloc(bn_problem p, const uint32_t* pixels, const ui
   return sync(p);
 }
 
+bn_status bn_measure_peak(bn_peak kind, uint64_t bytes, uint32_t reps, double* out) {
+  if (!out) return fail(BN_EINVAL, "out is NULL");
+  if (kind != BN_PEAK_HBM_COPY && kind != BN_PEAK_VALU_DOT2 && kind != BN_PEAK_MFMA_BF16)
+    return fail(BN_EINVAL, "unknown peak kind %d", (int)kind);
+  if (reps < 1 || reps > 1000) return fail(BN_EINVAL, "reps must lie in [1, 1000]");
+  if (kind == BN_PEAK_HBM_COPY && (bytes < (1u << 20) || bytes % 16))
+    return fail(BN_EINVAL, "copy size must be a multiple of 16 bytes and at least 1 MiB");
+  bn_status s = check_device();
+  if (s != BN_OK) return s;
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const uint32_t blocks = 8u * (uint32_t)cus;   // eight workgroups of four waves per CU
+  const uint32_t iters = kind == BN_PEAK_VALU_DOT2 ? 20000u : 4000u;
+  const size_t nbuf = kind == BN_PEAK_HBM_COPY ? (size_t)bytes : (size_t)blocks * 256 * 4;
+  void *a = nullptr, *b = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+  };
+  hipError_t e = hipMalloc(&a, nbuf);
+  if (e == hipSuccess && kind == BN_PEAK_HBM_COPY) e = hipMalloc(&b, nbuf);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(BN_ENOMEM, "peak buffers of %zu bytes: %s", nbuf, hipGetErrorString(e));
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemsetAsync(a, 1, nbuf, st);
+  if (e == hipSuccess) e = peak_launch((int)kind, a, b, nbuf, iters, blocks, st);   // warm-up
+  double best = 0.0;
+  for (uint32_t r = 0; r < reps && e == hipSuccess; ++r) {
+    // copies: odd repetitions time the runtime's own device-to-device copy,
+    // even ones the library's copy kernel; the better rate is kept
+    const bool rt_copy = kind == BN_PEAK_HBM_COPY && (r & 1);
+    e = hipEventRecord(e0, st);
+    if (e == hipSuccess)
+      e = rt_copy ? hipMemcpyAsync(b, a, nbuf, hipMemcpyDeviceToDevice, st)
+                  : peak_launch((int)kind, a, b, nbuf, iters, blocks, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess || ms <= 0.f) break;
+    const double work = kind == BN_PEAK_HBM_COPY ? 2.0 * (double)nbuf
+                        : kind == BN_PEAK_VALU_DOT2 ? (double)blocks * 256.0 * iters * 8.0
+                                                    : (double)blocks * 4.0 * iters * 4.0 * 32768.0;
+    best = std::max(best, work / (ms * 1e-3));
+  }
+  release();
+  if (e != hipSuccess) return fail(BN_EHIP, "peak measurement: %s", hipGetErrorString(e));
+  *out = best;
+  return BN_OK;
+}
+
 bn_status bn_set_profiling(bn_problem p, int enable) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   bn_status s = sync(p);

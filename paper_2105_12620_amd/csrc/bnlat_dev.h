@@ -95,6 +95,11 @@ hipError_t launch_commit_batch(const DevView* views, const uint32_t* pre, uint32
                                uint32_t kappa, hipStream_t s);
 hipError_t launch_advance_batch(const DevView* views, uint32_t nmem, hipStream_t s);
 
+// device peak loops: kind 0 copy (buf -> buf2, size bytes), 1 dot2 chains,
+// 2 BF16 MFMA accumulations (iters iterations each); blocks workgroups of 256
+hipError_t peak_launch(int kind, void* buf, void* buf2, uint64_t size, uint32_t iters, uint32_t blocks,
+                       hipStream_t s);
+
 // allocation-free entry point: device address of the scratch array on
 // `device` (located once per device), and tiled counts -> host row layout
 hipError_t noalloc_scratch(int device, void** ptr);
