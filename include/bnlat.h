@@ -56,13 +56,24 @@ typedef enum {
   BN_ENUMERIC = -6      /* non-finite or out-of-range numeric result          */
 } bn_status;
 
-/* Arithmetic of the energy-change evaluation (the neighbourhood Gram part).
- * BN_FP32: integer hit counts and FP32 error vectors on the vector ALUs.
- * BN_BF16: hit counts in BF16 on the matrix cores with FP32 accumulation
- *          (N <= 256, K = 2); a slice whose partial sums could exceed 2^24
- *          flags its pixels and accepted flagged moves are re-checked with
- *          the exact integer form.  For N > 256 (counts not exact in BF16)
- *          the exact integer stencil runs instead.                          */
+/* Arithmetic of the colour phases' energy change (Eq. (1) over the window).
+ * BN_FP32: exact integer class sums of the hit counts on the vector ALUs
+ *          (Gaussian rows: FP64 arithmetic on FP32 estimates).
+ * BN_BF16: the neighbour (Gram) products sum_t d_t e_{p+o,t}, d = e' - e, on
+ *          the matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation)
+ *          from a BF16 copy of the error field kept in device memory; the
+ *          self term W sum_t d_t (e'_t + e_t) stays in full precision.
+ *          - N <= 256 with Heaviside rows only: the operands are the hit
+ *            counts and their changes, exact in BF16, and a slice whose
+ *            partial sums stay below 2^24 is exact; decisions equal BN_FP32's
+ *            (uncertified accepted moves are re-checked exactly).
+ *          - otherwise: the operands are e = c/N - A (g - I for Gaussians)
+ *            formed in FP32 and rounded to BF16, and d rounded to BF16: an
+ *            approximate energy change.  Every move it accepts is
+ *            re-evaluated with the BN_FP32 arithmetic and committed only if
+ *            that accepts it too (else counted in bf16_vetoes); moves it
+ *            rejects stay rejected.
+ *          colour_k must be 1, 2 or 4; redraw moves only.                   */
 typedef enum { BN_FP32 = 0, BN_BF16 = 1 } bn_precision;
 
 /* Mutation.
@@ -168,6 +179,13 @@ bn_status bn_sweep(bn_problem p, uint32_t k, bn_sweep_stats* stats);
  * distance class and combined in FP64.  Synchronises. */
 bn_status bn_energy(bn_problem p, double* out);
 
+/* BF16 precision form only: Eq. (1) over the window evaluated from the BF16
+ * field (FP32 squares per 8 integrands, FP64 sums): the counts' exact energy
+ * when N <= 256 with Heaviside rows only, else the energy of the BF16-rounded
+ * error vectors, to be compared with bn_energy's FP64 value (the error of
+ * the form).  BN_ESTATE for BN_FP32 problems.  Synchronises. */
+bn_status bn_energy_bf16(bn_problem p, double* out);
+
 /* Blur criterion of Sec. 3.3 / Fig. 1c: for each sigmas[i] > 0,
  * out[i] = sqrt(mean_{p,t} ((k_sigma * e_t)(p))^2) over all T + T_G rows, with k_sigma the
  * normalised Gaussian of standard deviation sigma periodised on the torus,
@@ -261,6 +279,12 @@ bn_status bn_phase_commit(bn_problem p, uint32_t kappa);
 bn_status bn_phase_advance(bn_problem p);
 bn_status bn_get_phase(bn_problem p, uint16_t* u_new, uint16_t* c_new, double* delta,
                        uint8_t* accept);
+
+/* BF16 form: the last phase's energy changes as the matrix-core pass
+ * computed them, before the exact re-evaluation of accepted moves
+ * (bn_get_phase's delta holds the re-evaluated value for those):
+ * delta_bf16 double [M].  BN_ESTATE for BN_FP32 problems.  Synchronises. */
+bn_status bn_get_phase_bf16(bn_problem p, double* delta_bf16);
 
 /* Swap problems (BN_SWAP): the phase steps above run swap pass kappa
  * (propose lists the pass's couples, evaluate decides them, commit exchanges

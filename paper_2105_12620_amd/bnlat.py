@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbnlat.so")
+# BNLAT_LIB names another build of the same library (e.g. a host-sanitized test build)
+LIB_PATH = os.environ.get("BNLAT_LIB") or os.path.join(HERE, "libbnlat.so")
 
 BN_OK, BN_EINVAL, BN_ENOMEM, BN_EHIP, BN_ESTATE, BN_EUNSUPPORTED, BN_ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 BN_FP32, BN_BF16 = 0, 1
@@ -66,6 +67,8 @@ _SIGNATURES = {
     "bn_compute_errors": [_P],
     "bn_sweep": [_P, C.c_uint32, C.POINTER(SweepStats)],
     "bn_energy": [_P, C.POINTER(C.c_double)],
+    "bn_energy_bf16": [_P, C.POINTER(C.c_double)],
+    "bn_get_phase_bf16": [_P, _P],
     "bn_quality_metric": [_P, _P, C.c_uint32, _P],
     "bn_quality_metric_family": [_P, C.c_int, _P, C.c_uint32, _P],
     "bn_get_offsets": [_P, _P],
@@ -274,6 +277,12 @@ class Problem:
         _call("bn_energy", self.handle, C.byref(out))
         return out.value
 
+    def energy_bf16(self) -> float:
+        """Eq. (1) from the BF16 field (BF16 precision form only)."""
+        out = C.c_double()
+        _call("bn_energy_bf16", self.handle, C.byref(out))
+        return out.value
+
     def quality_metric(self, sigmas, rows: int = 0) -> np.ndarray:
         """Blur criterion per sigma over all rows (0), Heaviside rows (1) or Gaussian rows (2)."""
         s = np.ascontiguousarray(sigmas, dtype=np.float64)
@@ -373,6 +382,12 @@ class Problem:
         a = np.zeros(self.M, dtype=np.uint8)
         _call("bn_get_phase", self.handle, _ptr(u), _ptr(c), _ptr(d), _ptr(a))
         return {"u_new": u, "c_new": c, "delta": d, "accept": a.astype(bool)}
+
+    def get_phase_bf16(self) -> np.ndarray:
+        """Energy changes of the last phase from the BF16 matrix-core pass."""
+        d = np.zeros(self.M, dtype=np.float64)
+        _call("bn_get_phase_bf16", self.handle, _ptr(d))
+        return d
 
     def get_swap_pass(self):
         """Couples of the last evaluated swap pass: pixels a, b, delta, accept."""

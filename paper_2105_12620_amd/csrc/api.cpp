@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -22,6 +23,33 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// Diagnostics, read from the environment at each use:
+//   BNLAT_LOG=1          failures and problem creation / destruction are
+//                        reported on stderr, one line each;
+//   BNLAT_FAULT=alloc:K  the K-th device allocation of every problem being
+//                        created (counted from 1) fails as if the device were
+//                        out of memory: the error paths can be exercised.
+bool log_on() {
+  const char* e = std::getenv("BNLAT_LOG");
+  return e && *e && std::strcmp(e, "0") != 0;
+}
+
+void log_msg(const char* fmt, ...) {
+  if (!log_on()) return;
+  char buf[640];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[bnlat] %s\n", buf);
+}
+
+long fault_alloc_index() {
+  const char* e = std::getenv("BNLAT_FAULT");
+  if (!e || std::strncmp(e, "alloc:", 6) != 0) return 0;
+  return std::strtol(e + 6, nullptr, 10);
+}
+
 bn_status fail(bn_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -29,6 +57,7 @@ bn_status fail(bn_status s, const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_last_error = buf;
+  log_msg("error %d: %s", (int)s, buf);
   return s;
 }
 
@@ -219,6 +248,9 @@ struct bn_problem_s {
   template <class T>
   bn_status alloc(T** ptr, size_t count) {
     void* p = nullptr;
+    const long k = fault_alloc_index();
+    if (k > 0 && (long)allocs.size() + 1 == k)
+      return fail(BN_ENOMEM, "hipMalloc of %zu bytes failed: injected by BNLAT_FAULT", count * sizeof(T));
     hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -307,8 +339,8 @@ bn_status supported(const bn_config* c) {
   if (c->radius > 6) return fail(BN_EUNSUPPORTED, "radius > 6 is not supported by this build");
   if (c->t_heaviside == 0) return fail(BN_EUNSUPPORTED, "at least one Heaviside integrand is required");
   if (c->t_gauss > (1u << 16)) return fail(BN_EINVAL, "more than 65536 Gaussian integrands");
-  if (c->precision == BN_BF16 && c->colour_k != 2)
-    return fail(BN_EUNSUPPORTED, "the BF16 matrix-core form needs colour_k = 2");
+  if (c->precision == BN_BF16 && !bf16_supported_k(c->colour_k))
+    return fail(BN_EUNSUPPORTED, "the BF16 matrix-core form needs colour_k in {1, 2, 4}");
   if (c->move == BN_SWAP) {
     const uint64_t P = (uint64_t)c->width * c->height;
     if (!is_pow2((uint32_t)P) || P < 2ull * c->colour_k * c->colour_k)
@@ -1062,6 +1094,13 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   }
   v.tg = cfg->t_gauss;
   v.tgp = round_up(v.tg, 64);
+  v.tb = v.tp + v.tgp;
+  // BF16 form: exact counts on the matrix cores where they are exact in BF16
+  // (N <= 256, Heaviside rows only), else rounded error vectors
+  v.mfma = cfg->precision != BN_BF16 ? 0u : (v.n <= 256 && v.tg == 0 ? 1u : 2u);
+  v.xscale = v.mfma == 2 ? 0x1p-39 : 2.0 / ((double)v.n * (double)v.n);
+  v.bf = nullptr;
+  v.delta_bf = nullptr;
   const size_t P = (size_t)v.w * v.h;
 
   std::vector<uint32_t> lat(v.n);
@@ -1131,7 +1170,10 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   }
   v.pix_list = nullptr;
   const unsigned long long zero[4] = {0ull, 0ull, 0ull, 0ull};
-  v.mfma = cfg->precision == BN_BF16 ? 1u : 0u;
+  if (v.mfma && ((s = p->alloc(&v.bf, P * v.tb)) != BN_OK || (s = p->alloc(&v.delta_bf, v.pc)) != BN_OK)) {
+    delete p;
+    return s;
+  }
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMemcpyAsync(lat_d, lat.data(), v.n * 4, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(ihp_d, ihp.data(), v.tp * 8, hipMemcpyHostToDevice, p->stream);
@@ -1149,12 +1191,17 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
     delete p;
     return s;
   }
+  log_msg("created problem %p: %ux%u, N=%u, T=%u+%u, r=%u, K=%u, %s, %s, %zu device buffers", (void*)p,
+          cfg->width, cfg->height, cfg->n, cfg->t_heaviside, cfg->t_gauss, cfg->radius, cfg->colour_k,
+          cfg->precision == BN_BF16 ? (v.mfma == 1 ? "BF16 (exact counts)" : "BF16 (rounded errors)") : "FP32",
+          cfg->move == BN_SWAP ? "swap" : "redraw", p->allocs.size());
   *out = p;
   return BN_OK;
 }
 
 bn_status bn_destroy_problem(bn_problem p) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
+  log_msg("destroyed problem %p", (void*)p);
   delete p;
   return BN_OK;
 }
@@ -1180,6 +1227,7 @@ bn_status bn_compute_errors(bn_problem p) {
   HIPCHK(launch_count(p->v, MODE_ALL, 0, p->v.w * p->v.h, p->stream));
   HIPCHK(launch_gauss_est(p->v, MODE_ALL, p->v.w * p->v.h, p->stream));
   HIPCHK(launch_gauss_errors(p->v, p->stream));
+  HIPCHK(launch_bf_field(p->v, p->stream));
   p->have_counts = true;
   p->errors_valid = true;
   return BN_OK;
@@ -1235,6 +1283,34 @@ bn_status bn_energy(bn_problem p, double* out) {
   }
   if (!std::isfinite(*out)) return fail(BN_ENUMERIC, "energy is not finite");
   return BN_OK;
+}
+
+bn_status bn_energy_bf16(bn_problem p, double* out) {
+  if (!p || !out) return fail(BN_EINVAL, "NULL argument");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  if (!p->v.mfma) return fail(BN_ESTATE, "the problem is not in the BF16 form");
+  double* acc = (double*)p->ysum;   // the energy's class-sum buffer, 8 bytes per class
+  HIPCHK(hipMemsetAsync(acc, 0, p->v.ncls * sizeof(double), p->stream));
+  HIPCHK(launch_energy_bf16(p->v, acc, p->stream));
+  std::vector<double> y(p->v.ncls);
+  HIPCHK(hipMemcpyAsync(y.data(), acc, y.size() * 8, hipMemcpyDeviceToHost, p->stream));
+  bn_status s = sync(p);
+  if (s != BN_OK) return s;
+  // half window summed on the device; the mirrored half has the same total
+  double e = 0.0;
+  for (uint32_t c = 0; c < p->v.ncls; ++c) e = e + p->cls_w[c] * (2.0 * y[c]);
+  if (p->v.mfma == 1) e = e / ((double)p->v.n * (double)p->v.n);
+  *out = e;
+  if (!std::isfinite(*out)) return fail(BN_ENUMERIC, "energy is not finite");
+  return BN_OK;
+}
+
+bn_status bn_get_phase_bf16(bn_problem p, double* delta_bf16) {
+  if (!p || !delta_bf16) return fail(BN_EINVAL, "NULL argument");
+  if (!p->v.mfma) return fail(BN_ESTATE, "the problem is not in the BF16 form");
+  if (p->cfg.move == BN_SWAP) return fail(BN_ESTATE, "swap passes have no BF16 form");
+  HIPCHK(hipMemcpyAsync(delta_bf16, p->v.delta_bf, (size_t)p->v.pc * 8, hipMemcpyDeviceToHost, p->stream));
+  return sync(p);
 }
 
 bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, double* out) {

@@ -45,7 +45,13 @@ struct DevView {
   unsigned long long* ctr;   // [0] sweep index, [1] accepted total, [2] BF16 vetoes
   long long* xpart;          // [ncls][pc] integer class sums of the staged evaluation (kept zero between phases)
   uint32_t* unsure;          // [pc] matrix-core results not certified exact (kept zero between phases)
-  uint32_t mfma;             // 1: BF16 matrix-core evaluation of the colour phases
+  uint32_t mfma;             // colour phases' evaluation: 0 FP32 form (exact integer stencil), 1 BF16 matrix
+                             // cores on exact counts (N <= 256, Heaviside rows only), 2 BF16 matrix cores on
+                             // rounded error vectors with exact re-evaluation of accepted moves
+  uint32_t tb;               // rows of the BF16 field: tp + tgp
+  uint16_t* bf;              // [tb/8][P][8] BF16 field (mode 1: counts; mode 2: errors), else null
+  double* delta_bf;          // [M] energy change the BF16 pass computed (before re-evaluation), else null
+  double xscale;             // energy change = xscale * sum_d w_d X_d of the class sums X_d
   uint32_t tch;              // integrands per wave in the counting kernels (launch shape)
   uint32_t slice_target;     // workgroups the staged energy-change launch aims for
   uint32_t count_cap;        // workgroup cap of the sweep-wide recount launch (0: none)
@@ -94,6 +100,16 @@ hipError_t launch_finish_batch(const DevView* views, const uint32_t* pre, uint32
 hipError_t launch_commit_batch(const DevView* views, const uint32_t* pre, uint32_t nmem, uint32_t blocks,
                                uint32_t kappa, hipStream_t s);
 hipError_t launch_advance_batch(const DevView* views, uint32_t nmem, hipStream_t s);
+
+// BF16 precision form (mfma.hip): the field from counts / estimates, the
+// colour phase's evaluation (Gram pass + decision + exact re-evaluation), the
+// field's energy
+bool bf16_supported_k(uint32_t k);
+hipError_t launch_bf_field(const DevView& v, hipStream_t s);
+hipError_t launch_delta_bf16(const DevView& v, uint32_t kappa, hipStream_t s);
+hipError_t launch_energy_bf16(const DevView& v, double* ysum, hipStream_t s);
+// decision from the summed class sums of a colour phase (clears them)
+hipError_t launch_finish(const DevView& v, hipStream_t s);
 
 // device peak loops: kind 0 copy (buf -> buf2, size bytes), 1 dot2 chains,
 // 2 BF16 MFMA accumulations (iters iterations each); blocks workgroups of 256

@@ -85,6 +85,37 @@ __device__ inline uint32_t proposal(const DevView& v, uint32_t p, uint32_t sweep
   return q16_pair(philox_w01(p, sweep, v.problem, S_PROP, v.seed_lo, v.seed_hi));
 }
 
+// ------------------------------------------------- BF16 error field values
+
+// Round to the nearest BF16 (ties to even); bits of two values packed.
+__device__ inline uint32_t bf16x2_bits(float lo, float hi) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)lo) | ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)hi) << 16);
+}
+
+// Field value of 8 Heaviside counts (one 16-byte count tile) in either mode.
+__device__ inline uint4 heaviside_field_tile(const DevView& v, const uint4 c8, uint32_t t) {
+  const uint32_t w[4] = {c8.x, c8.y, c8.z, c8.w};
+  uint32_t o[4];
+  const float inv_n = 1.0f / (float)v.n;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float c0 = (float)(w[k] & 0xFFFFu), c1 = (float)(w[k] >> 16);
+    if (v.mfma == 1) {
+      o[k] = bf16x2_bits(c0, c1);
+    } else {
+      o[k] = bf16x2_bits(__fsub_rn(__fmul_rn(c0, inv_n), v.area[t + 2 * k]),
+                         __fsub_rn(__fmul_rn(c1, inv_n), v.area[t + 2 * k + 1]));
+    }
+  }
+  return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+// Field value of Gaussian row t (FP32 estimate g): g - I rounded to FP32,
+// then to BF16 by the caller; padded rows are 0.
+__device__ inline float gaussian_error(const DevView& v, float g, uint32_t t) {
+  return t < v.tg ? (float)((double)g - v.gint[t]) : 0.0f;
+}
+
 // --------------------------------------------------------- window tables
 
 // Offsets of the (2R+1)^2 - 1 window grouped by squared distance d in

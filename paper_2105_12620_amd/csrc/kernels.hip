@@ -283,8 +283,8 @@ template <int R, int K, int BY, int V>
 __global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kappa, uint32_t trlen,
                                                          long long* __restrict__ xpart) {
   // the colour phases' waves issue ahead of the sweep-wide recount running
-  // beside them (k_delta_finish, k_commit and the BF16 form's k_delta_mfma
-  // and k_delta_recheck likewise), which fills the remaining issue slots
+  // beside them (k_delta_finish, k_commit and the BF16 form's k_delta_bf
+  // and k_delta_refine likewise), which fills the remaining issue slots
   __builtin_amdgcn_s_setprio(2);
   delta_stage_body<R, K, BY, V>(v, kappa, trlen, xpart, blockIdx.x, blockIdx.y, blockIdx.z);
 }
@@ -314,9 +314,11 @@ __device__ __forceinline__ void delta_finish_body(const DevView& v, long long* _
     xsum[(size_t)c * v.pc + j] = 0;
     acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)x));
   }
-  double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
-  if (v.tgp) total = __dadd_rn(total, v.gdelta[j]);
+  double total = __dmul_rn(acc, v.xscale);
+  // the approximate BF16 form's class sums already hold the Gaussian rows
+  if (v.tgp && v.mfma != 2) total = __dadd_rn(total, v.gdelta[j]);
   v.delta[j] = total;
+  if (v.delta_bf) v.delta_bf[j] = total;
   v.accept[j] = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
 }
 
@@ -333,305 +335,7 @@ __global__ __launch_bounds__(256) void k_delta_finish_batch(const DevView* __res
   delta_finish_body(v, v.xpart, blockIdx.x - pre[i]);
 }
 
-// ---------------------------------------------- energy change on matrix cores
-//
-// BF16 form of the neighbourhood Gram products (K = 2 colour classes per
-// axis).  A block holds BYC class rows x 16 class pixels; wave w owns class row
-// w, i.e. the 16 rows of an MFMA tile.  For every 16-integrand slice the
-// counts of the block's window region are staged in LDS as BF16 (integer
-// counts up to 256 are exact in BF16), together with the moved pixels'
-// count changes dc = c' - c.  v_mfma_f32_16x16x16_bf16 then forms, for each
-// of the 2r+1 neighbour rows and 3 column tiles, the products
-//   G[b][col] = sum_t dc[b][t] * c[row][col][t]
-// with FP32 accumulation; the window entries (col - 2b - r in [-r, r]) are the
-// Gram terms the energy change needs.  A slice's partial sums are exact
-// integers when every partial sum stays below 2^24, which holds if
-// N <= 256 and N * sum_t |dc_t| < 2^24 over the slice; slices that cannot
-// certify this mark the pixel, and accepted marked moves are re-checked with
-// the exact integer kernel (k_delta_recheck).
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-template <int R, int BYC_>
-struct MfmaGeom {
-  static constexpr int BYC = BYC_;                    // class rows (waves) per block
-  static constexpr int BXC = 16;                      // class pixels per row (MFMA rows)
-  static constexpr int RROWS = 2 * (BYC - 1) + 1 + 2 * R;
-  static constexpr int RUSED = 2 * (BXC - 1) + 1 + 2 * R;   // region columns read
-  static constexpr int RCOLS = 48;                    // three 16-column tiles
-  static constexpr int NB = BYC * BXC;
-  // LDS in 8-byte units (4 BF16 = 4 integrands of one pixel):
-  //   region [4 quarter-slices][RROWS][RCOLS], dc [4][NB]
-  static constexpr int REG8 = 4 * RROWS * RCOLS;
-  static constexpr int DC8 = 4 * NB;
-  static constexpr int LDS_BYTES = 8 * (REG8 + DC8);
-  static_assert(RUSED <= RCOLS, "window too wide for three column tiles");
-};
-
-__device__ inline uint2 to_bf16x4(uint32_t c01, uint32_t c23) {
-  // four non-negative integer counts -> BF16 (round to nearest even)
-  const __bf16 a = (__bf16)(float)(c01 & 0xFFFFu), b = (__bf16)(float)(c01 >> 16);
-  const __bf16 c = (__bf16)(float)(c23 & 0xFFFFu), d = (__bf16)(float)(c23 >> 16);
-  return make_uint2((uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16),
-                    (uint32_t)__builtin_bit_cast(uint16_t, c) | ((uint32_t)__builtin_bit_cast(uint16_t, d) << 16));
-}
-
-__device__ inline uint32_t bf16_pair(int x, int y) {
-  const __bf16 a = (__bf16)(float)x, b = (__bf16)(float)y;
-  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
-}
-
-template <int R, int BYC>
-__global__ __launch_bounds__(64 * BYC) void k_delta_mfma(DevView v, uint32_t kappa, uint32_t trlen,
-                                                    long long* __restrict__ xsum,
-                                                    uint32_t* __restrict__ unsure) {
-  // raised issue priority beside the sweep-wide recount, as in k_delta_stage
-  __builtin_amdgcn_s_setprio(2);
-  using G = MfmaGeom<R, BYC>;
-  constexpr Window<R> W = WinConst<R>::w;
-  constexpr int NCLS = WinConst<R>::NCLS;
-  extern __shared__ uint2 lds8[];
-  uint2* reg = lds8;                 // [4][RROWS][RCOLS]
-  uint2* dcs = lds8 + G::REG8;       // [4][NB]
-  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t a0 = blockIdx.y * G::BYC, b0 = blockIdx.x * G::BXC;
-  const uint32_t ky = kappa >> 1, kx = kappa & 1;
-  const uint32_t ys = (ky + 2 * a0 + v.h * (R / v.h + 1) - R) % v.h;
-  const uint32_t xs = (kx + 2 * b0 + v.w * (R / v.w + 1) - R) % v.w;
-  const uint32_t P = v.w * v.h;
-
-  // columns past the used ones are never read back; keep them finite
-  for (uint32_t i = threadIdx.x; i < (uint32_t)(4 * G::RROWS * (G::RCOLS - G::RUSED)); i += blockDim.x) {
-    const uint32_t q = i / (G::RCOLS - G::RUSED), c = G::RUSED + i % (G::RCOLS - G::RUSED);
-    reg[q * G::RCOLS + c] = make_uint2(0, 0);
-  }
-
-  // staging roles: thread i < 2*NB owns (class pixel i >> 1, half of the slice)
-  const uint32_t own_cp = threadIdx.x >> 1, own_half = threadIdx.x & 1;
-  const uint32_t own_a = a0 + own_cp / G::BXC, own_b = b0 + own_cp % G::BXC;
-  const bool own_ok = threadIdx.x < 2u * G::NB && own_a < v.ch && own_b < v.cw;
-  const uint32_t own_p = own_ok ? (ky + 2 * own_a) * v.w + (kx + 2 * own_b) : 0;
-  long long z0 = 0;          // sum_t dc (c' + c) over this thread's integrands
-  uint32_t absdc = 0;        // sum_t |dc| over this thread's integrands
-
-  f32x4 acc[2 * R + 1][3];
-#pragma unroll
-  for (int oy = 0; oy < 2 * R + 1; ++oy)
-#pragma unroll
-    for (int ct = 0; ct < 3; ++ct) acc[oy][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  // Staging plan, fixed for the whole integrand range: thread i stages region
-  // items i, i + 512, ... (an item = 8 counts of one region pixel, half 0 or 1
-  // of the 16-integrand slice); the global pixel of each item is computed once.
-  constexpr int NT = 64 * G::BYC;
-  constexpr int NITEM = 2 * G::RROWS * G::RUSED;
-  constexpr int ITER = (NITEM + NT - 1) / NT;
-  uint32_t item_pix[ITER], item_lds[ITER];
-#pragma unroll
-  for (int it = 0; it < ITER; ++it) {
-    const uint32_t i = threadIdx.x + it * NT;
-    item_pix[it] = 0xFFFFFFFFu;
-    item_lds[it] = 0;
-    if (i < (uint32_t)NITEM) {
-      const uint32_t half = i / (G::RROWS * G::RUSED), pix = i - half * (G::RROWS * G::RUSED);
-      const uint32_t rr = pix / G::RUSED, cc = pix - rr * G::RUSED;
-      uint32_t gy = ys + rr, gx = xs + cc;
-      while (gy >= v.h) gy -= v.h;
-      while (gx >= v.w) gx -= v.w;
-      item_pix[it] = (gy * v.w + gx) | (half << 31);
-      item_lds[it] = ((2 * half) * G::RROWS + rr) * G::RCOLS + cc;
-    }
-  }
-  const uint32_t own_j = own_ok ? own_a * v.cw + own_b : 0;
-
-  // Software pipeline: the loads of slice t0 + 16 are in flight while the
-  // matrix cores work on slice t0.
-  uint4 q[ITER], cn = make_uint4(0, 0, 0, 0), co = make_uint4(0, 0, 0, 0);
-  const uint32_t t_begin = blockIdx.z * trlen, t_end = min(t_begin + trlen, v.tp);
-  auto load_slice = [&](uint32_t t0) {
-#pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      if (item_pix[it] != 0xFFFFFFFFu) {
-        const uint32_t half = item_pix[it] >> 31, pix = item_pix[it] & 0x7FFFFFFFu;
-        q[it] = *(const uint4*)(v.cnt + tix(pix, t0 + 8 * half, P));
-      }
-    }
-    if (own_ok) {
-      cn = *(const uint4*)(v.c_new + tix(own_j, t0 + 8 * own_half, v.pc));
-      co = *(const uint4*)(v.cnt + tix(own_p, t0 + 8 * own_half, P));
-    }
-  };
-  if (t_begin < t_end) load_slice(t_begin);
-  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 16) {
-    // region counts for integrands t0..t0+15 (two 8-integrand tiles) as BF16
-#pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      if (item_pix[it] != 0xFFFFFFFFu) {
-        reg[item_lds[it]] = to_bf16x4(q[it].x, q[it].y);
-        reg[item_lds[it] + G::RROWS * G::RCOLS] = to_bf16x4(q[it].z, q[it].w);
-      }
-    }
-    // count changes of the moved pixels
-    if (threadIdx.x < 2u * G::NB) {
-      uint2 lo = make_uint2(0, 0), hi = make_uint2(0, 0);
-      if (own_ok) {
-        const uint32_t nw[4] = {cn.x, cn.y, cn.z, cn.w}, ow[4] = {co.x, co.y, co.z, co.w};
-        int d[8];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int n0 = (int)(nw[k] & 0xFFFFu), n1 = (int)(nw[k] >> 16);
-          const int o0 = (int)(ow[k] & 0xFFFFu), o1 = (int)(ow[k] >> 16);
-          d[2 * k] = n0 - o0;
-          d[2 * k + 1] = n1 - o1;
-          z0 += (long long)(d[2 * k] * (n0 + o0) + d[2 * k + 1] * (n1 + o1));
-          absdc += (uint32_t)(abs(d[2 * k]) + abs(d[2 * k + 1]));
-        }
-        lo = make_uint2(bf16_pair(d[0], d[1]), bf16_pair(d[2], d[3]));
-        hi = make_uint2(bf16_pair(d[4], d[5]), bf16_pair(d[6], d[7]));
-      }
-      dcs[(2 * own_half) * G::NB + own_cp] = lo;
-      dcs[(2 * own_half + 1) * G::NB + own_cp] = hi;
-    }
-    __syncthreads();
-    if (t0 + 16 < t_end) load_slice(t0 + 16);
-    // lane l: MFMA row (pixel) l % 16, integrands 4 (l / 16) .. +3 of the slice
-    const uint32_t quarter = lane >> 4, m = lane & 15;
-    const uint2 a2 = dcs[quarter * G::NB + w * G::BXC + m];
-    const bf16x4 af = __builtin_bit_cast(bf16x4, a2);
-#pragma unroll
-    for (int oy = 0; oy < 2 * R + 1; ++oy) {
-      const uint32_t rr = 2 * w + oy;
-#pragma unroll
-      for (int ct = 0; ct < 3; ++ct) {
-        const uint2 b2 = reg[(quarter * G::RROWS + rr) * G::RCOLS + ct * 16 + m];
-        acc[oy][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, __builtin_bit_cast(bf16x4, b2),
-                                                                acc[oy][ct], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-
-  // certificate and z0 of each pixel: combine the two halves through LDS
-  long long* zsh = (long long*)lds8;                     // [NB]
-  uint32_t* ash = (uint32_t*)(zsh + G::NB);              // [NB]
-  if (threadIdx.x < 2u * G::NB && own_half == 0) {
-    zsh[own_cp] = z0;
-    ash[own_cp] = absdc;
-  }
-  __syncthreads();
-  if (threadIdx.x < 2u * G::NB && own_half == 1) {
-    zsh[own_cp] += z0;
-    ash[own_cp] += absdc;
-  }
-  __syncthreads();
-
-  // Gram extraction: per neighbour row, the wave's three tiles go through
-  // LDS and lanes 0..15 (one per class pixel) collect the window entries.
-  float* gsh = (float*)(ash + G::NB) + w * (16 * G::RCOLS);   // [16][48] per wave
-  const uint32_t b = lane;                                    // class pixel of lanes 0..15
-  long long zd[NCLS];
-#pragma unroll
-  for (int c = 0; c < NCLS; ++c) zd[c] = 0;
-#pragma unroll
-  for (int oy = 0; oy < 2 * R + 1; ++oy) {
-#pragma unroll
-    for (int ct = 0; ct < 3; ++ct)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) gsh[(4 * (lane >> 4) + i) * G::RCOLS + ct * 16 + (lane & 15)] = acc[oy][ct][i];
-    // Only this wave touches its gsh: the lanes' LDS stores are ordered
-    // before the cross-lane reads below by a wavefront-scope release/acquire
-    // pair around a wave barrier (no workgroup barrier is needed).
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < 16) {
-#pragma unroll
-      for (int ox = -R; ox <= R; ++ox) {
-        if (ox == 0 && oy == R) continue;
-        const int d2 = ox * ox + (oy - R) * (oy - R);
-        int cidx = 0;
-#pragma unroll
-        for (int c = 0; c < NCLS; ++c)
-          if (W.d[c] == d2) cidx = c;
-        zd[cidx] += (long long)gsh[b * G::RCOLS + 2 * b + R + ox];
-      }
-    }
-    // the reads are done before the next row's stores overwrite gsh
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  const uint32_t a = a0 + w, bb = b0 + b;
-  if (lane < 16 && a < v.ch && bb < v.cw) {
-    const uint32_t cp = w * G::BXC + b;
-    const uint32_t j = a * v.cw + bb;
-    const long long zz = zsh[cp];
-    if (v.n > 256 || (unsigned long long)ash[cp] * v.n >= (1ull << 24)) atomicOr(&unsure[j], 1u);
-#pragma unroll
-    for (int c = 0; c < NCLS; ++c)
-      atomicAdd((unsigned long long*)&xsum[(size_t)c * v.pc + j],
-                (unsigned long long)((long long)W.csize[c] * zz - 2 * zd[c]));
-  }
-}
-
-// Exact re-check of accepted moves the matrix-core pass could not certify:
-// the integer energy change decides, a reversed decision is a veto.
-template <int R>
-__global__ __launch_bounds__(256) void k_delta_recheck(DevView v, uint32_t kappa,
-                                                       uint32_t* __restrict__ unsure) {
-  __builtin_amdgcn_s_setprio(2);
-  constexpr Window<R> W = WinConst<R>::w;
-  constexpr int NCLS = WinConst<R>::NCLS;
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t j = wave_id();
-  if (j >= v.pc) return;
-  const uint32_t flagged = unsure[j];
-  if (!flagged) return;
-  if (!v.accept[j]) {
-    if (lane == 0) unsure[j] = 0;
-    return;
-  }
-  const uint32_t p = class_pixel(v, kappa, j);
-  const uint32_t y = p / v.w, x = p - y * v.w, P = v.w * v.h;
-  long long z0 = 0, zd[NCLS];
-#pragma unroll
-  for (int c = 0; c < NCLS; ++c) zd[c] = 0;
-  for (uint32_t base = 0; base < v.tp; base += 128) {
-    const uint32_t t = base + 2 * lane;
-    const uint32_t cn = *(const uint32_t*)(v.c_new + tix(j, t, v.pc));
-    const uint32_t co = *(const uint32_t*)(v.cnt + tix(p, t, P));
-    const int n0 = (int)(cn & 0xFFFFu), n1 = (int)(cn >> 16);
-    const int o0 = (int)(co & 0xFFFFu), o1 = (int)(co >> 16);
-    const int dc0 = n0 - o0, dc1 = n1 - o1;
-    const uint32_t dcp = ((uint32_t)dc0 & 0xFFFFu) | ((uint32_t)dc1 << 16);
-    z0 += (long long)(dc0 * (n0 + o0) + dc1 * (n1 + o1));
-#pragma unroll
-    for (int mm = 0; mm < W.M; ++mm) {
-      const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
-      zd[W.cls[mm]] += dot2(dcp, *(const uint32_t*)(v.cnt + tix(q, t, P)), 0);
-    }
-  }
-  double acc = 0.0;
-#pragma unroll
-  for (int c = 0; c < NCLS; ++c) {
-    long long xv = (long long)W.csize[c] * z0 - 2 * zd[c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
-    acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)xv));
-  }
-  if (lane == 0) {
-    double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
-    if (v.tgp) total = __dadd_rn(total, v.gdelta[j]);
-    const bool ok = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
-    v.delta[j] = total;
-    if (!ok) {
-      v.accept[j] = 0;
-      atomicAdd(&v.ctr[2], 1ull);
-    }
-    unsure[j] = 0;
-  }
-}
 
 // ------------------------------------------------------------------ commit
 // Accepted moves of the phase become the state (Sec. 3.4): offset and hit
@@ -654,8 +358,11 @@ __device__ __forceinline__ void commit_body(const DevView& v, uint32_t kappa, ui
   if (g == 0) v.U[p] = v.u_new[j];
   const uint32_t t0 = g * CT, t1 = min(t0 + CT, v.tp >> 3);
   const size_t P = (size_t)v.w * v.h;
-  for (uint32_t tt = t0; tt < t1; ++tt)
-    *(uint4*)(v.cnt + (tt * P + p) * 8) = *(const uint4*)(v.c_new + ((size_t)tt * v.pc + j) * 8);
+  for (uint32_t tt = t0; tt < t1; ++tt) {
+    const uint4 c8 = *(const uint4*)(v.c_new + ((size_t)tt * v.pc + j) * 8);
+    *(uint4*)(v.cnt + (tt * P + p) * 8) = c8;
+    if (v.bf) *(uint4*)(v.bf + (tt * P + p) * 8) = heaviside_field_tile(v, c8, tt * 8);
+  }
 }
 
 // FP32 error vectors e = c/N - A_t of every pixel from the exact counts
@@ -1088,7 +795,13 @@ __global__ __launch_bounds__(256) void k_commit_gauss(DevView v, uint32_t kappa)
   const uint32_t j = wave_id();
   if (j >= v.pc || !v.accept[j]) return;
   const uint32_t p = class_pixel(v, kappa, j);
-  for (uint32_t t = lane; t < v.tgp; t += 64) v.gest[(size_t)p * v.tgp + t] = v.g_new[(size_t)j * v.tgp + t];
+  const uint32_t P = v.w * v.h;
+  for (uint32_t t = lane; t < v.tgp; t += 64) {
+    const float g = v.g_new[(size_t)j * v.tgp + t];
+    v.gest[(size_t)p * v.tgp + t] = g;
+    if (v.bf)
+      v.bf[tix(p, v.tp + t, P)] = __builtin_bit_cast(uint16_t, (__bf16)gaussian_error(v, g, t));
+  }
 }
 
 // Gaussian error rows g - I (refreshed on demand).
@@ -1150,8 +863,7 @@ hipError_t stage_launch(const DevView& v, uint32_t kappa, long long* xpart, hipS
                      trlen, xpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_delta_finish, dim3((v.pc + 255) / 256), dim3(256), 0, s, v, xpart);
-  return hipGetLastError();
+  return launch_finish(v, s);
 }
 
 template <int R>
@@ -1173,41 +885,9 @@ hipError_t launch_init_offsets(const DevView& v, hipStream_t s) {
 }
 
 
-template <int R>
-hipError_t mfma_launch(const DevView& v, uint32_t kappa, hipStream_t s) {
-  // four class rows (one wave per SIMD) per block: a block then fits beside
-  // the waves of a concurrently running counting launch
-  using G = MfmaGeom<R, 4>;
-  const uint32_t bx = (v.cw + G::BXC - 1) / G::BXC, by = (v.ch + G::BYC - 1) / G::BYC;
-  uint32_t trlen = 0;
-  const uint32_t ns = stage_slices(v, bx * by, &trlen, 16);
-  const size_t lds = (size_t)G::LDS_BYTES;
-  hipLaunchKernelGGL((k_delta_mfma<R, G::BYC>), dim3(bx, by, ns), dim3(64 * G::BYC), lds, s, v, kappa, trlen,
-                     v.xpart, v.unsure);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_delta_finish, dim3((v.pc + 255) / 256), dim3(256), 0, s, v, v.xpart);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_delta_recheck<R>), dim3((v.pc + 3) / 4), dim3(256), 0, s, v, kappa, v.unsure);
-  return hipGetLastError();
-}
-
 hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
-  // The matrix-core form only certifies exactness for N <= 256 (counts exact
-  // in BF16); above that every accepted move would be re-checked, so the
-  // exact integer stencil runs directly (same decisions, less work).
-  if (mode == MODE_CLASS && v.mfma && v.n <= 256) {
-    switch (v.radius) {
-      case 1: return mfma_launch<1>(v, kappa, s);
-      case 2: return mfma_launch<2>(v, kappa, s);
-      case 3: return mfma_launch<3>(v, kappa, s);
-      case 4: return mfma_launch<4>(v, kappa, s);
-      case 5: return mfma_launch<5>(v, kappa, s);
-      case 6: return mfma_launch<6>(v, kappa, s);
-      default: return hipErrorInvalidValue;
-    }
-  }
+  // BF16 precision form: matrix-core Gram pass, decision, exact re-evaluation
+  if (mode == MODE_CLASS && v.mfma) return launch_delta_bf16(v, kappa, s);
   if (mode == MODE_CLASS && v.xpart) {
     switch (v.radius) {
       case 1: return stage_by_k<1>(v, kappa, v.xpart, s);
@@ -1224,6 +904,11 @@ hipError_t launch_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
 }
 
 uint32_t xpart_words(const DevView& v) { return v.ncls * v.pc; }
+
+hipError_t launch_finish(const DevView& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_delta_finish, dim3((v.pc + 255) / 256), dim3(256), 0, s, v, v.xpart);
+  return hipGetLastError();
+}
 
 uint32_t commit_blocks(const DevView& v) {
   return (uint32_t)(((uint64_t)v.pc * (((v.tp >> 3) + CT - 1) / CT) + 255) / 256);
@@ -1333,6 +1018,9 @@ hipError_t gauss_stage_by_k(const DevView& v, uint32_t kappa, hipStream_t s) {
 
 hipError_t launch_gauss_delta(const DevView& v, int mode, uint32_t kappa, uint32_t m, hipStream_t s) {
   if (!v.tgp || m == 0) return hipSuccess;
+  // the approximate BF16 form evaluates the Gaussian rows in its Gram pass
+  // and re-evaluates accepted moves exactly
+  if (mode == MODE_CLASS && v.mfma == 2) return hipSuccess;
   if (mode == MODE_CLASS) {
     switch (v.radius) {
       case 1: return gauss_stage_by_k<1>(v, kappa, s);

@@ -1,12 +1,13 @@
-"""BF16 matrix-core form of the energy change (precision = BF16).
+"""BF16 matrix-core form of the energy change (precision = BF16), exact mode.
 
-Where the exactness certificate holds (N <= 256 and N * sum|dc| < 2^24 per
-integrand slice) the FP32-accumulated MFMA Gram products are exact integers,
-so decisions, energy changes and trajectories equal the oracle's bit for bit.
-Slices that cannot certify (large count changes) flag their pixels and
-accepted flagged moves are re-checked with the exact integer form (vetoes
-counted).  For N > 256 the counts are not exact in BF16 and the library runs
-the exact integer stencil instead."""
+With N <= 256 and Heaviside rows only, counts and count changes are exact in
+BF16 and, where the exactness certificate holds (N * sum|dc| < 2^24 per
+integrand slice), the FP32-accumulated MFMA Gram products are exact
+integers, so decisions, energy changes and trajectories equal the oracle's
+bit for bit.  Slices that cannot certify flag their pixels and accepted
+flagged moves are re-checked with the exact integer form (vetoes counted).
+The approximate mode (N > 256 or Gaussian rows) is tested in
+test_gpu_bf16_approx.py."""
 import numpy as np
 import pytest
 
@@ -28,16 +29,17 @@ def bf16(w):
 
 
 @pytest.mark.parametrize("name", ["tile32_n16_t64", "n256_r4", "rect_ascend", "wide64", "r6",
-                                  "tile4_alias"])
+                                  "tile4_alias", "k1", "k4_conflict_free", "k4_r6"])
 def test_bf16_phases_match_oracle_exactly(name):
     w = bf16(EDGE.get(name) or workload(name))
     say("case", name)
     inp = synthgen.problem_inputs(w)
     ref = oracle_problem(w, inp)
     st = osw.initial_state(ref, inp["offsets"])
+    K2 = w["colour_k"] ** 2
     with gpu_problem(w, inp) as p:
         for s in range(2):
-            for kappa in range(4):
+            for kappa in range(K2):
                 p.phase_propose(kappa)
                 p.phase_evaluate(kappa)
                 got = p.get_phase()
@@ -63,36 +65,6 @@ def test_bf16_trajectory_matches_oracle(name, k):
         assert stats["bf16_vetoes"] == 0
         np.testing.assert_array_equal(p.get_offsets(), st.u)
         assert p.energy() == pytest.approx(osw.energy_of(ref, st), rel=1e-12)
-
-
-def test_bf16_above_256_uses_the_exact_stencil():
-    """N = 1024: counts are not exact in BF16, so the certificate could never
-    hold and the library runs the exact integer stencil for the BF16 form:
-    phase results and the trajectory equal the oracle's bit for bit and no
-    move is vetoed."""
-    name = "n1024_r5"
-    w = bf16(EDGE[name])
-    inp = synthgen.problem_inputs(w)
-    ref = oracle_problem(w, inp)
-    st = osw.initial_state(ref, inp["offsets"])
-    ph = osw.phase(ref, st, 0)
-    with gpu_problem(w, inp) as p:
-        p.phase_propose(0)
-        p.phase_evaluate(0)
-        got = p.get_phase()
-        np.testing.assert_array_equal(got["accept"], ph["accept"])
-        np.testing.assert_allclose(got["delta"], ph["delta"], rtol=1e-12)
-        p.phase_commit(0)
-        for kappa in (1, 2, 3):
-            p.phase_propose(kappa)
-            p.phase_evaluate(kappa)
-            p.phase_commit(kappa)
-        p.phase_advance()
-        stats = p.sweep(5, stats=True)
-        u = p.get_offsets()
-    st = osw.run(ref, osw.initial_state(ref, inp["offsets"]), 6)
-    np.testing.assert_array_equal(u, st.u)
-    assert stats["bf16_vetoes"] == 0
 
 
 def test_bf16_full_size_first_phase_sampled():
@@ -121,8 +93,23 @@ def test_bf16_full_size_first_phase_sampled():
         assert bool(ph["accept"][j]) == bool(d[0] < 0)
 
 
+def test_bf16_energy_of_counts_is_exact():
+    w = bf16(EDGE["n256_r4"])
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.run(ref, osw.initial_state(ref, inp["offsets"]), 2)
+    with gpu_problem(w, inp) as p:
+        p.sweep(2)
+        assert p.energy_bf16() == pytest.approx(osw.energy_of(ref, st), rel=1e-12)
+        assert p.energy() == pytest.approx(osw.energy_of(ref, st), rel=1e-12)
+
+
 def test_bf16_rejects_other_colourings():
-    w = bf16(EDGE["k4_conflict_free"])
+    w = bf16(workload(colour_k=3, width=12, height=12))
     with pytest.raises(bnlat.BnlatError) as e:
         bnlat.create_problem(w, None)
     assert e.value.status == bnlat.BN_EUNSUPPORTED
+    with bnlat.create_problem(dict(w, precision=0), None) as p:
+        with pytest.raises(bnlat.BnlatError) as e:
+            p.energy_bf16()
+        assert e.value.status == bnlat.BN_ESTATE
