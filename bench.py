@@ -198,8 +198,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="tile256_n256_t1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp32,bf16,swap,batched,large",
-                    help="comma list of forms to run: fp32 (headline), bf16, swap, batched, large")
+    ap.add_argument("--forms", default="fp32,bf16,swap,batched,large,precision_large",
+                    help="comma list of forms to run: fp32 (headline), bf16, swap, batched, large, "
+                         "precision_large")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--experiment", choices=["quality"], default=None,
@@ -368,6 +369,55 @@ def main() -> int:
 
     big = large() if "large" in forms else None
 
+    def precision_large() -> dict:
+        """One 512x512 problem of the largest configuration (N = 1024, 3072
+        Heavisides + 1024 Gaussians, 11x11 window) in the FP32 form and in the
+        BF16 form's approximate mode from the same start: colour-phase
+        evaluation time (event-timed, overlapped schedule), sweep time, the
+        BF16 form's vetoes, the energies after the same number of sweeps, and
+        the BF16 field's energy against the FP64 energy of the same state."""
+        base = dict(synthgen.WORKLOADS["tile512_n1024_t4096"])
+        mi = synthgen.problem_inputs(base)
+        res = {}
+        for name, prec in (("fp32", bnlat.BN_FP32), ("bf16", bnlat.BN_BF16)):
+            q = bnlat.create_problem(base, bnlat.heaviside_array(mi["heaviside"]), stream=stream.cuda_stream,
+                                     gaussians=bnlat.gaussian_array(mi["gauss"]), precision=prec)
+            q.init_offsets(mi["offsets"])
+            q.compute_errors()
+            e0 = q.energy()
+            q.set_profiling(True)
+            st = q.sweep(3, stats=True)
+            prof = q.get_profile()
+            q.set_profiling(False)
+            torch.cuda.synchronize()
+            e0v, e1v = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0v.record(stream)
+            q.sweep(2)
+            e1v.record(stream)
+            torch.cuda.synchronize()
+            res[name] = {"evaluate_ms_per_phase": prof["evaluate_ms"] / max(1, prof["phases"]),
+                         "ms_per_sweep": e0v.elapsed_time(e1v) / 2, "energy_start": e0,
+                         "energy_after_3_sweeps": None, "accepts_3_sweeps": st["accepts"],
+                         "bf16_vetoes_3_sweeps": st["bf16_vetoes"]}
+            res[name]["energy_after_5_sweeps"] = q.energy()
+            del res[name]["energy_after_3_sweeps"]
+            if prec == bnlat.BN_BF16:
+                ebf = q.energy_bf16()
+                res[name]["bf16_field_energy"] = ebf
+                res[name]["bf16_field_energy_rel_gap_vs_fp64"] = abs(ebf - res[name]["energy_after_5_sweeps"]) / \
+                    res[name]["energy_after_5_sweeps"]
+            res[name]["quality_sigma_1_4_16"] = q.quality_metric([1.0, 4.0, 16.0]).tolist()
+            q.close()
+        res["energy_rel_diff_bf16_vs_fp32"] = abs(res["bf16"]["energy_after_5_sweeps"] -
+                                                  res["fp32"]["energy_after_5_sweeps"]) / \
+            res["fp32"]["energy_after_5_sweeps"]
+        res["quality_rel_diff_bf16_vs_fp32"] = max(abs(a - b) / b for a, b in zip(res["bf16"]["quality_sigma_1_4_16"],
+                                                                                res["fp32"]["quality_sigma_1_4_16"]))
+        res["shape"] = "512^2, N=1024, 3072 Heavisides + 1024 Gaussians, 11x11"
+        return res
+
+    prec_large = precision_large() if "precision_large" in forms else None
+
     # Algorithmic work per launch of the counting kernel (one sweep-wide
     # recount): N*T predicates per proposal at two vector lane-operations each
     # (int16 dot product + sign test).  The kernel's own instruction count is
@@ -442,6 +492,7 @@ def main() -> int:
             "whole batched sweep (recounts of every member's proposals over the sweep time)",
             "sum over members of P N T x 2 lane-ops")),
         "batched_large": big,
+        "precision_large": prec_large,
         "window_offsets": win,
     }
     if cpu is not None:

@@ -22,7 +22,8 @@
  *     v / 65536); the modulo-one wrap is uint16 wrap-around.  N = 2^m must
  *     divide 65536.
  *   - Memory: the library allocates and owns every device buffer of a
- *     problem (created in bn_create_problem, freed in bn_destroy_problem).
+ *     problem (created in bn_create_problem, freed in bn_destroy_problem),
+ *     except those a caller hands to bn_create_problem_ext.
  *     Every pointer argument named host_* or out is caller-owned host
  *     memory of the size stated; the library never keeps it.
  *   - Streams: all device work of a problem is ordered on its HIP stream
@@ -149,6 +150,29 @@ typedef struct {
  * arithmetic); Heaviside rows stay exact.  *out receives the handle. */
 bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides,
                             const bn_gaussian* gaussians, void* stream, bn_problem* out);
+/* Device buffers the caller owns (for example PyTorch tensors), so that a
+ * problem's state lives in memory the caller allocates and can read in
+ * place.  Every pointer is nullable (the library then allocates that buffer
+ * itself).  Layouts, with P = W H and Tp = T rounded up to 128:
+ *   offsets  uint32 [P]           pixel p = y W + x, Q0.16 x | y << 16;
+ *   counts   uint16 [Tp/8][P][8]  hit counts in 16-byte tiles of 8 integrands
+ *                                 (integrand t of pixel p at ((t/8) P + p) 8 + t%8;
+ *                                 rows past T hold 0);
+ *   errors   float  [P][Tp]       error vectors c/N - A (brought up to date from
+ *                                 the counts by the calls that read them).
+ * Each must be device memory of at least that size, 256-byte aligned (else
+ * BN_EINVAL), alive and unmoved until bn_destroy_problem; the library never
+ * frees them and the caller must not write them while the problem's stream
+ * has work pending.  Otherwise identical to bn_create_problem (the
+ * ownership convention of the C ABI's boundary). */
+typedef struct {
+  void* offsets;
+  void* counts;
+  void* errors;
+} bn_device_buffers;
+bn_status bn_create_problem_ext(const bn_config* cfg, const bn_heaviside* heavisides,
+                                const bn_gaussian* gaussians, void* stream, const bn_device_buffers* bufs,
+                                bn_problem* out);
 bn_status bn_destroy_problem(bn_problem p);
 
 /* Set the offset tile U = {u_p} (Sec. 2).  host_u: uint16 [H][W][2] (x then y), or

@@ -56,6 +56,10 @@ HEAVISIDE_DTYPE = np.dtype([("nx", "<i2"), ("ny", "<i2"), ("cx", "<u2"), ("cy", 
 GAUSSIAN_DTYPE = np.dtype([("mx", "<f8"), ("my", "<f8"), ("s", "<f8")])
 
 
+class DeviceBuffers(C.Structure):
+    _fields_ = [("offsets", C.c_void_p), ("counts", C.c_void_p), ("errors", C.c_void_p)]
+
+
 class Gaussian(C.Structure):
     _fields_ = [("mx", C.c_double), ("my", C.c_double), ("s", C.c_double)]
 
@@ -63,6 +67,7 @@ _P = C.c_void_p
 _SIGNATURES = {
     "bn_create_problem": [C.POINTER(Config), _P, _P, _P, C.POINTER(_P)],
     "bn_destroy_problem": [_P],
+    "bn_create_problem_ext": [C.POINTER(Config), _P, _P, _P, _P, C.POINTER(_P)],
     "bn_init_offsets": [_P, _P],
     "bn_compute_errors": [_P],
     "bn_sweep": [_P, C.c_uint32, C.POINTER(SweepStats)],
@@ -223,7 +228,10 @@ class Problem:
     """Owns one ``bn_problem`` handle."""
 
     def __init__(self, cfg: Config, heavisides: np.ndarray | None = None, stream: int | None = None,
-                 gaussians: np.ndarray | None = None):
+                 gaussians: np.ndarray | None = None, buffers: tuple | None = None):
+        """buffers: optional (offsets, counts, errors) device addresses the
+        caller owns (bn_create_problem_ext); None entries are allocated by
+        the library."""
         self.cfg = cfg
         self.P = cfg.width * cfg.height
         self.T = cfg.t_heaviside
@@ -236,7 +244,12 @@ class Problem:
         if g is not None and g.shape[0] != cfg.t_gauss:
             raise ValueError("gaussian table length differs from t_gauss")
         handle = C.c_void_p()
-        _call("bn_create_problem", C.byref(cfg), _ptr(h), _ptr(g), C.c_void_p(stream or 0), C.byref(handle))
+        if buffers is None:
+            _call("bn_create_problem", C.byref(cfg), _ptr(h), _ptr(g), C.c_void_p(stream or 0), C.byref(handle))
+        else:
+            b = DeviceBuffers(*[C.c_void_p(x) if x else None for x in buffers])
+            _call("bn_create_problem_ext", C.byref(cfg), _ptr(h), _ptr(g), C.c_void_p(stream or 0),
+                  C.byref(b), C.byref(handle))
         self.handle = handle
 
     def close(self):
@@ -451,8 +464,9 @@ class Batch:
         self.close()
 
 
-def create_problem(workload: dict, heavisides=None, stream=None, gaussians=None, **overrides) -> Problem:
+def create_problem(workload: dict, heavisides=None, stream=None, gaussians=None, buffers=None,
+                   **overrides) -> Problem:
     """Create a problem from a workload description (synthgen format)."""
     w = dict(workload)
     w.update(overrides)
-    return Problem(make_config(**w), heavisides, stream, gaussians)
+    return Problem(make_config(**w), heavisides, stream, gaussians, buffers)

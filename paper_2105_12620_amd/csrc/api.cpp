@@ -260,6 +260,13 @@ struct bn_problem_s {
     *ptr = (T*)p;
     return BN_OK;
   }
+  // A caller-owned buffer when given (never freed here), else a new allocation.
+  template <class T>
+  bn_status adopt(T** ptr, void* given, size_t count) {
+    if (!given) return alloc(ptr, count);
+    *ptr = (T*)given;
+    return BN_OK;
+  }
   ~bn_problem_s() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -284,7 +291,9 @@ struct BatchGroup {
   int kind = 0;               // counting-kernel variant (count_kind: N up to 64, else 64 + lanes per item)
   uint32_t radius = 0, k = 0; // staged energy-change variant
   std::vector<uint32_t> idx;  // member indices
-  DevView* d_views = nullptr;
+  // member view tables on the device: counting groups, one per proposal set
+  // (whole sweep); phase groups, one per (set, colour class): set * K^2 + kappa
+  std::vector<DevView*> views;
   uint32_t* d_pre = nullptr;  // block prefix sums, idx.size() + 1 entries
   uint32_t* d_geo = nullptr;  // per member (gx, gy, slice length) for the staged kernel
   uint32_t blocks = 0;
@@ -297,9 +306,14 @@ struct bn_batch_s {
   std::vector<BatchGroup> count_groups, stage_groups;
   BatchGroup finish_all, commit_all;
   // members outside the grouped FP32 redraw launches (BF16, Gaussian rows or
-  // swap moves): their own sweep is recorded into the same graph
+  // swap moves): their own overlapped sweeps are recorded into the same graph
   std::vector<uint32_t> solo;
   std::vector<void*> allocs;
+  // overlapped schedule of the grouped members: the sweep-wide recount of
+  // sweep s+1 on `aux` beside the colour phases of sweep s; two sweeps per
+  // replay of the captured graph
+  hipStream_t aux = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   uint32_t tch = 256, slice_target = 512;
@@ -307,7 +321,11 @@ struct bn_batch_s {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (stream) (void)hipStreamSynchronize(stream);
+    if (aux) (void)hipStreamSynchronize(aux);
     for (void* q : allocs) (void)hipFree(q);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (aux) (void)hipStreamDestroy(aux);
   }
 };
 
@@ -768,7 +786,7 @@ bool tune_choice_valid(uint32_t tch, uint32_t slices) {
 }
 
 // (Re)build the per-group device tables from the members' current launch
-// choices.  Invalidates any captured graph.
+// choices and proposal sets.  Invalidates any captured graph.
 bn_status batch_upload(bn_batch b) {
   if (b->graph_exec) {
     (void)hipGraphExecDestroy(b->graph_exec);
@@ -788,16 +806,28 @@ bn_status batch_upload(bn_batch b) {
     p->v.tch = std::min<uint32_t>(b->tch, p->v.tp);
     p->v.slice_target = b->slice_target;
   }
-  auto upload = [&](BatchGroup& g, auto blocks_of, bool geo) -> bn_status {
+  const uint32_t K2 = b->colour_k * b->colour_k;
+  auto dev_copy = [&](const void* src, size_t bytes, void** dst) -> bn_status {
+    void* d = nullptr;
+    if (hipMalloc(&d, std::max<size_t>(bytes, 4)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BN_ENOMEM, "batch tables");
+    }
+    b->allocs.push_back(d);
+    *dst = d;
+    if (bytes) HIPCHK(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+    return BN_OK;
+  };
+  // kind 0: whole-sweep counting views per set; kind 1: phase views per (set, class)
+  auto upload = [&](BatchGroup& g, int kind, auto blocks_of, bool geo) -> bn_status {
     g.blocks = 0;
+    g.views.clear();
     if (g.idx.empty()) return BN_OK;
-    std::vector<DevView> views;
     std::vector<uint32_t> pre(1, 0), gv;
     for (uint32_t i : g.idx) {
       const DevView& v = b->members[i]->v;
-      views.push_back(v);
-      uint32_t gx = 0, gy = 0, gz = 0, trl = 0;
       if (geo) {
+        uint32_t gx = 0, gy = 0, gz = 0, trl = 0;
         stage_geometry(v, &gx, &gy, &gz, &trl);
         gv.push_back(gx);
         gv.push_back(gy);
@@ -808,61 +838,130 @@ bn_status batch_upload(bn_batch b) {
       }
     }
     g.blocks = pre.back();
-    void *dv = nullptr, *dp = nullptr, *dg = nullptr;
-    if (hipMalloc(&dv, views.size() * sizeof(DevView)) != hipSuccess ||
-        hipMalloc(&dp, pre.size() * 4) != hipSuccess || hipMalloc(&dg, std::max<size_t>(gv.size(), 1) * 4) != hipSuccess) {
-      (void)hipGetLastError();
-      if (dv) (void)hipFree(dv);
-      if (dp) (void)hipFree(dp);
-      if (dg) (void)hipFree(dg);
-      return fail(BN_ENOMEM, "batch tables");
+    bn_status st;
+    if ((st = dev_copy(pre.data(), pre.size() * 4, (void**)&g.d_pre)) != BN_OK) return st;
+    if ((st = dev_copy(gv.data(), gv.size() * 4, (void**)&g.d_geo)) != BN_OK) return st;
+    const uint32_t ntab = kind == 0 ? 2 : 2 * K2;
+    for (uint32_t tab = 0; tab < ntab; ++tab) {
+      std::vector<DevView> views;
+      for (uint32_t i : g.idx) {
+        bn_problem p = b->members[i];
+        views.push_back(kind == 0 ? sweep_view(p, (int)tab) : phase_view(p, (int)(tab / K2), tab % K2));
+      }
+      DevView* d = nullptr;
+      if ((st = dev_copy(views.data(), views.size() * sizeof(DevView), (void**)&d)) != BN_OK) return st;
+      g.views.push_back(d);
     }
-    b->allocs.push_back(dv);
-    b->allocs.push_back(dp);
-    b->allocs.push_back(dg);
-    g.d_views = (DevView*)dv;
-    g.d_pre = (uint32_t*)dp;
-    g.d_geo = (uint32_t*)dg;
-    HIPCHK(hipMemcpy(dv, views.data(), views.size() * sizeof(DevView), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(dp, pre.data(), pre.size() * 4, hipMemcpyHostToDevice));
-    if (!gv.empty()) HIPCHK(hipMemcpy(dg, gv.data(), gv.size() * 4, hipMemcpyHostToDevice));
     return BN_OK;
   };
   bn_status s;
   for (BatchGroup& g : b->count_groups)
-    if ((s = upload(g, [](const DevView& v) { return count_blocks(v); }, false)) != BN_OK) return s;
+    if ((s = upload(g, 0, [](const DevView& v) { return count_blocks(v, true); }, false)) != BN_OK) return s;
   for (BatchGroup& g : b->stage_groups)
-    if ((s = upload(g, [](const DevView&) { return 0u; }, true)) != BN_OK) return s;
-  if ((s = upload(b->finish_all, [](const DevView& v) { return (v.pc + 255) / 256; }, false)) != BN_OK) return s;
-  if ((s = upload(b->commit_all, [](const DevView& v) { return commit_blocks(v); }, false)) != BN_OK) return s;
+    if ((s = upload(g, 1, [](const DevView&) { return 0u; }, true)) != BN_OK) return s;
+  if ((s = upload(b->finish_all, 1, [](const DevView& v) { return (v.pc + 255) / 256; }, false)) != BN_OK) return s;
+  if ((s = upload(b->commit_all, 1, [](const DevView& v) { return commit_blocks(v); }, false)) != BN_OK) return s;
   return BN_OK;
 }
 
-bn_status batch_evaluate(bn_batch b, uint32_t kappa) {
-  if (b->finish_all.idx.empty()) return BN_OK;
+// Sweep-wide recount of every grouped member, `ahead` sweeps past its
+// counter, into proposal set `set`, on stream st.
+bn_status batch_recount(bn_batch b, int set, uint32_t ahead, hipStream_t st) {
   for (BatchGroup& g : b->count_groups)
-    HIPCHK(launch_count_batch(g.kind, g.d_views, g.d_pre, (uint32_t)g.idx.size(), g.blocks, kappa, b->stream));
+    HIPCHK(launch_count_batch(g.kind, g.views[set], g.d_pre, (uint32_t)g.idx.size(), g.blocks, ahead, true, st));
+  return BN_OK;
+}
+
+// Energy change and decision of colour class kappa for every grouped member,
+// proposals from set `set` (no state change).
+bn_status batch_evaluate(bn_batch b, int set, uint32_t kappa) {
+  const uint32_t t = set * b->colour_k * b->colour_k + kappa;
   for (BatchGroup& g : b->stage_groups)
-    HIPCHK(launch_stage_batch(g.radius, g.k, g.d_views, g.d_pre, g.d_geo, (uint32_t)g.idx.size(), g.blocks,
+    HIPCHK(launch_stage_batch(g.radius, g.k, g.views[t], g.d_pre, g.d_geo, (uint32_t)g.idx.size(), g.blocks,
                               kappa, b->stream));
-  HIPCHK(launch_finish_batch(b->finish_all.d_views, b->finish_all.d_pre, (uint32_t)b->finish_all.idx.size(),
+  HIPCHK(launch_finish_batch(b->finish_all.views[t], b->finish_all.d_pre, (uint32_t)b->finish_all.idx.size(),
                              b->finish_all.blocks, b->stream));
   return BN_OK;
 }
 
-bn_status batch_record_sweep(bn_batch b) {
+bn_status batch_phases(bn_batch b, int set) {
   bn_status s;
-  if (!b->commit_all.idx.empty()) {
-    for (uint32_t kappa = 0; kappa < b->colour_k * b->colour_k; ++kappa) {
-      if ((s = batch_evaluate(b, kappa)) != BN_OK) return s;
-      HIPCHK(launch_commit_batch(b->commit_all.d_views, b->commit_all.d_pre, (uint32_t)b->commit_all.idx.size(),
-                                 b->commit_all.blocks, kappa, b->stream));
+  for (uint32_t kappa = 0; kappa < b->colour_k * b->colour_k; ++kappa) {
+    if ((s = batch_evaluate(b, set, kappa)) != BN_OK) return s;
+    const uint32_t t = set * b->colour_k * b->colour_k + kappa;
+    HIPCHK(launch_commit_batch(b->commit_all.views[t], b->commit_all.d_pre, (uint32_t)b->commit_all.idx.size(),
+                               b->commit_all.blocks, kappa, b->stream));
+  }
+  return BN_OK;
+}
+
+bool batch_has_groups(bn_batch b) { return !b->commit_all.idx.empty(); }
+
+// Proposals of every redraw member's current sweep into set 0 where they are
+// not there yet (stream-ordered on the batch stream).
+bn_status batch_prefetch(bn_batch b) {
+  bn_status s;
+  bool group_stale = false;
+  for (uint32_t i : b->commit_all.idx) group_stale = group_stale || b->members[i]->prefetched != b->members[i]->sweep;
+  if (group_stale && (s = batch_recount(b, 0, 0, b->stream)) != BN_OK) return s;
+  for (uint32_t i : b->commit_all.idx) b->members[i]->prefetched = b->members[i]->sweep;
+  for (uint32_t i : b->solo) {
+    bn_problem p = b->members[i];
+    if (p->cfg.move == BN_SWAP || p->prefetched == p->sweep) continue;
+    if ((s = record_proposals(p, 0, 0, p->stream)) != BN_OK) return s;
+    p->prefetched = p->sweep;
+  }
+  return BN_OK;
+}
+
+// Two sweeps of every member: the grouped members' overlapped halves
+// [recount(s+1) -> set 1 || phases(s) from set 0], join, advance, then the
+// same with the sets exchanged; each solo member's own overlapped pair (or two
+// swap sweeps).  Set 0 holds every redraw member's current proposals before
+// and after.
+bn_status batch_record_pair(bn_batch b) {
+  bn_status s;
+  if (batch_has_groups(b)) {
+    for (int half = 0; half < 2; ++half) {
+      const int cur = half, nxt = 1 - half;
+      HIPCHK(hipEventRecord(b->ev[2 * half], b->stream));
+      HIPCHK(hipStreamWaitEvent(b->aux, b->ev[2 * half], 0));
+      if ((s = batch_recount(b, nxt, 1, b->aux)) != BN_OK) return s;
+      HIPCHK(hipEventRecord(b->ev[2 * half + 1], b->aux));
+      if ((s = batch_phases(b, cur)) != BN_OK) return s;
+      HIPCHK(hipStreamWaitEvent(b->stream, b->ev[2 * half + 1], 0));
+      HIPCHK(launch_advance_batch(b->commit_all.views[0], (uint32_t)b->commit_all.idx.size(), b->stream));
     }
-    HIPCHK(launch_advance_batch(b->commit_all.d_views, (uint32_t)b->commit_all.idx.size(), b->stream));
   }
   for (uint32_t i : b->solo) {
     bn_problem p = b->members[i];
-    if ((s = p->cfg.move == BN_SWAP ? record_swap_sweep(p) : record_sweep(p)) != BN_OK) return s;
+    if (p->cfg.move == BN_SWAP) {
+      if ((s = record_swap_sweep(p)) != BN_OK || (s = record_swap_sweep(p)) != BN_OK) return s;
+    } else if ((s = record_pair(p)) != BN_OK) {
+      return s;
+    }
+  }
+  return BN_OK;
+}
+
+// One sweep of every member outside the pair graph, leaving the next sweep's
+// proposals in set 0.
+bn_status batch_single_sweep(bn_batch b) {
+  bn_status s;
+  if (batch_has_groups(b)) {
+    if ((s = batch_phases(b, 0)) != BN_OK) return s;
+    HIPCHK(launch_advance_batch(b->commit_all.views[0], (uint32_t)b->commit_all.idx.size(), b->stream));
+    if ((s = batch_recount(b, 0, 0, b->stream)) != BN_OK) return s;
+  }
+  for (uint32_t i : b->solo) {
+    bn_problem p = b->members[i];
+    if (p->cfg.move == BN_SWAP) {
+      if ((s = record_swap_sweep(p)) != BN_OK) return s;
+    } else {
+      if ((s = record_phases(p, 0)) != BN_OK) return s;
+      HIPCHK(launch_advance(p->v, p->stream));
+      if ((s = record_proposals(p, 0, 0, p->stream)) != BN_OK) return s;
+    }
   }
   return BN_OK;
 }
@@ -877,8 +976,17 @@ std::string batch_key(bn_batch b) {
   return key;
 }
 
-// Launch-shape tuner: times one colour class's propose + evaluate (no commit,
-// so the optimisation state is untouched) for each candidate and keeps the
+// Work the tuner times for one candidate: the grouped members' sweep-wide
+// recount into set 1 (scratch until the next sweep writes it) and K^2
+// evaluations of colour class 0 from set 0 (decisions only, no commit), so
+// the optimisation state is untouched.
+bn_status batch_tune_step(bn_batch b) {
+  bn_status s = batch_recount(b, 1, 1, b->stream);
+  for (uint32_t k = 0; k < b->colour_k * b->colour_k && s == BN_OK; ++k) s = batch_evaluate(b, 0, 0);
+  return s;
+}
+
+// Launch-shape tuner: times batch_tune_step for each candidate and keeps the
 // fastest.  Results do not depend on the choice.
 bn_status batch_tune(bn_batch b) {
   const uint32_t* tchs = kTuneTch;
@@ -895,9 +1003,9 @@ bn_status batch_tune(bn_batch b) {
       b->tch = tc;
       b->slice_target = sl;
       if ((s = batch_upload(b)) != BN_OK) break;
-      if ((s = batch_evaluate(b, 0)) != BN_OK) break;   // warm-up
+      if ((s = batch_tune_step(b)) != BN_OK) break;   // warm-up
       if (hipEventRecord(e0, b->stream) != hipSuccess) { s = fail(BN_EHIP, "event record"); break; }
-      if ((s = batch_evaluate(b, 0)) != BN_OK) break;
+      if ((s = batch_tune_step(b)) != BN_OK) break;
       if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
         s = fail(BN_EHIP, "event timing");
         break;
@@ -1008,11 +1116,19 @@ bn_status bn_gaussian_integral(const bn_gaussian* g, double* out) {
 
 bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides, const bn_gaussian* gaussians,
                             void* stream, bn_problem* out) {
+  return bn_create_problem_ext(cfg, heavisides, gaussians, stream, nullptr, out);
+}
+
+bn_status bn_create_problem_ext(const bn_config* cfg, const bn_heaviside* heavisides, const bn_gaussian* gaussians,
+                                void* stream, const bn_device_buffers* bufs, bn_problem* out) {
   bn_status s = validate(cfg);
   if (s != BN_OK) return s;
   if (!out) return fail(BN_EINVAL, "out is NULL");
   if ((s = supported(cfg)) != BN_OK) return s;
   *out = nullptr;
+  if (bufs)
+    for (const void* b : {bufs->offsets, bufs->counts, bufs->errors})
+      if ((uintptr_t)b % 256) return fail(BN_EINVAL, "caller-owned device buffers must be 256-byte aligned");
 
   // Host tables first: every input is checked before the device is touched.
   std::vector<bn_heaviside> heav(cfg->t_heaviside);
@@ -1125,8 +1241,9 @@ bn_status bn_create_problem(const bn_config* cfg, const bn_heaviside* heavisides
   double* wd_d;
   if ((s = p->alloc(&lat_d, v.n)) != BN_OK || (s = p->alloc(&ihp_d, v.tp)) != BN_OK ||
       (s = p->alloc(&area_d, v.tp)) != BN_OK || (s = p->alloc(&wd_d, v.ncls)) != BN_OK ||
-      (s = p->alloc(&v.U, P)) != BN_OK || (s = p->alloc(&v.cnt, P * v.tp)) != BN_OK ||
-      (s = p->alloc(&v.err, P * v.tp)) != BN_OK || (s = p->alloc(&v.u_new, v.pc)) != BN_OK ||
+      (s = p->adopt(&v.U, bufs ? bufs->offsets : nullptr, P)) != BN_OK ||
+      (s = p->adopt(&v.cnt, bufs ? bufs->counts : nullptr, P * v.tp)) != BN_OK ||
+      (s = p->adopt(&v.err, bufs ? bufs->errors : nullptr, P * v.tp)) != BN_OK || (s = p->alloc(&v.u_new, v.pc)) != BN_OK ||
       (s = p->alloc(&v.c_new, (size_t)v.pc * v.tp)) != BN_OK || (s = p->alloc(&v.delta, v.pc)) != BN_OK ||
       (s = p->alloc(&v.accept, v.pc)) != BN_OK || (s = p->alloc(&v.ctr, 4)) != BN_OK ||
       (s = p->alloc(&v.unsure, v.pc)) != BN_OK ||
@@ -1811,6 +1928,20 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
     b->finish_all.idx.push_back(i);
     b->commit_all.idx.push_back(i);
   }
+  // proposal sets of every redraw member and the batch's auxiliary stream
+  {
+    bn_status s = BN_OK;
+    for (uint32_t i = 0; i < m && s == BN_OK; ++i)
+      if (members[i]->cfg.move == BN_REDRAW) s = ensure_sweep_sets(members[i]);
+    hipError_t e = s == BN_OK ? hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) : hipSuccess;
+    for (hipEvent_t& ev : b->ev)
+      if (e == hipSuccess && s == BN_OK) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (s == BN_OK && e != hipSuccess) s = fail(BN_EHIP, "batch stream and events: %s", hipGetErrorString(e));
+    if (s != BN_OK) {
+      delete b;
+      return s;
+    }
+  }
   // launch choices: cached, else tuned on the device
   bool cached = false;
   const std::string key = batch_key(b);
@@ -1833,7 +1964,9 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
       std::fclose(f);
     }
   }
-  bn_status s = cached ? batch_upload(b) : batch_tune(b);
+  bn_status s = batch_upload(b);
+  if (s == BN_OK) s = batch_prefetch(b);
+  if (s == BN_OK && !cached) s = batch_tune(b);
   if (s != BN_OK) {
     delete b;
     return s;
@@ -1850,9 +1983,12 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
 
 bn_status bn_batch_sweep(bn_batch b, uint32_t k) {
   if (!b) return fail(BN_EINVAL, "NULL batch");
-  if (!b->graph_exec) {
+  if (!k) return BN_OK;
+  bn_status s = batch_prefetch(b);
+  if (s != BN_OK) return s;
+  if (k >= 2 && !b->graph_exec) {
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    bn_status s = batch_record_sweep(b);
+    s = batch_record_pair(b);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (s != BN_OK) {
@@ -1868,10 +2004,14 @@ bn_status bn_batch_sweep(bn_batch b, uint32_t k) {
     }
     b->graph = g;
   }
-  for (uint32_t i = 0; i < k; ++i) HIPCHK(hipGraphLaunch(b->graph_exec, b->stream));
+  for (uint32_t i = 0; i + 1 < k; i += 2) HIPCHK(hipGraphLaunch(b->graph_exec, b->stream));
+  if (k & 1) {
+    if ((s = batch_single_sweep(b)) != BN_OK) return s;
+  }
   for (bn_problem p : b->members) {
     p->sweep += k;
-    if (k) p->errors_valid = false;
+    p->errors_valid = false;
+    if (p->cfg.move == BN_REDRAW) p->prefetched = p->sweep;
   }
   return BN_OK;
 }

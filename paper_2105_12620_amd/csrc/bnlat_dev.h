@@ -87,11 +87,11 @@ hipError_t launch_gauss_energy(const DevView& v, double* gsum, hipStream_t s);
 
 // batched launches: member i of a group owns blocks pre[i] .. pre[i+1]-1
 int count_kind(const DevView& v);
-uint32_t count_blocks(const DevView& v);
+uint32_t count_blocks(const DevView& v, bool sweep);
 uint32_t stage_rows(uint32_t k);
 void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen);
 hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
-                              uint32_t blocks, uint32_t kappa, hipStream_t s);
+                              uint32_t blocks, uint32_t kappa, bool sweep, hipStream_t s);
 hipError_t launch_stage_batch(uint32_t radius, uint32_t k, const DevView* views, const uint32_t* pre,
                               const uint32_t* geo, uint32_t nmem, uint32_t blocks, uint32_t kappa,
                               hipStream_t s);
@@ -110,6 +110,10 @@ hipError_t launch_delta_bf16(const DevView& v, uint32_t kappa, hipStream_t s);
 hipError_t launch_energy_bf16(const DevView& v, double* ysum, hipStream_t s);
 // decision from the summed class sums of a colour phase (clears them)
 hipError_t launch_finish(const DevView& v, hipStream_t s);
+// the FP32 form's staged evaluation of a colour phase without its decision:
+// exact Heaviside class sums into xpart, Gaussian rows' part into gdelta
+hipError_t launch_stage_exact(const DevView& v, uint32_t kappa, hipStream_t s);
+hipError_t launch_gauss_delta_exact(const DevView& v, uint32_t kappa, hipStream_t s);
 
 // device peak loops: kind 0 copy (buf -> buf2, size bytes), 1 dot2 chains,
 // 2 BF16 MFMA accumulations (iters iterations each); blocks workgroups of 256

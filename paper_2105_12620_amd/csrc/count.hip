@@ -180,13 +180,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
   for (uint32_t b = blockIdx.x; b < vblocks; b += gridDim.x) count_lanes_body<NS, L, MODE>(v, ihp, kappa, m, tch, b);
 }
 
-template <int NS, int L>
+// Batched form: member i owns blocks pre[i] .. pre[i+1]-1.  MODE_CLASS counts
+// the proposals of colour class kappa; MODE_SWEEP those of every pixel of the
+// sweep kappa steps ahead of the member's sweep counter (the overlapped
+// schedule's sweep-wide recount).
+template <int NS, int L, int MODE>
 __global__ __launch_bounds__(256) void k_count_batch(const DevView* __restrict__ views,
                                                      const uint32_t* __restrict__ pre, uint32_t nmem,
                                                      uint32_t kappa) {
   const uint32_t i = batch_member(pre, nmem, blockIdx.x);
   const DevView v = views[i];
-  count_lanes_body<NS, L, MODE_CLASS>(v, v.ihp, kappa, v.pc, L == 1 ? 64u : v.tch, blockIdx.x - pre[i]);
+  const uint32_t m = MODE == MODE_SWEEP ? v.w * v.h : v.pc;
+  count_lanes_body<NS, L, MODE>(v, v.ihp, kappa, m, L == 1 ? 64u : v.tch, blockIdx.x - pre[i]);
 }
 
 // Lanes per work item (N / 64 above N = 64) and the integrand chunk of a wave:
@@ -256,14 +261,16 @@ hipError_t launch_count(const DevView& v, int mode, uint32_t kappa, uint32_t m, 
 // lanes per work item (one kernel per N either way).
 int count_kind(const DevView& v) { return v.n <= 64 ? (int)v.n : 64 + (int)count_lanes(v.n); }
 
-uint32_t count_blocks(const DevView& v) {
-  return (uint32_t)((count_waves(v, v.pc, v.n <= 64 ? 64u : v.tch) + 3) / 4);
+uint32_t count_blocks(const DevView& v, bool sweep) {
+  return (uint32_t)((count_waves(v, sweep ? v.w * v.h : v.pc, v.n <= 64 ? 64u : v.tch) + 3) / 4);
 }
 
-hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
-                              uint32_t blocks, uint32_t kappa, hipStream_t s) {
+template <int MODE>
+hipError_t count_batch_dispatch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
+                                uint32_t blocks, uint32_t kappa, hipStream_t s) {
   const dim3 g(blocks), b(256);
-#define BN_COUNT(NS, L) hipLaunchKernelGGL((k_count_batch<NS, L>), g, b, 0, s, views, pre, nmem, kappa); break
+#define BN_COUNT(NS, L) \
+  hipLaunchKernelGGL((k_count_batch<NS, L, MODE>), g, b, 0, s, views, pre, nmem, kappa); break
   switch (kind) {
     case 1: BN_COUNT(1, 1);
     case 2: BN_COUNT(2, 1);
@@ -282,6 +289,12 @@ hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pr
   }
 #undef BN_COUNT
   return hipGetLastError();
+}
+
+hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
+                              uint32_t blocks, uint32_t kappa, bool sweep, hipStream_t s) {
+  return sweep ? count_batch_dispatch<MODE_SWEEP>(kind, views, pre, nmem, blocks, kappa, s)
+               : count_batch_dispatch<MODE_CLASS>(kind, views, pre, nmem, blocks, kappa, s);
 }
 
 }  // namespace bnlat

@@ -849,7 +849,7 @@ inline uint32_t stage_slices(const DevView& v, uint32_t blocks, uint32_t* trlen,
 }
 
 template <int R, int K>
-hipError_t stage_launch(const DevView& v, uint32_t kappa, long long* xpart, hipStream_t s) {
+hipError_t stage_launch(const DevView& v, uint32_t kappa, long long* xpart, hipStream_t s, bool finish = true) {
   using S = StageShape<R, K>;
   using G = StageGeom<R, K, S::BY, S::V>;
   static_assert(G::LDS_BYTES <= 65536, "staged block exceeds 64 KiB of LDS");
@@ -862,16 +862,16 @@ hipError_t stage_launch(const DevView& v, uint32_t kappa, long long* xpart, hipS
   hipLaunchKernelGGL((k_delta_stage<R, K, S::BY, S::V>), grid, dim3(G::NT), (size_t)G::LDS_BYTES, s, v, kappa,
                      trlen, xpart);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !finish) return e;
   return launch_finish(v, s);
 }
 
 template <int R>
-hipError_t stage_by_k(const DevView& v, uint32_t kappa, long long* xpart, hipStream_t s) {
+hipError_t stage_by_k(const DevView& v, uint32_t kappa, long long* xpart, hipStream_t s, bool finish = true) {
   switch (v.k) {
-    case 1: return stage_launch<R, 1>(v, kappa, xpart, s);
-    case 2: return stage_launch<R, 2>(v, kappa, xpart, s);
-    case 4: return stage_launch<R, 4>(v, kappa, xpart, s);
+    case 1: return stage_launch<R, 1>(v, kappa, xpart, s, finish);
+    case 2: return stage_launch<R, 2>(v, kappa, xpart, s, finish);
+    case 4: return stage_launch<R, 4>(v, kappa, xpart, s, finish);
     default: return delta_dispatch<MODE_CLASS>(v, kappa, v.pc, s);
   }
 }
@@ -1034,6 +1034,31 @@ hipError_t launch_gauss_delta(const DevView& v, int mode, uint32_t kappa, uint32
   }
   return mode == MODE_CLASS ? gauss_delta_dispatch<MODE_CLASS>(v, kappa, m, s)
                             : gauss_delta_dispatch<MODE_LIST>(v, kappa, m, s);
+}
+
+hipError_t launch_stage_exact(const DevView& v, uint32_t kappa, hipStream_t s) {
+  switch (v.radius) {
+    case 1: return stage_by_k<1>(v, kappa, v.xpart, s, false);
+    case 2: return stage_by_k<2>(v, kappa, v.xpart, s, false);
+    case 3: return stage_by_k<3>(v, kappa, v.xpart, s, false);
+    case 4: return stage_by_k<4>(v, kappa, v.xpart, s, false);
+    case 5: return stage_by_k<5>(v, kappa, v.xpart, s, false);
+    case 6: return stage_by_k<6>(v, kappa, v.xpart, s, false);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gauss_delta_exact(const DevView& v, uint32_t kappa, hipStream_t s) {
+  if (!v.tgp) return hipSuccess;
+  switch (v.radius) {
+    case 1: return gauss_stage_by_k<1>(v, kappa, s);
+    case 2: return gauss_stage_by_k<2>(v, kappa, s);
+    case 3: return gauss_stage_by_k<3>(v, kappa, s);
+    case 4: return gauss_stage_by_k<4>(v, kappa, s);
+    case 5: return gauss_stage_by_k<5>(v, kappa, s);
+    case 6: return gauss_stage_by_k<6>(v, kappa, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_gauss_commit(const DevView& v, uint32_t kappa, hipStream_t s) {

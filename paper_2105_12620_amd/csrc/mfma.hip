@@ -300,11 +300,9 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
   }
 }
 
-// Exact re-evaluation of the moves the BF16 pass accepted (approximate mode:
-// every one; exact mode: those whose slices could not certify exactness): the
-// integer Heaviside class sums and the Gaussian rows' plain FP64 part, as the
-// FP32 form computes them.  One wave per class pixel; a move the exact value
-// rejects is a veto.
+// Exact mode: re-check of the accepted moves whose slices could not certify
+// exactness, with the integer class sums (one wave per flagged pixel; a move
+// the exact value rejects is a veto).
 template <int R>
 __global__ __launch_bounds__(256) void k_delta_refine(DevView v, uint32_t kappa, uint32_t* __restrict__ unsure) {
   __builtin_amdgcn_s_setprio(2);
@@ -313,11 +311,8 @@ __global__ __launch_bounds__(256) void k_delta_refine(DevView v, uint32_t kappa,
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t j = wave_id();
   if (j >= v.pc) return;
-  bool todo = v.accept[j] != 0;
-  if (v.mfma == 1) {
-    todo = todo && unsure[j] != 0;
-    if (lane == 0) unsure[j] = 0;
-  }
+  const bool todo = v.accept[j] != 0 && unsure[j] != 0;
+  if (lane == 0) unsure[j] = 0;
   if (!todo) return;
   const uint32_t p = class_pixel(v, kappa, j);
   const uint32_t y = p / v.w, x = p - y * v.w, P = v.w * v.h;
@@ -379,6 +374,32 @@ __global__ __launch_bounds__(256) void k_delta_refine(DevView v, uint32_t kappa,
       v.accept[j] = 0;
       atomicAdd(&v.ctr[2], 1ull);
     }
+  }
+}
+
+// Approximate mode: every move the BF16 value accepted is re-evaluated with
+// the FP32 form's arithmetic (its staged stencils have just summed the exact
+// integer class sums into xsum and the Gaussian rows' part into gdelta, for
+// every class pixel of the phase: staging the window costs the same for one
+// pixel of a block as for all of them).  The exact value is combined in the
+// FP32 form's order; a move it rejects is a veto.  Clears xsum.
+__global__ __launch_bounds__(256) void k_refine_combine(DevView v, long long* __restrict__ xsum) {
+  __builtin_amdgcn_s_setprio(2);
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= v.pc) return;
+  double acc = 0.0;
+  for (uint32_t c = 0; c < v.ncls; ++c) {
+    const long long x = xsum[(size_t)c * v.pc + j];
+    xsum[(size_t)c * v.pc + j] = 0;
+    acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)x));
+  }
+  if (!v.accept[j]) return;
+  double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+  if (v.tgp) total = __dadd_rn(total, v.gdelta[j]);
+  v.delta[j] = total;
+  if (!((v.objective > 0) ? (total < 0.0) : (total > 0.0))) {
+    v.accept[j] = 0;
+    atomicAdd(&v.ctr[2], 1ull);
   }
 }
 
@@ -489,7 +510,13 @@ hipError_t bf_launch(const DevView& v, uint32_t kappa, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = launch_finish(v, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_delta_refine<R>), dim3((v.pc + 3) / 4), dim3(256), 0, s, v, kappa, v.unsure);
+  if (v.mfma == 1) {
+    hipLaunchKernelGGL((k_delta_refine<R>), dim3((v.pc + 3) / 4), dim3(256), 0, s, v, kappa, v.unsure);
+    return hipGetLastError();
+  }
+  if ((e = launch_stage_exact(v, kappa, s)) != hipSuccess) return e;
+  if ((e = launch_gauss_delta_exact(v, kappa, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_refine_combine, dim3((v.pc + 255) / 256), dim3(256), 0, s, v, v.xpart);
   return hipGetLastError();
 }
 
