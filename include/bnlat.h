@@ -222,6 +222,18 @@ bn_status bn_quality_metric(bn_problem p, const double* sigmas, uint32_t n, doub
 typedef enum { BN_ROWS_ALL = 0, BN_ROWS_HEAVISIDE = 1, BN_ROWS_GAUSSIAN = 2 } bn_rows;
 bn_status bn_quality_metric_family(bn_problem p, bn_rows rows, const double* sigmas, uint32_t n, double* out);
 
+/* Error spectrum beside the blur criterion (the |FFT(e)|^2 insets of
+ * Fig. 1b): for every integrand row of the family (BN_ROWS_* as above) the
+ * power |DFT2(e_t)(u, v)|^2 / (W H) over the W x H torus, averaged over the
+ * rows and over the frequencies of each radial bin.  Frequency (u, v) has
+ * the radius of (u/W, v/H) folded to [-1/2, 1/2) in cycles per pixel; its bin
+ * is that radius times min(W, H), rounded to the nearest integer; bins from
+ * nbins on are dropped.  out double [nbins] (0 for an empty bin), counts
+ * uint32 [nbins] frequencies per bin (nullable).  White noise of variance s^2
+ * gives s^2 in every bin.  Direct DFT on the device (FP32 within a row or
+ * column, FP64 across rows); allocates scratch for the call.  Synchronises. */
+bn_status bn_error_spectrum(bn_problem p, bn_rows rows, uint32_t nbins, double* out, uint32_t* counts);
+
 /* Copy the offset tile to host_u: uint16 [H][W][2].  Synchronises. */
 bn_status bn_get_offsets(bn_problem p, uint16_t* host_u);
 
@@ -362,26 +374,30 @@ bn_status bn_sample_device(const bn_problem* pairs, uint32_t npairs, const uint3
 /* ----------------------------------------------------------------- batching */
 
 /* Independent problems (e.g. the dimension pairs of a padded sampler,
- * Sec. 3.1) swept together: for each colour class, one launch per kernel
- * variant covers every member (members grouped by samples-per-pixel class for
- * counting and by window radius for the energy change), and a whole sweep of
- * all members is captured once as a HIP graph and replayed k times.  Each
- * member's trajectory equals the one bn_sweep gives it alone.  Members in the
- * FP32 form with Heaviside rows only and redraw moves share the grouped
- * launches; members in the BF16 form, with Gaussian rows or with swap moves
- * have their own sweep recorded into the same graph.  Requirements: members
- * distinct, created on one stream, bn_compute_errors done, profiling off, one
- * common colour_k in {1, 2, 4}.  tune_cache (nullable) names a text
- * file of launch choices keyed by the members' shapes; when the key is absent
- * the tuner times the candidates on the device (propose + evaluate only, no
- * state change) and appends its choice.  Members stay owned by the caller and
- * must outlive the batch; do not sweep them individually while batched. */
+ * Sec. 3.1) swept together in one captured HIP graph of two sweeps.  Members
+ * in the FP32 form with Heaviside rows only and redraw moves share grouped
+ * launches: one sweep-wide recount launch per samples-per-pixel class (on an
+ * auxiliary stream, for the next sweep) beside, per colour class, one launch
+ * per window radius for the energy change and one decision and one commit
+ * launch over all of them.  Members in the BF16 form, with Gaussian rows or
+ * with swap moves have their own overlapped sweeps recorded into the same
+ * graph as independent branches.  Each member's trajectory equals the one
+ * bn_sweep gives it alone.  Requirements: members distinct, created on one
+ * stream, bn_compute_errors done, profiling off, one common colour_k in
+ * {1, 2, 4}.  tune_cache (nullable) names a text file of launch choices
+ * keyed by the members' shapes; when the key is absent (or its choice is not
+ * one of the candidates) the tuner times the candidates on the device (a
+ * recount and evaluations without commit, no state change) and appends its
+ * choice.  Members stay owned by the caller and must outlive the batch;
+ * sweeping a member on its own between batched sweeps is allowed. */
 bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tune_cache,
                           bn_batch* out);
 bn_status bn_batch_sweep(bn_batch b, uint32_t k);
 /* Launch choices the tuner picked (integrands per counting wave, workgroup
- * target of the staged energy-change launch); no device work. */
-bn_status bn_batch_tuning(bn_batch b, uint32_t* tch, uint32_t* slice_target);
+ * target of the staged energy-change launch, its block shape: 0 the
+ * single-problem shape, 1 the alternative with half the waves per workgroup
+ * for K = 1, 2 and twice for K = 4); every pointer nullable; no device work. */
+bn_status bn_batch_tuning(bn_batch b, uint32_t* tch, uint32_t* slice_target, uint32_t* stage_shape);
 bn_status bn_destroy_batch(bn_batch b);
 
 /* ------------------------------------------------ host-only (no device work) */

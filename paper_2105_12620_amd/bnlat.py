@@ -76,6 +76,7 @@ _SIGNATURES = {
     "bn_get_phase_bf16": [_P, _P],
     "bn_quality_metric": [_P, _P, C.c_uint32, _P],
     "bn_quality_metric_family": [_P, C.c_int, _P, C.c_uint32, _P],
+    "bn_error_spectrum": [_P, C.c_int, C.c_uint32, _P, _P],
     "bn_get_offsets": [_P, _P],
     "bn_get_counts": [_P, _P],
     "bn_get_errors": [_P, _P],
@@ -99,7 +100,7 @@ _SIGNATURES = {
     "bn_create_batch": [_P, C.c_uint32, C.c_char_p, C.POINTER(_P)],
     "bn_batch_sweep": [_P, C.c_uint32],
     "bn_destroy_batch": [_P],
-    "bn_batch_tuning": [_P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)],
+    "bn_batch_tuning": [_P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)],
     "bn_validate_config": [C.POINTER(Config)],
     "bn_swap_permutation": [C.POINTER(Config), _P],
     "bn_window_classes": [C.POINTER(Config), C.POINTER(C.c_uint32), _P, _P],
@@ -306,6 +307,13 @@ class Problem:
             _call("bn_quality_metric", self.handle, _ptr(s), s.shape[0], _ptr(out))
         return out
 
+    def error_spectrum(self, nbins: int, rows: int = 0):
+        """Radially averaged |DFT2(e_t)|^2 / P: (mean power [nbins], frequencies per bin)."""
+        out = np.zeros(nbins, dtype=np.float64)
+        cnt = np.zeros(nbins, dtype=np.uint32)
+        _call("bn_error_spectrum", self.handle, rows, nbins, _ptr(out), _ptr(cnt))
+        return out, cnt
+
     def get_offsets(self) -> np.ndarray:
         out = np.zeros((self.cfg.height, self.cfg.width, 2), dtype=np.uint16)
         _call("bn_get_offsets", self.handle, _ptr(out))
@@ -442,9 +450,9 @@ class Batch:
         _call("bn_batch_sweep", self.handle, k)
 
     def tuning(self):
-        a, b = C.c_uint32(), C.c_uint32()
-        _call("bn_batch_tuning", self.handle, C.byref(a), C.byref(b))
-        return {"tch": a.value, "slice_target": b.value}
+        a, b, c = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _call("bn_batch_tuning", self.handle, C.byref(a), C.byref(b), C.byref(c))
+        return {"tch": a.value, "slice_target": b.value, "stage_shape": c.value}
 
     def close(self):
         if getattr(self, "handle", None):

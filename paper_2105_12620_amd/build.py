@@ -12,7 +12,8 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/count.hip", "csrc/kernels.hip", "csrc/swap.hip", "csrc/sampler.hip", "csrc/mfma.hip",
-           "csrc/noalloc.hip", "csrc/peaks.hip", "csrc/api.cpp"]
+           "csrc/noalloc.hip", "csrc/peaks.hip",
+           "csrc/spectrum.hip", "csrc/api.cpp"]
 LIB = os.path.join(HERE, "libbnlat.so")
 
 FLAGS = [

@@ -316,7 +316,7 @@ struct bn_batch_s {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  uint32_t tch = 256, slice_target = 512;
+  uint32_t tch = 256, slice_target = 512, shape = 0;
   ~bn_batch_s() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -779,10 +779,12 @@ bn_status build_graph(bn_problem p) {
 // workgroup target of the staged energy-change launch.
 const uint32_t kTuneTch[] = {64, 128, 256, 512};
 const uint32_t kTuneSlices[] = {128, 256, 512, 1024, 2048};
+const uint32_t kTuneShapes[] = {0, 1};
 
-bool tune_choice_valid(uint32_t tch, uint32_t slices) {
+bool tune_choice_valid(uint32_t tch, uint32_t slices, uint32_t shape) {
   return std::find(std::begin(kTuneTch), std::end(kTuneTch), tch) != std::end(kTuneTch) &&
-         std::find(std::begin(kTuneSlices), std::end(kTuneSlices), slices) != std::end(kTuneSlices);
+         std::find(std::begin(kTuneSlices), std::end(kTuneSlices), slices) != std::end(kTuneSlices) &&
+         std::find(std::begin(kTuneShapes), std::end(kTuneShapes), shape) != std::end(kTuneShapes);
 }
 
 // (Re)build the per-group device tables from the members' current launch
@@ -796,9 +798,9 @@ bn_status batch_upload(bn_batch b) {
     (void)hipGraphDestroy(b->graph);
     b->graph = nullptr;
   }
-  if (!tune_choice_valid(b->tch, b->slice_target))
-    return fail(BN_EINVAL, "launch choice tch=%u slices=%u is not one of the tuner's candidates", b->tch,
-                b->slice_target);
+  if (!tune_choice_valid(b->tch, b->slice_target, b->shape))
+    return fail(BN_EINVAL, "launch choice tch=%u slices=%u shape=%u is not one of the tuner's candidates", b->tch,
+                b->slice_target, b->shape);
   HIPCHK(hipStreamSynchronize(b->stream));
   for (void* q : b->allocs) (void)hipFree(q);
   b->allocs.clear();
@@ -828,7 +830,7 @@ bn_status batch_upload(bn_batch b) {
       const DevView& v = b->members[i]->v;
       if (geo) {
         uint32_t gx = 0, gy = 0, gz = 0, trl = 0;
-        stage_geometry(v, &gx, &gy, &gz, &trl);
+        stage_geometry(v, b->shape, &gx, &gy, &gz, &trl);
         gv.push_back(gx);
         gv.push_back(gy);
         gv.push_back(trl);
@@ -875,9 +877,10 @@ bn_status batch_recount(bn_batch b, int set, uint32_t ahead, hipStream_t st) {
 // Energy change and decision of colour class kappa for every grouped member,
 // proposals from set `set` (no state change).
 bn_status batch_evaluate(bn_batch b, int set, uint32_t kappa) {
+  if (b->finish_all.idx.empty()) return BN_OK;   // no grouped members
   const uint32_t t = set * b->colour_k * b->colour_k + kappa;
   for (BatchGroup& g : b->stage_groups)
-    HIPCHK(launch_stage_batch(g.radius, g.k, g.views[t], g.d_pre, g.d_geo, (uint32_t)g.idx.size(), g.blocks,
+    HIPCHK(launch_stage_batch(g.radius, g.k, b->shape, g.views[t], g.d_pre, g.d_geo, (uint32_t)g.idx.size(), g.blocks,
                               kappa, b->stream));
   HIPCHK(launch_finish_batch(b->finish_all.views[t], b->finish_all.d_pre, (uint32_t)b->finish_all.idx.size(),
                              b->finish_all.blocks, b->stream));
@@ -986,37 +989,40 @@ bn_status batch_tune_step(bn_batch b) {
   return s;
 }
 
-// Launch-shape tuner: times batch_tune_step for each candidate and keeps the
-// fastest.  Results do not depend on the choice.
+// Launch-shape tuner: times batch_tune_step for every candidate (integrands
+// per counting wave, workgroup target and block shape of the staged energy
+// change) and keeps the fastest.  Results do not depend on the choice.
 bn_status batch_tune(bn_batch b) {
-  const uint32_t* tchs = kTuneTch;
-  const uint32_t* slices = kTuneSlices;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   float best = 1e30f;
-  uint32_t bt = b->tch, bs = b->slice_target;
+  uint32_t bt = b->tch, bs = b->slice_target, bh = b->shape;
   bn_status s = BN_OK;
-  for (uint32_t ti = 0; ti < std::size(kTuneTch); ++ti) {
-    for (uint32_t si = 0; si < std::size(kTuneSlices); ++si) {
-      const uint32_t tc = tchs[ti], sl = slices[si];
-      b->tch = tc;
-      b->slice_target = sl;
-      if ((s = batch_upload(b)) != BN_OK) break;
-      if ((s = batch_tune_step(b)) != BN_OK) break;   // warm-up
-      if (hipEventRecord(e0, b->stream) != hipSuccess) { s = fail(BN_EHIP, "event record"); break; }
-      if ((s = batch_tune_step(b)) != BN_OK) break;
-      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-        s = fail(BN_EHIP, "event timing");
-        break;
+  for (uint32_t sh : kTuneShapes) {
+    for (uint32_t tc : kTuneTch) {
+      for (uint32_t sl : kTuneSlices) {
+        b->tch = tc;
+        b->slice_target = sl;
+        b->shape = sh;
+        if ((s = batch_upload(b)) != BN_OK) break;
+        if ((s = batch_tune_step(b)) != BN_OK) break;   // warm-up
+        if (hipEventRecord(e0, b->stream) != hipSuccess) { s = fail(BN_EHIP, "event record"); break; }
+        if ((s = batch_tune_step(b)) != BN_OK) break;
+        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          s = fail(BN_EHIP, "event timing");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          bt = tc;
+          bs = sl;
+          bh = sh;
+        }
       }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
-        bt = tc;
-        bs = sl;
-      }
+      if (s != BN_OK) break;
     }
     if (s != BN_OK) break;
   }
@@ -1025,6 +1031,7 @@ bn_status batch_tune(bn_batch b) {
   if (s != BN_OK) return s;
   b->tch = bt;
   b->slice_target = bs;
+  b->shape = bh;
   return batch_upload(b);
 }
 
@@ -1502,6 +1509,76 @@ bn_status bn_quality_metric_family(bn_problem p, bn_rows rows, const double* sig
   return BN_OK;
 }
 
+bn_status bn_error_spectrum(bn_problem p, bn_rows rows, uint32_t nbins, double* out, uint32_t* counts) {
+  if (!p || !nbins || !out) return fail(BN_EINVAL, "NULL argument or no bins");
+  if (rows != BN_ROWS_ALL && rows != BN_ROWS_HEAVISIDE && rows != BN_ROWS_GAUSSIAN)
+    return fail(BN_EINVAL, "unknown row family");
+  if (rows == BN_ROWS_GAUSSIAN && !p->v.tg) return fail(BN_EINVAL, "the problem has no Gaussian integrands");
+  if (!p->have_counts) return fail(BN_ESTATE, "bn_compute_errors must run first");
+  bn_status rs = refresh_errors(p);
+  if (rs != BN_OK) return rs;
+  const uint32_t W = p->v.w, H = p->v.h;
+  const size_t P = (size_t)W * H;
+  std::vector<float2> twx(W), twy(H);
+  for (uint32_t k = 0; k < W; ++k)
+    twx[k] = make_float2((float)std::cos(2.0 * M_PI * k / W), (float)-std::sin(2.0 * M_PI * k / W));
+  for (uint32_t k = 0; k < H; ++k)
+    twy[k] = make_float2((float)std::cos(2.0 * M_PI * k / H), (float)-std::sin(2.0 * M_PI * k / H));
+  float2 *d_rows = nullptr, *d_twx = nullptr, *d_twy = nullptr;
+  double* d_pw = nullptr;
+  auto release = [&]() {
+    for (void* q : {(void*)d_rows, (void*)d_twx, (void*)d_twy, (void*)d_pw})
+      if (q) (void)hipFree(q);
+  };
+  // scratch for the duration of the call only
+  hipError_t e = hipMalloc((void**)&d_rows, spectrum_scratch_floats2(p->v) * sizeof(float2));
+  if (e == hipSuccess) e = hipMalloc((void**)&d_twx, W * sizeof(float2));
+  if (e == hipSuccess) e = hipMalloc((void**)&d_twy, H * sizeof(float2));
+  if (e == hipSuccess) e = hipMalloc((void**)&d_pw, P * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(BN_ENOMEM, "spectrum scratch: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpyAsync(d_twx, twx.data(), W * sizeof(float2), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_twy, twy.data(), H * sizeof(float2), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d_pw, 0, P * sizeof(double), p->stream);
+  const float* fields[2] = {p->v.err, p->v.gerr};
+  const uint32_t pitches[2] = {p->v.tp, p->v.tgp}, valids[2] = {p->v.t, p->v.tg};
+  uint32_t used = 0;
+  for (int f = 0; f < 2 && e == hipSuccess; ++f) {
+    if (!valids[f] || (rows == BN_ROWS_HEAVISIDE && f == 1) || (rows == BN_ROWS_GAUSSIAN && f == 0)) continue;
+    used += valids[f];
+    for (uint32_t t0 = 0; t0 < valids[f] && e == hipSuccess; t0 += spectrum_chunk())
+      e = launch_spectrum_chunk(p->v, fields[f], pitches[f], valids[f], t0, d_twx, d_twy, d_rows, d_pw, p->stream);
+  }
+  std::vector<double> pw(P);
+  if (e == hipSuccess) e = hipMemcpyAsync(pw.data(), d_pw, P * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  release();
+  if (e != hipSuccess) return fail(BN_EHIP, "error spectrum: %s", hipGetErrorString(e));
+  // radial bins: the frequency in cycles per pixel, folded to [-1/2, 1/2),
+  // in units of 1 / min(W, H), rounded
+  std::vector<double> sum(nbins, 0.0);
+  std::vector<uint32_t> cnt(nbins, 0);
+  const double unit = (double)std::min(W, H);
+  for (uint32_t v = 0; v < H; ++v)
+    for (uint32_t u = 0; u < W; ++u) {
+      const double fu = 2 * u < W ? (double)u / W : (double)u / W - 1.0;
+      const double fv = 2 * v < H ? (double)v / H : (double)v / H - 1.0;
+      const double b = std::nearbyint(std::sqrt(fu * fu + fv * fv) * unit);
+      if (b < (double)nbins) {
+        sum[(size_t)b] += pw[(size_t)v * W + u];
+        cnt[(size_t)b] += 1;
+      }
+    }
+  for (uint32_t b = 0; b < nbins; ++b) {
+    out[b] = cnt[b] ? sum[b] / ((double)cnt[b] * (double)P * (double)used) : 0.0;
+    if (counts) counts[b] = cnt[b];
+  }
+  return BN_OK;
+}
+
 bn_status bn_get_offsets(bn_problem p, uint16_t* host_u) {
   if (!p || !host_u) return fail(BN_EINVAL, "NULL argument");
   if (!p->have_offsets) return fail(BN_ESTATE, "offsets are not initialised");
@@ -1950,14 +2027,15 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
       char line[8192];
       while (std::fgets(line, sizeof line, f)) {
         char k[4096];
-        unsigned tc = 0, sl = 0;
-        if (std::sscanf(line, "%4095s tch=%u slices=%u", k, &tc, &sl) == 3 && key == k) {
+        unsigned tc = 0, sl = 0, sh = 0;
+        if (std::sscanf(line, "%4095s tch=%u slices=%u shape=%u", k, &tc, &sl, &sh) >= 3 && key == k) {
           // only the tuner's own candidates are trusted: a chunk that is not
           // a multiple of 64 integrands would make the counting waves' tiles
           // overlap
-          if (!tune_choice_valid(tc, sl)) continue;
+          if (!tune_choice_valid(tc, sl, sh)) continue;
           b->tch = tc;
           b->slice_target = sl;
+          b->shape = sh;
           cached = true;
         }
       }
@@ -1973,7 +2051,7 @@ bn_status bn_create_batch(const bn_problem* members, uint32_t m, const char* tun
   }
   if (tune_cache && !cached) {
     if (FILE* f = std::fopen(tune_cache, "a")) {
-      std::fprintf(f, "%s tch=%u slices=%u\n", key.c_str(), b->tch, b->slice_target);
+      std::fprintf(f, "%s tch=%u slices=%u shape=%u\n", key.c_str(), b->tch, b->slice_target, b->shape);
       std::fclose(f);
     }
   }
@@ -2016,10 +2094,11 @@ bn_status bn_batch_sweep(bn_batch b, uint32_t k) {
   return BN_OK;
 }
 
-bn_status bn_batch_tuning(bn_batch b, uint32_t* tch, uint32_t* slice_target) {
+bn_status bn_batch_tuning(bn_batch b, uint32_t* tch, uint32_t* slice_target, uint32_t* stage_shape) {
   if (!b) return fail(BN_EINVAL, "NULL batch");
   if (tch) *tch = b->tch;
   if (slice_target) *slice_target = b->slice_target;
+  if (stage_shape) *stage_shape = b->shape;
   return BN_OK;
 }
 

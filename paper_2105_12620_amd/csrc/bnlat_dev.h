@@ -88,11 +88,12 @@ hipError_t launch_gauss_energy(const DevView& v, double* gsum, hipStream_t s);
 // batched launches: member i of a group owns blocks pre[i] .. pre[i+1]-1
 int count_kind(const DevView& v);
 uint32_t count_blocks(const DevView& v, bool sweep);
-uint32_t stage_rows(uint32_t k);
-void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen);
+// staged-kernel block shape 0 (default) or 1 (the tuner's alternative)
+uint32_t stage_rows(uint32_t k, uint32_t shape);
+void stage_geometry(const DevView& v, uint32_t shape, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen);
 hipError_t launch_count_batch(int kind, const DevView* views, const uint32_t* pre, uint32_t nmem,
                               uint32_t blocks, uint32_t kappa, bool sweep, hipStream_t s);
-hipError_t launch_stage_batch(uint32_t radius, uint32_t k, const DevView* views, const uint32_t* pre,
+hipError_t launch_stage_batch(uint32_t radius, uint32_t k, uint32_t shape, const DevView* views, const uint32_t* pre,
                               const uint32_t* geo, uint32_t nmem, uint32_t blocks, uint32_t kappa,
                               hipStream_t s);
 hipError_t launch_finish_batch(const DevView* views, const uint32_t* pre, uint32_t nmem, uint32_t blocks,
@@ -114,6 +115,14 @@ hipError_t launch_finish(const DevView& v, hipStream_t s);
 // exact Heaviside class sums into xpart, Gaussian rows' part into gdelta
 hipError_t launch_stage_exact(const DevView& v, uint32_t kappa, hipStream_t s);
 hipError_t launch_gauss_delta_exact(const DevView& v, uint32_t kappa, hipStream_t s);
+
+// error spectrum (spectrum.hip): DFT of SPEC_CHUNK integrand rows along x
+// into rows [H][W][chunk] (complex), then along y with |.|^2 summed over the
+// chunk into power [H][W] (added to)
+uint32_t spectrum_chunk();
+size_t spectrum_scratch_floats2(const DevView& v);
+hipError_t launch_spectrum_chunk(const DevView& v, const float* field, uint32_t pitch, uint32_t valid, uint32_t t0,
+                                 const float2* twx, const float2* twy, float2* rows, double* power, hipStream_t s);
 
 // device peak loops: kind 0 copy (buf -> buf2, size bytes), 1 dot2 chains,
 // 2 BF16 MFMA accumulations (iters iterations each); blocks workgroups of 256

@@ -131,10 +131,12 @@ struct StageGeom {
 
 // Block shape of the staged kernel for K colour classes per axis and radius R:
 // class rows per thread (V) and thread rows (BY), within 64 KiB of LDS.
-template <int R, int K>
+// Shape 0 is the single-problem default; the batched form's tuner also tries
+// shape 1 (twice the waves per workgroup for K = 4, half for K = 1, 2).
+template <int R, int K, int SH = 0>
 struct StageShape {
   static constexpr int V = (K == 4) ? 1 : 2;
-  static constexpr int BY = (K == 4) ? 2 : 8;
+  static constexpr int BY = (K == 4) ? (SH ? 4 : 2) : (SH ? 4 : 8);
 };
 
 // Largest slice (a multiple of 8 integrands) whose class sums fit int32: every
@@ -1093,11 +1095,13 @@ hipError_t launch_gauss_energy(const DevView& v, double* gsum, hipStream_t s) {
 
 // ------------------------------------------------------------------ batches
 
-uint32_t stage_rows(uint32_t k) { return k == 4 ? StageShape<1, 4>::BY * StageShape<1, 4>::V
-                                                : StageShape<1, 2>::BY * StageShape<1, 2>::V; }
+uint32_t stage_rows(uint32_t k, uint32_t shape) {
+  if (k == 4) return shape ? StageShape<1, 4, 1>::BY * StageShape<1, 4, 1>::V : StageShape<1, 4>::BY * StageShape<1, 4>::V;
+  return shape ? StageShape<1, 2, 1>::BY * StageShape<1, 2, 1>::V : StageShape<1, 2>::BY * StageShape<1, 2>::V;
+}
 
-void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen) {
-  const uint32_t cr = stage_rows(v.k);
+void stage_geometry(const DevView& v, uint32_t shape, uint32_t* gx, uint32_t* gy, uint32_t* gz, uint32_t* trlen) {
+  const uint32_t cr = stage_rows(v.k, shape);
   *gx = (v.cw + 31) / 32;
   *gy = (v.ch + cr - 1) / cr;
   *gz = stage_slices(v, *gx * *gy, trlen, 8, stage_max_slice(v.n), 64);
@@ -1105,41 +1109,44 @@ void stage_geometry(const DevView& v, uint32_t* gx, uint32_t* gy, uint32_t* gz, 
 
 
 namespace {
-template <int R, int K>
+template <int R, int K, int SH>
 hipError_t stage_batch_rk(const DevView* views, const uint32_t* pre, const uint32_t* geo, uint32_t nmem,
                           uint32_t blocks, uint32_t kappa, hipStream_t s) {
-  using S = StageShape<R, K>;
+  using S = StageShape<R, K, SH>;
   using G = StageGeom<R, K, S::BY, S::V>;
-  static_assert(G::CR == (K == 4 ? StageShape<1, 4>::BY * StageShape<1, 4>::V
-                                 : StageShape<1, 2>::BY * StageShape<1, 2>::V),
-                "batched geometry assumes one block shape per K");
+  static_assert(G::LDS_BYTES <= 65536, "staged block exceeds 64 KiB of LDS");
+  static_assert(G::CR == StageShape<1, K == 4 ? 4 : 2, SH>::BY * StageShape<1, K == 4 ? 4 : 2, SH>::V,
+                "batched geometry assumes one block shape per (K, shape)");
   hipLaunchKernelGGL((k_delta_stage_batch<R, K, S::BY, S::V>), dim3(blocks), dim3(G::NT), (size_t)G::LDS_BYTES, s,
                      views, pre, geo, nmem, kappa);
   return hipGetLastError();
 }
 
 template <int R>
-hipError_t stage_batch_r(uint32_t k, const DevView* views, const uint32_t* pre, const uint32_t* geo,
+hipError_t stage_batch_r(uint32_t k, uint32_t shape, const DevView* views, const uint32_t* pre, const uint32_t* geo,
                          uint32_t nmem, uint32_t blocks, uint32_t kappa, hipStream_t s) {
-  switch (k) {
-    case 1: return stage_batch_rk<R, 1>(views, pre, geo, nmem, blocks, kappa, s);
-    case 2: return stage_batch_rk<R, 2>(views, pre, geo, nmem, blocks, kappa, s);
-    case 4: return stage_batch_rk<R, 4>(views, pre, geo, nmem, blocks, kappa, s);
+  switch (k * 2 + (shape ? 1 : 0)) {
+    case 2: return stage_batch_rk<R, 1, 0>(views, pre, geo, nmem, blocks, kappa, s);
+    case 3: return stage_batch_rk<R, 1, 1>(views, pre, geo, nmem, blocks, kappa, s);
+    case 4: return stage_batch_rk<R, 2, 0>(views, pre, geo, nmem, blocks, kappa, s);
+    case 5: return stage_batch_rk<R, 2, 1>(views, pre, geo, nmem, blocks, kappa, s);
+    case 8: return stage_batch_rk<R, 4, 0>(views, pre, geo, nmem, blocks, kappa, s);
+    case 9: return stage_batch_rk<R, 4, 1>(views, pre, geo, nmem, blocks, kappa, s);
     default: return hipErrorInvalidValue;
   }
 }
 }  // namespace
 
-hipError_t launch_stage_batch(uint32_t radius, uint32_t k, const DevView* views, const uint32_t* pre,
+hipError_t launch_stage_batch(uint32_t radius, uint32_t k, uint32_t shape, const DevView* views, const uint32_t* pre,
                               const uint32_t* geo, uint32_t nmem, uint32_t blocks, uint32_t kappa,
                               hipStream_t s) {
   switch (radius) {
-    case 1: return stage_batch_r<1>(k, views, pre, geo, nmem, blocks, kappa, s);
-    case 2: return stage_batch_r<2>(k, views, pre, geo, nmem, blocks, kappa, s);
-    case 3: return stage_batch_r<3>(k, views, pre, geo, nmem, blocks, kappa, s);
-    case 4: return stage_batch_r<4>(k, views, pre, geo, nmem, blocks, kappa, s);
-    case 5: return stage_batch_r<5>(k, views, pre, geo, nmem, blocks, kappa, s);
-    case 6: return stage_batch_r<6>(k, views, pre, geo, nmem, blocks, kappa, s);
+    case 1: return stage_batch_r<1>(k, shape, views, pre, geo, nmem, blocks, kappa, s);
+    case 2: return stage_batch_r<2>(k, shape, views, pre, geo, nmem, blocks, kappa, s);
+    case 3: return stage_batch_r<3>(k, shape, views, pre, geo, nmem, blocks, kappa, s);
+    case 4: return stage_batch_r<4>(k, shape, views, pre, geo, nmem, blocks, kappa, s);
+    case 5: return stage_batch_r<5>(k, shape, views, pre, geo, nmem, blocks, kappa, s);
+    case 6: return stage_batch_r<6>(k, shape, views, pre, geo, nmem, blocks, kappa, s);
     default: return hipErrorInvalidValue;
   }
 }

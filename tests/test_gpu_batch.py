@@ -75,8 +75,14 @@ def test_tune_cache_round_trip(stream, tmp_path):
     with open(fixed, "w") as f:
         f.write(f"{key} tch=64 slices=2048\n")
     with bnlat.Batch(probs, tune_cache=fixed) as b:
-        assert b.tuning() == {"tch": 64, "slice_target": 2048}
+        # a line written before the block shape was a choice: shape 0
+        assert b.tuning() == {"tch": 64, "slice_target": 2048, "stage_shape": 0}
         b.sweep(1)
+    with open(fixed, "w") as f:
+        f.write(f"{key} tch=128 slices=512 shape=1\n")
+    with bnlat.Batch(probs, tune_cache=fixed) as b:
+        assert b.tuning() == {"tch": 128, "slice_target": 512, "stage_shape": 1}
+        b.sweep(2)
     for p in probs:
         p.close()
 
@@ -94,14 +100,14 @@ def test_tune_cache_rejects_foreign_choices(stream, tmp_path):
     key = open(probe).read().split()[0]
     bad = str(tmp_path / "bad.txt")
     with open(bad, "w") as f:
-        f.write(f"{key} tch=100 slices=2048\n{key} tch=256 slices=7\n")
+        f.write(f"{key} tch=100 slices=2048\n{key} tch=256 slices=7\n{key} tch=256 slices=512 shape=2\n")
     with bnlat.Batch(probs, tune_cache=bad) as b:
         got = b.tuning()
         assert got["tch"] in (64, 128, 256, 512)
         assert got["slice_target"] in (128, 256, 512, 1024, 2048)
         b.sweep(1)
     lines = open(bad).read().splitlines()
-    assert len(lines) == 3 and lines[2].startswith(key)
+    assert len(lines) == 4 and lines[3].startswith(key)
     for w, inp, p in zip(MEMBERS[:3], inps, probs):
         with make(w, inp, stream) as alone:
             alone.sweep(1)
@@ -213,3 +219,21 @@ def test_benchmark_batch_full_size(stream):
             with make(mw, mi, stream) as alone:
                 alone.sweep(1)
                 np.testing.assert_array_equal(got[j], alone.get_offsets(), err_msg=f"member {j} vs solo")
+
+
+def test_batch_of_solo_members_only(stream):
+    """A batch whose members all sweep on their own (BF16 form, Gaussian rows,
+    swap moves): no grouped launches at all; one sweep, then a graph-replayed
+    pair plus one more, each member equal to its own sweeps alone."""
+    ws = [MIXED[1], MIXED[2], MIXED[3], MIXED[4]]
+    inps = [synthgen.problem_inputs(w) for w in ws]
+    batched = [make_any(w, inp, stream) for w, inp in zip(ws, inps)]
+    with bnlat.Batch(batched) as b:
+        b.sweep(1)
+        b.sweep(3)
+    for w, inp, p in zip(ws, inps, batched):
+        with make_any(w, inp, stream) as alone:
+            alone.sweep(4)
+            np.testing.assert_array_equal(p.get_offsets(), alone.get_offsets())
+            assert p.get_sweep_index() == 4
+        p.close()
