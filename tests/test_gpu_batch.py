@@ -237,3 +237,31 @@ def test_batch_of_solo_members_only(stream):
             np.testing.assert_array_equal(p.get_offsets(), alone.get_offsets())
             assert p.get_sweep_index() == 4
         p.close()
+
+
+@pytest.mark.parametrize("k_col,shape", [(1, 0), (1, 1), (4, 0), (4, 1)])
+def test_batched_colour_moduli_and_stage_shapes(stream, tmp_path, k_col, shape):
+    """Colour moduli 1 and 4 with either stage block shape (forced through the
+    tune cache), over a pair graph and an odd sweep: every member equals the
+    oracle's trajectory."""
+    ws = [workload(n=16, g=(1, 7), width=16, height=16, t_heaviside=40, colour_k=k_col, problem_id=20),
+          workload(n=256, g=(1, 79), width=16, height=8, t_heaviside=70, radius=2, colour_k=k_col,
+                   problem_id=21),
+          workload(n=4, g=(1, 3), width=32, height=16, t_heaviside=30, radius=3, colour_k=k_col, problem_id=22)]
+    inps = [synthgen.problem_inputs(w) for w in ws]
+    probs = [make(w, inp, stream) for w, inp in zip(ws, inps)]
+    probe = str(tmp_path / "probe.txt")
+    with bnlat.Batch(probs, tune_cache=probe):
+        pass
+    key = open(probe).read().split()[0]
+    forced = str(tmp_path / "forced.txt")
+    with open(forced, "w") as f:
+        f.write(f"{key} tch=128 slices=256 shape={shape}\n")
+    with bnlat.Batch(probs, tune_cache=forced) as b:
+        assert b.tuning()["stage_shape"] == shape
+        b.sweep(3)
+    for w, inp, p in zip(ws, inps, probs):
+        ref = oracle_problem(w, inp)
+        st = osw.run(ref, osw.initial_state(ref, inp["offsets"]), 3)
+        np.testing.assert_array_equal(p.get_offsets(), st.u)
+        p.close()
