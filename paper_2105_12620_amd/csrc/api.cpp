@@ -661,7 +661,7 @@ bn_status setup_swap(bn_problem p) {
   bn_status s;
   if ((s = p->alloc(&perm_d, P)) != BN_OK || (s = p->alloc(&pinv_d, P)) != BN_OK ||
       (s = p->alloc(&dcls_d, dmax + 1)) != BN_OK || (s = p->alloc(&sv.xs, (size_t)p->v.ncls * M)) != BN_OK ||
-      (s = p->alloc(&sv.d2, M / 2)) != BN_OK)
+      (s = p->alloc(&sv.d2, M / 2)) != BN_OK || (s = p->alloc(&sv.row, (size_t)P * p->v.tp)) != BN_OK)
     return s;
   sv.perm = perm_d;
   sv.pinv = pinv_d;
@@ -1349,6 +1349,7 @@ bn_status bn_compute_errors(bn_problem p) {
   if (!p) return fail(BN_EINVAL, "NULL problem");
   if (!p->have_offsets) return fail(BN_ESTATE, "offsets are not initialised");
   HIPCHK(launch_count(p->v, MODE_ALL, 0, p->v.w * p->v.h, p->stream));
+  if (p->cfg.move == BN_SWAP) HIPCHK(launch_swap_rows(p->v, p->sv, p->stream));
   HIPCHK(launch_gauss_est(p->v, MODE_ALL, p->v.w * p->v.h, p->stream));
   HIPCHK(launch_gauss_errors(p->v, p->stream));
   HIPCHK(launch_bf_field(p->v, p->stream));

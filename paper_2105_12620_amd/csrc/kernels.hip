@@ -281,14 +281,19 @@ __device__ __forceinline__ void delta_stage_body(const DevView& v, uint32_t kapp
   }
 }
 
+// One-dimensional grid of gx x gy blocks x slices, renumbered per XCD: the
+// blocks one L2 serves at a time are whole rows of blocks of one slice, whose
+// window halos are then read from HBM once.
 template <int R, int K, int BY, int V>
 __global__ __launch_bounds__(32 * BY) void k_delta_stage(DevView v, uint32_t kappa, uint32_t trlen,
-                                                         long long* __restrict__ xpart) {
+                                                         long long* __restrict__ xpart, uint32_t gx,
+                                                         uint32_t gy) {
   // the colour phases' waves issue ahead of the sweep-wide recount running
   // beside them (k_delta_finish, k_commit and the BF16 form's k_delta_bf
   // and k_delta_refine likewise), which fills the remaining issue slots
   __builtin_amdgcn_s_setprio(2);
-  delta_stage_body<R, K, BY, V>(v, kappa, trlen, xpart, blockIdx.x, blockIdx.y, blockIdx.z);
+  const uint32_t wk = xcd_block(blockIdx.x, gridDim.x), bxy = wk % (gx * gy);
+  delta_stage_body<R, K, BY, V>(v, kappa, trlen, xpart, bxy % gx, bxy / gx, wk / (gx * gy));
 }
 
 // Batched form: member i owns blocks pre[i] .. pre[i+1]-1, laid out as its own
@@ -860,9 +865,9 @@ hipError_t stage_launch(const DevView& v, uint32_t kappa, long long* xpart, hipS
   // slices of at least 64 integrands: each adds its class sums with atomics
   // and restages the window halo
   const uint32_t ns = stage_slices(v, blocks, &trlen, 8, stage_max_slice(v.n), 64);
-  const dim3 grid((v.cw + G::BX - 1) / G::BX, (v.ch + G::CR - 1) / G::CR, ns);
-  hipLaunchKernelGGL((k_delta_stage<R, K, S::BY, S::V>), grid, dim3(G::NT), (size_t)G::LDS_BYTES, s, v, kappa,
-                     trlen, xpart);
+  const uint32_t gx = (v.cw + G::BX - 1) / G::BX, gy = (v.ch + G::CR - 1) / G::CR;
+  hipLaunchKernelGGL((k_delta_stage<R, K, S::BY, S::V>), dim3(gx * gy * ns), dim3(G::NT), (size_t)G::LDS_BYTES, s,
+                     v, kappa, trlen, xpart, gx, gy);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !finish) return e;
   return launch_finish(v, s);

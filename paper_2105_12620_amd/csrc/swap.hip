@@ -15,6 +15,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bnlat_dev.h"
 #include "device_common.h"
@@ -29,62 +30,117 @@ __device__ inline uint32_t swap_mask(const DevView& v, uint32_t kappa) {
   return philox_w01(kappa, sweep, v.problem, S_SWAP, v.seed_lo, v.seed_hi).x & (v.w * v.h - 1);
 }
 
-// LDS-staged member evaluation.  A workgroup owns a 32 x 6 block of tile
+// LDS-staged member evaluation.  A workgroup owns a BW x BH block of tile
 // pixels; its pass members (pixels whose scrambled list position falls in the
-// pass) are listed in LDS.  For 64 integrands at a time the counts of the
-// block plus its window halo are staged in LDS (region RH x RW), and every
-// member is served by a group of 16 lanes, lane k holding integrands
-// 4k .. 4k+3 of dc = c_partner - c_own (partner counts read from HBM, own
-// counts from LDS).  Per window offset a group reads the neighbour's 32 words
-// with one ds_read_b64 per lane and takes two v_dot2 per lane.
+// pass) are listed in LDS.  For 16 integrands at a time (two 8-integrand count
+// planes, one stage) the counts of the block plus its window halo (region
+// RH x RW, row pitch RWP = RW + 1) and the two partner words of every member
+// are staged in LDS, and every member is served by a group of 16 lanes: lane
+// (i, p) forms dc = c_partner - c_own of plane p and, per step, reads one
+// 16-byte word of plane p at window offset i of the step.  A row step covers
+// eight consecutive offsets of a window row, a column step eight consecutive
+// rows of one of the columns the row steps leave over.  gfx950's LDS serves a
+// ds_read_b128 in passes of 16 lanes over 64 four-byte banks: with the plane
+// stride 8 words of 16 bytes past a multiple of 16 and RWP odd, the 16 words
+// a group reads fall in 16 distinct bank quads wherever the member lies, so
+// every pass is conflict-free.
 //
-// Staging goes straight from HBM to LDS (global_load_lds_dwordx4: lane l of a
-// load writes 16 bytes at the wave's LDS base + 16 l).  LDS holds eight planes
-// (one per 8-integrand tile) of RA_PAD pixels x 4 words; the plane stride is 4
-// words past a multiple of 32, so the 32 words a group reads for one
-// neighbour fall in 32 distinct banks.
+// Staging is a ring of three stage buffers filled straight from HBM by
+// global_load_lds_dwordx4 (lane l of a load writes 16 bytes at the wave's LDS
+// base + 16 l): the loads of stage s + 2 are issued while stage s is
+// evaluated.  Every wave issues the same number D of loads per stage (slots
+// past the stage's loads repeat one of them), so waiting for stage s is
+// s_waitcnt vmcnt(D) while stage s + 1 is in flight (loads return in order),
+// followed by a barrier without a memory fence (a fence would wait for every
+// load in flight).  A stage buffer is refilled only after the barrier that
+// follows the last reads of it.
 //
-// Integrand slices of the tile run in separate workgroups (grid z) and meet
-// in exact int64 atomics; per-lane int32 partial sums stay below 2^31 because
-// the host bounds a slice to S stages with S * 48 N^2 < 2^31 (at most 12
-// offsets per distance class, 4 integrands per lane per stage).
+// A lane accumulates its product of each step separately (int32 per step);
+// when the member's integrand slice is done, the steps' sums are gathered
+// into distance classes (the lane's offset of a step fixes the class),
+// reduced over the group and added to HBM with exact int64 atomics, member
+// by member in a contiguous row of classes.  The workgroups are renumbered
+// per XCD (xcd_block), so that the blocks one L2 serves at a time are whole
+// rows of blocks of one integrand slice and their halos are read from HBM
+// once.
+//
+// Integrand slices of the tile run in separate workgroups; per-lane int32
+// step sums stay below 2^31 because the host bounds a slice to S stages with
+// S * 8 N^2 < 2^31 (eight products of at most N^2 per lane and stage).
 
 template <int R>
 struct SwapGeom {
-  static constexpr int BW = 32, BH = 6;          // tile pixels per workgroup
+  static constexpr int BW = 32, BH = (R <= 4) ? 8 : 4;   // tile pixels per workgroup
+  static constexpr int WS = 2 * R + 1;                   // window side
   static constexpr int RW = BW + 2 * R, RH = BH + 2 * R;
-  static constexpr int RA = RW * RH;             // region pixels
-  static constexpr int RA_PAD = (RA + 63) / 64 * 64;
-  static constexpr int PLANE = RA_PAD * 4 + 4;   // words per 8-integrand plane
-  static constexpr int NPLANE = 8;               // 8-integrand tiles per stage (64 integrands)
-  static constexpr int BUF = NPLANE * PLANE;     // words of the stage buffer
-  static constexpr int GL = 16;                  // lanes per member group
-  static constexpr int NT = 512;                 // threads
+  static constexpr int RWP = RW + 1;                     // odd row pitch (16-byte words)
+  static constexpr int RA = RH * RWP;                    // words of one plane's region
+  static constexpr int RA_PAD = (RA + 63) / 64 * 64;     // whole 64-lane loads
+  static constexpr int PLANE = RA_PAD + 8;               // plane stride: 8 past a multiple of 16
+  static constexpr int NT = 512;                         // threads
   static constexpr int NWAVE = NT / 64;
-  static constexpr int LOADS = NPLANE * RA_PAD / 64;   // 64-lane 16-byte loads per stage
-  static constexpr int GROUPS = NT / GL;         // 32 member groups
-  static constexpr int SLOTS = 2;                // members per group and round
-  static constexpr int CAP = GROUPS * SLOTS;     // members per round
+  static constexpr int GL = 16;                          // lanes per member group
+  static constexpr int GROUPS = NT / GL;
+  static constexpr int SLOTS = (R <= 4) ? 3 : 2;         // members per group and round
+  static constexpr int CAP = GROUPS * SLOTS;             // members per round
+  static constexpr int PART = 2 * CAP;                   // partner words per stage
+  static constexpr int SBUF = 2 * PLANE + PART;          // words of one stage buffer
+  static constexpr int NBUF = 3;                         // ring depth
+  static constexpr int NRL = 2 * RA_PAD / 64;            // region loads per stage
+  static constexpr int NLD = NRL + PART / 64;            // loads per stage
+  static constexpr int D = (NLD + NWAVE - 1) / NWAVE;    // loads per wave and stage
+  static constexpr int RC = WS < 8 ? WS : 8;             // offsets of a row step
+  static constexpr int LC = WS - RC;                     // columns left to column steps
+  static constexpr int CH = (WS + 7) / 8;                // column steps per such column
+  static constexpr int LASTROWS = WS - 8 * (CH - 1);     // rows of a column's last step
+  static constexpr int STEPS = WS + LC * CH;
   static constexpr int NPIX = BW * BH;
-  static constexpr int NWV = (NPIX + 63) / 64;   // waves that test membership
-  static constexpr int LDS_WORDS = BUF + 3 * NPIX + NWV;
+  static constexpr int NWV = NPIX / 64;                  // waves that test membership
+  static constexpr int LDS_BYTES = NBUF * SBUF * 16 + (3 * NPIX + NWV + 8 * STEPS) * 4;
+  static_assert(NPIX % 64 == 0 && RWP % 2 == 1 && PLANE % 16 == 8 && PART % 64 == 0, "swap block geometry");
+  static_assert(D * NWAVE < 2 * NLD, "repeated load slots");
 };
+
+// Window offset of lane slot i at step st (row steps first, then column
+// steps), and whether the slot holds one.
+template <int R>
+__device__ inline bool swap_step_offset(int st, int i, int& ox, int& oy) {
+  using G = SwapGeom<R>;
+  if (st < G::WS) {
+    oy = st - R;
+    ox = -R + i;
+    return i < G::RC;
+  }
+  const int t = st - G::WS, col = t / G::CH, part = t % G::CH;
+  ox = -R + G::RC + col;
+  oy = -R + 8 * part + i;
+  return oy <= R;
+}
+
+// s_waitcnt with vmcnt(n) and lgkmcnt(0), expcnt left open (gfx9 encoding)
+template <int N>
+__device__ inline void wait_vm_lgkm0() {
+  static_assert(N < 64, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
 
 template <int R>
 __global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v, SwapView sv, uint32_t kappa,
-                                                                    uint32_t slen) {
+                                                                    uint32_t slen, uint32_t gx, uint32_t gy) {
   using G = SwapGeom<R>;
-  constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
-  extern __shared__ uint32_t lds[];
-  uint32_t* mpos = lds + G::BUF;                   // [NPIX] region pixel of each member
+  extern __shared__ u32x4 lds4[];
+  uint32_t* mpos = (uint32_t*)(lds4 + G::NBUF * G::SBUF);   // [NPIX] region word of each member
   uint32_t* mj = mpos + G::NPIX;                   // [NPIX] list slot
   uint32_t* mb = mj + G::NPIX;                     // [NPIX] partner pixel
   uint32_t* wcnt = mb + G::NPIX;                   // [NWV] members per wave
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int* ctab = (int*)(wcnt + G::NWV);               // [STEPS][8] class of each step's slot (-1: none)
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t P = v.w * v.h;
   const uint32_t mask = swap_mask(v, kappa);
-  const uint32_t x0 = blockIdx.x * G::BW, y0 = blockIdx.y * G::BH;
+  const uint32_t wk = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t bxy = wk % (gx * gy), bz = wk / (gx * gy);
+  const uint32_t x0 = (bxy % gx) * G::BW, y0 = (bxy / gx) * G::BH;
 
   // members of the block, in raster order
   bool in = false;
@@ -96,11 +152,15 @@ __global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v,
       in = L / sv.m == kappa;
       j = L - kappa * sv.m;
       b = sv.perm[L ^ 1u] ^ mask;
-      pos = (ly + R) * G::RW + lx + R;
+      pos = (ly + R) * G::RWP + lx + R;
     }
   }
   const unsigned long long bal = __ballot(in);
   if (lane == 0 && wv < (uint32_t)G::NWV) wcnt[wv] = (uint32_t)__popcll(bal);
+  if (tid < 8u * G::STEPS) {
+    int ox, oy;
+    ctab[tid] = swap_step_offset<R>((int)tid / 8, (int)tid % 8, ox, oy) ? sv.dcls[ox * ox + oy * oy] : -1;
+  }
   __syncthreads();
   uint32_t before = 0, nm = 0;
 #pragma unroll
@@ -115,142 +175,218 @@ __global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v,
     mb[idx] = b;
   }
 
-  // region pixel -> tile pixel (W and H are powers of two for swap problems)
+  // load slot k of this wave issues load d = wv + NWAVE k of a stage (slots
+  // past the stage's loads repeat load d - NLD).  Region load d < NRL covers
+  // plane d / (RA_PAD / 64), region words 64 (d mod RA_PAD/64) + lane (the
+  // padding column and words past the region load pixel 0); partner load d
+  // covers partner words 64 (d - NRL) + lane = 2 m + plane of round member m,
+  // read from the pixel-major copy (lsrc holds the partner pixel and plane).
+  // W and H are powers of two.
   const uint32_t ys = (y0 + v.h * (R / v.h + 1) - R) % v.h;
   const uint32_t xs = (x0 + v.w * (R / v.w + 1) - R) % v.w;
   const uint32_t wm = v.w - 1, hm = v.h - 1;
-  // the stage at t0: load n covers plane n / (RA_PAD / 64), region pixels
-  // 64 (n mod RA_PAD/64) + lane (padding lanes reload pixel 0)
-  auto issue_stage = [&](uint32_t t0) {
-    for (uint32_t n = wv; n < (uint32_t)G::LOADS; n += G::NWAVE) {
-      const uint32_t plane = n / (G::RA_PAD / 64), pix0 = (n % (G::RA_PAD / 64)) * 64;
-      const uint32_t pix = pix0 + lane;
-      uint32_t gq = 0;
-      if (pix < (uint32_t)G::RA) {
-        const uint32_t rr = pix / G::RW, cc = pix - rr * G::RW;
-        gq = ((ys + rr) & hm) * v.w + ((xs + cc) & wm);
-      }
-      const uint16_t* src = v.cnt + tix(gq, t0 + 8 * plane, P);
-      uint32_t* dst = lds + plane * G::PLANE + 4 * pix0;
+  uint32_t ldst[G::D], lsrc[G::D];
+#pragma unroll
+  for (int k = 0; k < G::D; ++k) {
+    uint32_t d = wv + G::NWAVE * k;
+    if (d >= (uint32_t)G::NLD) d -= G::NLD;
+    if (d < (uint32_t)G::NRL) {
+      const uint32_t pl = d / (G::RA_PAD / 64), u0 = (d % (G::RA_PAD / 64)) * 64, u = u0 + lane;
+      const uint32_t rr = u / G::RWP, cc = u - rr * G::RWP;
+      const uint32_t gq = (u < (uint32_t)G::RA && cc < (uint32_t)G::RW) ? ((ys + rr) & hm) * v.w + ((xs + cc) & wm) : 0;
+      ldst[k] = pl * G::PLANE + u0;
+      lsrc[k] = pl * P + gq;
+    } else {
+      ldst[k] = 2 * G::PLANE + 64 * (d - G::NRL);
+      lsrc[k] = 0;
+    }
+  }
+  const uint32_t tp8 = v.tp >> 3;
+  auto issue = [&](uint32_t t0, uint32_t buf) {
+    const u32x4* cs = (const u32x4*)(v.cnt + (size_t)(t0 >> 3) * P * 8);
+    const u32x4* rs = (const u32x4*)sv.row + (t0 >> 3);
+#pragma unroll
+    for (int k = 0; k < G::D; ++k) {
+      const u32x4* src = ldst[k] < 2u * G::PLANE ? cs + lsrc[k] : rs + (size_t)(lsrc[k] >> 1) * tp8 + (lsrc[k] & 1);
       __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
-                                       (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+                                       (__attribute__((address_space(3))) void*)(lds4 + buf * G::SBUF + ldst[k]),
+                                       16, 0, 0);
     }
   };
+  // wait until at most N of this wave's loads are in flight and its LDS
+  // accesses are done, then meet the other waves; the empty asm statements
+  // keep the compiler from moving memory accesses across
+  auto sync_vm = [&](auto n) {
+    asm volatile("" ::: "memory");
+    wait_vm_lgkm0<decltype(n)::value>();
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
 
-  const uint32_t grp = tid / G::GL, k = tid % G::GL;
-  const uint32_t lane_word = (k >> 1) * G::PLANE + 2 * (k & 1);
-  const uint32_t t_begin = blockIdx.z * slen, t_end = min(t_begin + slen, v.tp);
+  const uint32_t grp = tid / G::GL, li = tid & 7, lp = (tid >> 3) & 1;
+  // word of the lane's slot relative to the member's own word of plane lp:
+  // row steps, column steps, a column's last step (lanes past the window
+  // repeat its last offset)
+  const uint32_t lr = min(li, (uint32_t)G::RC - 1), lc = li * G::RWP,
+                 lcl = min(li, (uint32_t)G::LASTROWS - 1) * G::RWP;
+  const uint32_t t_begin = bz * slen, t_end = min(t_begin + slen, v.tp);
+  const uint32_t nst = t_end > t_begin ? (t_end - t_begin) / 16 : 0;
   __syncthreads();
   for (uint32_t base = 0; base < nm; base += G::CAP) {
-    int acc[G::SLOTS][NCLS];
+    // this round's partner pixels
+#pragma unroll
+    for (int k = 0; k < G::D; ++k) {
+      if (ldst[k] >= 2u * G::PLANE) {
+        const uint32_t e = ldst[k] - 2 * G::PLANE + lane, m = base + (e >> 1);
+        lsrc[k] = (m < nm ? mb[m] : 0) * 2 + (e & 1);
+      }
+    }
+    int acc[G::SLOTS][G::STEPS];
     int dd[G::SLOTS];
-    uint32_t spos[G::SLOTS], sb[G::SLOTS];
+    // per slot: the member's own word of plane lp, its partner word, and the
+    // bases of the row steps, the column steps and a column's last step,
+    // shifted so that every step reads at a non-negative constant offset
+    uint32_t sp[G::SLOTS], pe[G::SLOTS], rb[G::SLOTS], cb[G::SLOTS], cbl[G::SLOTS];
     bool ok[G::SLOTS];
 #pragma unroll
     for (int s = 0; s < G::SLOTS; ++s) {
-      const uint32_t mi = base + grp * G::SLOTS + s;
-      ok[s] = mi < nm;
-      spos[s] = ok[s] ? mpos[mi] : 0;
-      sb[s] = ok[s] ? mb[mi] : 0;
+      const uint32_t mi = grp + G::GROUPS * s;
+      ok[s] = base + mi < nm;
+      sp[s] = lp * G::PLANE + (ok[s] ? mpos[base + mi] : (uint32_t)(R * G::RWP + R));
+      pe[s] = 2 * G::PLANE + 2 * mi + lp;
+      rb[s] = sp[s] + lr - (R * G::RWP + R);
+      cb[s] = sp[s] + lc - (R * G::RWP + R - G::RC);
+      cbl[s] = sp[s] + lcl - (R * G::RWP + R - G::RC);
       dd[s] = 0;
 #pragma unroll
-      for (int c = 0; c < NCLS; ++c) acc[s][c] = 0;
+      for (int st = 0; st < G::STEPS; ++st) acc[s][st] = 0;
     }
-    for (uint32_t t0 = t_begin; t0 < t_end; t0 += 64) {
-      // partner counts: integrands t0 + 4k .. +3 (one 8-byte piece of a tile)
-      uint2 pw[G::SLOTS];
-#pragma unroll
-      for (int s = 0; s < G::SLOTS; ++s) pw[s] = *(const uint2*)(v.cnt + tix(sb[s], t0 + 4 * k, P));
-      __syncthreads();
-      issue_stage(t0);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      const uint32_t* reg = lds + lane_word;
+    // the previous round's reads of the ring are done
+    sync_vm(std::integral_constant<int, 0>{});
+    if (nst > 0) issue(t_begin, 0);
+    if (nst > 1) issue(t_begin + 16, 1);
+    for (uint32_t si = 0; si < nst; ++si) {
+      if (si + 1 < nst) sync_vm(std::integral_constant<int, G::D>{});
+      else sync_vm(std::integral_constant<int, 0>{});
+      if (si + 2 < nst) issue(t_begin + 16 * (si + 2), (si + 2) % G::NBUF);
+      const u32x4* bf = lds4 + (si % G::NBUF) * G::SBUF;
 #pragma unroll
       for (int s = 0; s < G::SLOTS; ++s) {
         if (ok[s]) {
-          const uint32_t* rp = reg + 4 * spos[s];
-          const uint2 own = *(const uint2*)rp;
-          const uint32_t pws[2] = {pw[s].x, pw[s].y}, ows[2] = {own.x, own.y};
-          uint32_t dl[2];
+          const u32x4 own = bf[sp[s]], pc = bf[pe[s]];
+          uint32_t dl[4];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int d0 = (int)(pws[h] & 0xFFFFu) - (int)(ows[h] & 0xFFFFu);
-            const int d1 = (int)(pws[h] >> 16) - (int)(ows[h] >> 16);
-            dl[h] = ((uint32_t)d0 & 0xFFFFu) | ((uint32_t)d1 << 16);
+          for (int h = 0; h < 4; ++h) {
+            // per int16 half: partner minus own count (|dc| <= N, no wrap); the
+            // words go through scalars (a bit cast straight from the vector
+            // element read only the first word)
+            const uint32_t pw_h = pc[h], ow_h = own[h];
+            dl[h] = __builtin_bit_cast(uint32_t, (v2i16)(__builtin_bit_cast(v2i16, pw_h) -
+                                                         __builtin_bit_cast(v2i16, ow_h)));
             dd[s] = dot2(dl[h], dl[h], dd[s]);
           }
+          const u32x4* rp = bf + rb[s];
+          const u32x4* cp = bf + cb[s];
+          const u32x4* clp = bf + cbl[s];
 #pragma unroll
-          for (int mm = 0; mm < W.M; ++mm) {
-            const int disp = 4 * (W.oy[mm] * G::RW + W.ox[mm]);
-            const uint2 c = *(const uint2*)(rp + disp);
-            int a = acc[s][W.cls[mm]];
-            a = dot2(dl[0], c.x, a);
-            a = dot2(dl[1], c.y, a);
-            acc[s][W.cls[mm]] = a;
+          for (int st = 0; st < G::STEPS; ++st) {
+            u32x4 c;
+            if (st < G::WS) {
+              c = rp[st * G::RWP];
+            } else {
+              const int t = st - G::WS, col = t / G::CH, part = t % G::CH;
+              c = (part < G::CH - 1 ? cp : clp)[col + 8 * part * G::RWP];
+            }
+            int a = acc[s][st];
+            a = dot2(dl[0], c[0], a);
+            a = dot2(dl[1], c[1], a);
+            a = dot2(dl[2], c[2], a);
+            acc[s][st] = dot2(dl[3], c[3], a);
           }
         }
       }
     }
-    // all reads of the buffers are done before a next round stages again
-    __syncthreads();
-    // members' class sums: reduce over the group's 16 lanes, add to HBM
+    // gather each member's step sums into classes, reduce over the group's
+    // 16 lanes and add them to HBM
 #pragma unroll
     for (int s = 0; s < G::SLOTS; ++s) {
-      if (!ok[s]) break;   // slots fill in order
-      const uint32_t js = mj[base + grp * G::SLOTS + s];
+      if (!ok[s]) continue;
+      long long cl[NCLS];
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) cl[c] = 0;
+#pragma unroll
+      for (int st = 0; st < G::STEPS; ++st) {
+        const int c = ctab[st * 8 + li];
+#pragma unroll
+        for (int cc = 0; cc < NCLS; ++cc) cl[cc] += (c == cc) ? (long long)acc[s][st] : 0ll;
+      }
 #pragma unroll
       for (int c = 0; c < NCLS; ++c) {
-        long long x = acc[s][c];
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) x += __shfl_xor(x, off);
-        if (k == 0 && x) atomicAdd((unsigned long long*)&sv.xs[(size_t)c * sv.m + js], (unsigned long long)(-2 * x));
+        for (int off = 1; off < G::GL; off <<= 1) cl[c] += __shfl_xor(cl[c], off);
       }
-      long long d = dd[s];
+      // dc^2 of plane lp is the same in the group's eight slots
+      long long d = li == 0 ? (long long)dd[s] : 0ll;
 #pragma unroll
-      for (int off = 8; off > 0; off >>= 1) d += __shfl_xor(d, off);
-      if (k == 0 && !(js & 1u) && d) atomicAdd((unsigned long long*)&sv.d2[js >> 1], (unsigned long long)d);
+      for (int off = 1; off < G::GL; off <<= 1) d += __shfl_xor(d, off);
+      const uint32_t js = mj[base + grp + G::GROUPS * s];
+      const uint32_t l16 = tid & 15;
+#pragma unroll
+      for (int c0 = 0; c0 < NCLS; c0 += G::GL) {
+        const uint32_t c = c0 + l16;
+        long long x = 0;
+#pragma unroll
+        for (int cc = c0; cc < c0 + G::GL && cc < NCLS; ++cc) x = (c == (uint32_t)cc) ? cl[cc] : x;
+        if (c < (uint32_t)NCLS && x)
+          atomicAdd((unsigned long long*)&sv.xs[(size_t)js * NCLS + c], (unsigned long long)(-2 * x));
+      }
+      if (l16 == 0 && !(js & 1u) && d) atomicAdd((unsigned long long*)&sv.d2[js >> 1], (unsigned long long)d);
     }
   }
 }
 
 // One thread per couple: add the two members' class sums and the pair
 // correction, take the FP64 weighted sum in increasing d and decide; the sums
-// are cleared for the next pass.
-__global__ __launch_bounds__(256) void k_swap_finish(DevView v, SwapView sv, uint32_t kappa) {
+// are cleared for the next pass.  All of a couple's sums are loaded before
+// any is cleared, so the loads are in flight together.
+template <int R>
+__global__ __launch_bounds__(128) void k_swap_finish(DevView v, SwapView sv, uint32_t kappa) {
+  constexpr int NCLS = WinConst<R>::NCLS;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t half = sv.m >> 1;
   if (i >= half) return;
   const uint32_t mask = swap_mask(v, kappa);
   const uint32_t L = kappa * sv.m + 2 * i;
   const uint32_t a = sv.perm[L] ^ mask, b = sv.perm[L + 1] ^ mask;
-  const uint32_t ay = a / v.w, ax = a - ay * v.w, by = b / v.w, bx = b - by * v.w;
-  // offsets o with a + o = b: at most two per axis because r < min(W, H)
-  int l0 = -1, l1 = -1, l2 = -1, l3 = -1;
-  const int r = (int)v.radius;
-  for (int oy = -r; oy <= r; ++oy) {
-    if ((ay + v.h + oy) % v.h != by) continue;
-    for (int ox = -r; ox <= r; ++ox) {
-      if ((ox == 0 && oy == 0) || (ax + v.w + ox) % v.w != bx) continue;
+  long long* xp = sv.xs + (size_t)2 * i * NCLS;
+  long long x[NCLS];
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) x[c] = xp[c] + xp[NCLS + c];
+  const long long d2 = sv.d2[i];
+  // the rows of the two members: 2 NCLS int64, 16-byte aligned
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) ((uint4*)xp)[c] = make_uint4(0u, 0u, 0u, 0u);
+  sv.d2[i] = 0;
+  // offsets o with a + o = b on the torus: o = d or d - W per axis with
+  // d = (b - a) mod W (two per axis at most because r < min(W, H)); W and H
+  // are powers of two
+  const uint32_t lw = __builtin_ctz(v.w), wm = v.w - 1, hm = v.h - 1;
+  const int dx = (int)(((b & wm) - (a & wm)) & wm), dy = (int)(((b >> lw) - (a >> lw)) & hm);
+  const int cx[2] = {dx, dx - (int)v.w}, cy[2] = {dy, dy - (int)v.h};
+#pragma unroll
+  for (int ky = 0; ky < 2; ++ky) {
+#pragma unroll
+    for (int kx = 0; kx < 2; ++kx) {
+      const int ox = cx[kx], oy = cy[ky];
+      if (ox < -R || ox > R || oy < -R || oy > R || (ox == 0 && oy == 0)) continue;
       const int cl = sv.dcls[ox * ox + oy * oy];
-      if (l0 < 0) l0 = cl;
-      else if (l1 < 0) l1 = cl;
-      else if (l2 < 0) l2 = cl;
-      else l3 = cl;
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) x[c] += (c == cl) ? 2 * d2 : 0ll;
     }
   }
-  const long long d2 = sv.d2[i];
-  sv.d2[i] = 0;
   double acc = 0.0;
-  for (uint32_t c = 0; c < v.ncls; ++c) {
-    const int ci = (int)c;
-    long long* xp = sv.xs + (size_t)c * sv.m + 2 * i;
-    long long x = xp[0] + xp[1];
-    xp[0] = 0;
-    xp[1] = 0;
-    x += 2 * d2 * (long long)((l0 == ci) + (l1 == ci) + (l2 == ci) + (l3 == ci));
-    acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)x));
-  }
+#pragma unroll
+  for (int c = 0; c < NCLS; ++c) acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)x[c]));
   const double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
   v.delta[i] = total;
   v.accept[i] = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
@@ -277,7 +413,21 @@ __global__ __launch_bounds__(256) void k_swap_commit(DevView v, SwapView sv) {
     const uint4 qa = *ra, qb = *rb;
     *ra = qb;
     *rb = qa;
+    uint4* wa = (uint4*)(sv.row + (size_t)a * v.tp) + tt;
+    uint4* wb = (uint4*)(sv.row + (size_t)b * v.tp) + tt;
+    *wa = qb;
+    *wb = qa;
   }
+}
+
+// Pixel-major copy of the tiled counts: thread per (pixel, 8-integrand tile),
+// pixels fastest, so that the tiled reads are coalesced.
+__global__ __launch_bounds__(256) void k_swap_rows(DevView v, SwapView sv) {
+  const uint32_t P = v.w * v.h;
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (uint64_t)P * (v.tp >> 3)) return;
+  const uint32_t tt = (uint32_t)(i / P), p = (uint32_t)(i - (uint64_t)tt * P);
+  *((uint4*)(sv.row + (size_t)p * v.tp) + tt) = *(const uint4*)(v.cnt + ((size_t)tt * P + p) * 8);
 }
 
 }  // namespace
@@ -290,7 +440,7 @@ hipError_t prepare_swap_kernels() {
 #define BN_SWAP_ATTR(RR)                                                                               \
   if (e == hipSuccess)                                                                                 \
     e = hipFuncSetAttribute((const void*)k_swap_stage<RR>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                            (int)(SwapGeom<RR>::LDS_WORDS * 4));
+                            (int)SwapGeom<RR>::LDS_BYTES);
     BN_SWAP_ATTR(1)
     BN_SWAP_ATTR(2)
     BN_SWAP_ATTR(3)
@@ -303,37 +453,44 @@ hipError_t prepare_swap_kernels() {
   return status;
 }
 
-// Integrand slices: enough workgroups to fill the device, and few enough
-// stages per slice that every per-lane int32 partial sum stays below 2^31.
-hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
-  const uint32_t gx = (v.w + 31) / 32, gy = (v.h + 5) / 6, chunks = v.tp / 64;
+// Integrand slices: enough workgroups to fill the device twice over, and few
+// enough stages per slice that every per-lane int32 step sum stays below 2^31.
+template <int R>
+hipError_t swap_stage_launch(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
+  using G = SwapGeom<R>;
+  const uint32_t gx = (v.w + G::BW - 1) / G::BW, gy = (v.h + G::BH - 1) / G::BH, chunks = v.tp / 16;
   const double n2 = (double)v.n * v.n;
-  const uint32_t smax = (uint32_t)std::max(1.0, std::floor(2147483647.0 / (48.0 * n2)));
-  uint32_t nz = std::max<uint32_t>(1, std::min<uint32_t>(chunks, (1024 + gx * gy - 1) / (gx * gy)));
+  const uint32_t smax = (uint32_t)std::max(1.0, std::floor(2147483647.0 / (8.0 * n2)));
+  uint32_t nz = std::max<uint32_t>(1, std::min<uint32_t>(chunks, (512 + gx * gy - 1) / (gx * gy)));
   uint32_t per = (chunks + nz - 1) / nz;
   if (per > smax) per = smax;
   nz = (chunks + per - 1) / per;
-  const uint32_t slen = per * 64;
-  const dim3 grid(gx, gy, nz), block(512);
-  switch (v.radius) {
-#define BN_SWAP_STAGE(RR)                                                                           \
-  case RR:                                                                                          \
-    hipLaunchKernelGGL(k_swap_stage<RR>, grid, block, (size_t)SwapGeom<RR>::LDS_WORDS * 4, s, v, sv, \
-                       kappa, slen);                                                                \
-    break;
-    BN_SWAP_STAGE(1)
-    BN_SWAP_STAGE(2)
-    BN_SWAP_STAGE(3)
-    BN_SWAP_STAGE(4)
-    BN_SWAP_STAGE(5)
-    BN_SWAP_STAGE(6)
-#undef BN_SWAP_STAGE
-    default: return hipErrorInvalidValue;
-  }
+  hipLaunchKernelGGL(k_swap_stage<R>, dim3(gx * gy * nz), dim3(G::NT), (size_t)G::LDS_BYTES, s, v, sv, kappa,
+                     per * 16, gx, gy);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint32_t half = sv.m >> 1;
-  hipLaunchKernelGGL(k_swap_finish, dim3((half + 255) / 256), dim3(256), 0, s, v, sv, kappa);
+  hipLaunchKernelGGL(k_swap_finish<R>, dim3((half + 127) / 128), dim3(128), 0, s, v, sv, kappa);
+  return hipGetLastError();
+}
+
+hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
+  hipError_t e;
+  switch (v.radius) {
+    case 1: e = swap_stage_launch<1>(v, sv, kappa, s); break;
+    case 2: e = swap_stage_launch<2>(v, sv, kappa, s); break;
+    case 3: e = swap_stage_launch<3>(v, sv, kappa, s); break;
+    case 4: e = swap_stage_launch<4>(v, sv, kappa, s); break;
+    case 5: e = swap_stage_launch<5>(v, sv, kappa, s); break;
+    case 6: e = swap_stage_launch<6>(v, sv, kappa, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return e;
+}
+
+hipError_t launch_swap_rows(const DevView& v, const SwapView& sv, hipStream_t s) {
+  const uint64_t n = (uint64_t)v.w * v.h * (v.tp >> 3);
+  hipLaunchKernelGGL(k_swap_rows, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, v, sv);
   return hipGetLastError();
 }
 

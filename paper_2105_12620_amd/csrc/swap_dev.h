@@ -21,6 +21,8 @@ struct SwapView {
   long long* xs;          // [ncls][M] integer class sums of each couple member's move (zero between passes)
   long long* d2;          // [M/2] sum_t (c_a,t - c_b,t)^2 of each couple (zero between passes)
   const int32_t* dcls;    // [2 r^2 + 1] class index of a squared distance (-1: none)
+  uint16_t* row;          // [P][Tp] pixel-major copy of the hit counts: a couple's partner counts
+                          // are read whole lines at a time (kept in step by the exchanges)
   uint32_t m;             // list positions per pass
 };
 
@@ -31,5 +33,7 @@ struct SwapView {
 hipError_t prepare_swap_kernels();
 hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s);
 hipError_t launch_swap_commit(const DevView& v, const SwapView& sv, hipStream_t s);
+// Rebuild the pixel-major copy from the tiled counts (after every recount).
+hipError_t launch_swap_rows(const DevView& v, const SwapView& sv, hipStream_t s);
 
 }  // namespace bnlat
