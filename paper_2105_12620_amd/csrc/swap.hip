@@ -406,17 +406,17 @@ __global__ __launch_bounds__(256) void k_swap_commit(DevView v, SwapView sv) {
     v.U[b] = ua;
     atomicAdd(&v.ctr[1], 1ull);
   }
+  // the counts are read from the pixel-major copy (whole lines), written to
+  // both layouts
   const uint32_t P = v.w * v.h;
+  uint4* wa = (uint4*)(sv.row + (size_t)a * v.tp);
+  uint4* wb = (uint4*)(sv.row + (size_t)b * v.tp);
   for (uint32_t tt = lane; tt < (v.tp >> 3); tt += 64) {
-    uint4* ra = (uint4*)(v.cnt + ((size_t)tt * P + a) * 8);
-    uint4* rb = (uint4*)(v.cnt + ((size_t)tt * P + b) * 8);
-    const uint4 qa = *ra, qb = *rb;
-    *ra = qb;
-    *rb = qa;
-    uint4* wa = (uint4*)(sv.row + (size_t)a * v.tp) + tt;
-    uint4* wb = (uint4*)(sv.row + (size_t)b * v.tp) + tt;
-    *wa = qb;
-    *wb = qa;
+    const uint4 qa = wa[tt], qb = wb[tt];
+    wa[tt] = qb;
+    wb[tt] = qa;
+    *(uint4*)(v.cnt + ((size_t)tt * P + a) * 8) = qb;
+    *(uint4*)(v.cnt + ((size_t)tt * P + b) * 8) = qa;
   }
 }
 
