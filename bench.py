@@ -429,8 +429,11 @@ def main() -> int:
     # evaluation of a phase: the tile's counts once (2 B each) plus the moved
     # pixels' proposal rows, and the decisions
     delta_bytes = 2.0 * T * (P + M) + 9.0 * M
-    # a swap pass reads the tile's counts once
-    swap_bytes = 2.0 * T * P
+    # a swap pass reads the tile's counts once and every member's partner row
+    swap_bytes = 2.0 * T * (P + M)
+    # the stencils' arithmetic: one product per (moved pixel, window offset,
+    # integrand), two per v_dot2 lane-instruction
+    stencil_lane_ops = M * win * T / 2.0
 
     def roof(bound, achieved, unit, kernel, work):
         vendor = {"hbm": HBM_PEAK_GBS, "alu": VALU_PEAK_TOPS, "mfma": MFMA_BF16_PEAK_TFLOPS}[bound]
@@ -461,7 +464,10 @@ def main() -> int:
                            "frac": delta_bytes / (fp32["evaluate_alone_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                            "roofline": roof("hbm", delta_bytes / (fp32["evaluate_alone_ms"] * 1e-3) / 1e9,
                                             "GB/s", "k_delta_stage + k_delta_finish (one colour phase, alone)",
-                                            f"tile counts once + {M} proposal rows, 2 B per integrand")},
+                                            f"tile counts once + {M} proposal rows, 2 B per integrand"),
+                           "roofline_alu": roof("alu", stencil_lane_ops / (fp32["evaluate_alone_ms"] * 1e-3) / 1e12,
+                                                "TOP/s", "k_delta_stage + k_delta_finish (one colour phase, alone)",
+                                                f"{M} pixels x {win} offsets x {T} integrands / 2 per v_dot2")},
         "graph_value": P * args.steps / (fp32["graph_ms"] * 1e-3),
         "bf16": None if bf16 is None else {
             "value": P * args.steps / (bf16["total_ms"] * 1e-3),
@@ -486,7 +492,10 @@ def main() -> int:
             "evaluate_hbm_gbs": swap_bytes / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9,
             "roofline": roof("hbm", swap_bytes / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9, "GB/s",
                              "k_swap_stage + k_swap_finish (one swap pass)",
-                             f"tile counts once ({P} pixels x {T} integrands x 2 B)")},
+                             f"tile counts once + {M} partner rows ({T} integrands x 2 B)"),
+            "roofline_alu": roof("alu", stencil_lane_ops / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e12,
+                                 "TOP/s", "k_swap_stage + k_swap_finish (one swap pass)",
+                                 f"{M} members x {win} offsets x {T} integrands / 2 per v_dot2")},
         "batched": None if batch is None else dict(batch, roofline=roof(
             "alu", batch["count_lane_ops_per_sweep"] / (batch["ms_per_sweep"] * 1e-3) / 1e12, "TOP/s",
             "whole batched sweep (recounts of every member's proposals over the sweep time)",
