@@ -303,6 +303,8 @@ __global__ __launch_bounds__(32 * BY) void k_delta_stage_batch(const DevView* __
                                                                const uint32_t* __restrict__ pre,
                                                                const uint32_t* __restrict__ geo,
                                                                uint32_t nmem, uint32_t kappa) {
+  // like the single problem's phase kernels: issue ahead of the recount
+  __builtin_amdgcn_s_setprio(2);
   const uint32_t i = batch_member(pre, nmem, blockIdx.x);
   const DevView v = views[i];
   const uint32_t lb = blockIdx.x - pre[i];
@@ -337,6 +339,7 @@ __global__ __launch_bounds__(256) void k_delta_finish(DevView v, long long* __re
 __global__ __launch_bounds__(256) void k_delta_finish_batch(const DevView* __restrict__ views,
                                                             const uint32_t* __restrict__ pre,
                                                             uint32_t nmem) {
+  __builtin_amdgcn_s_setprio(2);
   const uint32_t i = batch_member(pre, nmem, blockIdx.x);
   const DevView v = views[i];
   delta_finish_body(v, v.xpart, blockIdx.x - pre[i]);
@@ -405,6 +408,7 @@ __global__ __launch_bounds__(256) void k_commit(DevView v, uint32_t kappa) {
 __global__ __launch_bounds__(256) void k_commit_batch(const DevView* __restrict__ views,
                                                       const uint32_t* __restrict__ pre, uint32_t nmem,
                                                       uint32_t kappa) {
+  __builtin_amdgcn_s_setprio(2);
   const uint32_t i = batch_member(pre, nmem, blockIdx.x);
   const DevView v = views[i];
   commit_body(v, kappa, blockIdx.x - pre[i]);
