@@ -86,6 +86,7 @@ struct SwapGeom {
   static constexpr int PART = 2 * CAP;                   // partner words per stage
   static constexpr int SBUF = 2 * PLANE + PART;          // words of one stage buffer
   static constexpr int NBUF = 3;                         // ring depth
+  static constexpr int PD = NBUF - 1;                    // stages loaded ahead
   static constexpr int NRL = 2 * RA_PAD / 64;            // region loads per stage
   static constexpr int NLD = NRL + PART / 64;            // loads per stage
   static constexpr int D = (NLD + NWAVE - 1) / NWAVE;    // loads per wave and stage
@@ -99,6 +100,7 @@ struct SwapGeom {
   static constexpr int LDS_BYTES = NBUF * SBUF * 16 + (3 * NPIX + NWV + 8 * STEPS) * 4;
   static_assert(NPIX % 64 == 0 && RWP % 2 == 1 && PLANE % 16 == 8 && PART % 64 == 0, "swap block geometry");
   static_assert(D * NWAVE < 2 * NLD, "repeated load slots");
+  static_assert(PD >= 1 && PD <= 3 && (PD - 1) * D < 64, "ring depth and vmcnt");
 };
 
 // Window offset of lane slot i at step st (row steps first, then column
@@ -125,7 +127,7 @@ __device__ inline void wait_vm_lgkm0() {
 }
 
 template <int R>
-__global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v, SwapView sv, uint32_t kappa,
+__global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v, SwapView sv, uint32_t kappa,
                                                                     uint32_t slen, uint32_t gx, uint32_t gy) {
   using G = SwapGeom<R>;
   constexpr int NCLS = WinConst<R>::NCLS;
@@ -263,12 +265,17 @@ __global__ __launch_bounds__(512, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v,
     }
     // the previous round's reads of the ring are done
     sync_vm(std::integral_constant<int, 0>{});
-    if (nst > 0) issue(t_begin, 0);
-    if (nst > 1) issue(t_begin + 16, 1);
+#pragma unroll
+    for (int k = 0; k < G::PD; ++k)
+      if ((uint32_t)k < nst) issue(t_begin + 16 * k, k);
     for (uint32_t si = 0; si < nst; ++si) {
-      if (si + 1 < nst) sync_vm(std::integral_constant<int, G::D>{});
+      // stage si has landed once at most the loads of the stages issued
+      // after it (up to PD - 1 of them) are in flight
+      const uint32_t ahead = min((uint32_t)G::PD - 1, nst - 1 - si);
+      if (G::PD >= 3 && ahead == 2) sync_vm(std::integral_constant<int, 2 * G::D>{});
+      else if (G::PD >= 2 && ahead == 1) sync_vm(std::integral_constant<int, G::D>{});
       else sync_vm(std::integral_constant<int, 0>{});
-      if (si + 2 < nst) issue(t_begin + 16 * (si + 2), (si + 2) % G::NBUF);
+      if (si + G::PD < nst) issue(t_begin + 16 * (si + G::PD), (si + G::PD) % G::NBUF);
       const u32x4* bf = lds4 + (si % G::NBUF) * G::SBUF;
 #pragma unroll
       for (int s = 0; s < G::SLOTS; ++s) {
@@ -453,15 +460,18 @@ hipError_t prepare_swap_kernels() {
   return status;
 }
 
-// Integrand slices: enough workgroups to fill the device twice over, and few
-// enough stages per slice that every per-lane int32 step sum stays below 2^31.
+// Integrand slices: enough workgroups for about 1024 threads on each of the
+// 256 CUs, and few enough stages per slice that every per-lane int32 step sum
+// stays below 2^31.
 template <int R>
 hipError_t swap_stage_launch(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
   using G = SwapGeom<R>;
   const uint32_t gx = (v.w + G::BW - 1) / G::BW, gy = (v.h + G::BH - 1) / G::BH, chunks = v.tp / 16;
   const double n2 = (double)v.n * v.n;
   const uint32_t smax = (uint32_t)std::max(1.0, std::floor(2147483647.0 / (8.0 * n2)));
-  uint32_t nz = std::max<uint32_t>(1, std::min<uint32_t>(chunks, (512 + gx * gy - 1) / (gx * gy)));
+  // about 1024 threads per CU of 256 CUs
+  const uint32_t target = 262144 / G::NT;
+  uint32_t nz = std::max<uint32_t>(1, std::min<uint32_t>(chunks, (target + gx * gy - 1) / (gx * gy)));
   uint32_t per = (chunks + nz - 1) / nz;
   if (per > smax) per = smax;
   nz = (chunks + per - 1) / per;
