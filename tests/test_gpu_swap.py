@@ -24,6 +24,11 @@ SWAP = {
     "n1024_r5": workload(move=1, n=1024, g=(1, 381), width=16, height=16, radius=5, t_heaviside=66),
     "n4096_r6": workload(move=1, n=4096, g=(1, 1365), width=16, height=16, radius=6, t_heaviside=40),
     "r1": workload(move=1, width=8, height=32, radius=1, t_heaviside=130),
+    # one colour class: every pixel is a pass member, so a workgroup's block
+    # holds more members than one round of its member slots (three rounds at
+    # r = 3, 32x8 blocks; two at r = 5, 32x4 blocks)
+    "k1_rounds_r3": workload(move=1, colour_k=1, width=32, height=16, radius=3, t_heaviside=40),
+    "k1_rounds_r5": workload(move=1, colour_k=1, width=32, height=16, radius=5, t_heaviside=40),
 }
 
 
