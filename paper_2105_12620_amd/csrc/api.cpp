@@ -1298,7 +1298,7 @@ bn_status bn_create_problem_ext(const bn_config* cfg, const bn_heaviside* heavis
     delete p;
     return s;
   }
-  hipError_t e = hipSuccess;
+  hipError_t e = v.mfma ? prepare_bf_kernels(v.radius, v.k) : hipSuccess;
   if (e == hipSuccess) e = hipMemcpyAsync(lat_d, lat.data(), v.n * 4, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(ihp_d, ihp.data(), v.tp * 8, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(area_d, areaf.data(), v.tp * 4, hipMemcpyHostToDevice, p->stream);

@@ -107,6 +107,8 @@ hipError_t launch_advance_batch(const DevView* views, uint32_t nmem, hipStream_t
 // field's energy
 bool bf16_supported_k(uint32_t k);
 hipError_t launch_bf_field(const DevView& v, hipStream_t s);
+// raises the LDS launch limit of the BF16 kernels of this radius and K (once per process)
+hipError_t prepare_bf_kernels(uint32_t radius, uint32_t k);
 hipError_t launch_delta_bf16(const DevView& v, uint32_t kappa, hipStream_t s);
 hipError_t launch_energy_bf16(const DevView& v, double* ysum, hipStream_t s);
 // decision from the summed class sums of a colour phase (clears them)

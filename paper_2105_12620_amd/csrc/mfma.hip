@@ -35,6 +35,10 @@ namespace {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// LDS words written by global_load_lds are read as clang vector types: reads
+// through HIP's struct vector types make the compiler wait for every load
+// into LDS in flight (the waits here are explicit)
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // The whole BF16 field from the current counts and Gaussian estimates; one
 // thread per (8-integrand tile, pixel), pixels fastest.
@@ -61,29 +65,55 @@ __global__ __launch_bounds__(256) void k_bf_field(DevView v) {
 // ----------------------------------------------------------- the Gram kernel
 //
 // A workgroup owns BYC class rows x 16 class pixels; wave w owns class row w,
-// the 16 rows of its MFMA tiles.  Per 16-integrand slice the field values of
-// the window region (RROWS x RUSED pixels) are copied into LDS as they are
-// (already BF16), in four quarter planes of 4 integrands (8 bytes per pixel);
-// the class pixels' change operands go beside them.  For every neighbour row
-// oy of the pass and column tile ct, v_mfma_f32_16x16x16_bf16 accumulates
+// the 16 rows of its MFMA tiles.  Per 16-integrand slice the field words of
+// the window region (RROWS x RUSED pixels, two 16-byte words of 8 integrands
+// each) go from HBM straight into a ring of LDS slots (global_load_lds, no
+// registers), PD = NBUF - 1 slices ahead of the one multiplied, and the
+// class pixels' count words likewise one slice ahead; every lane forms its
+// own change operand (class pixel lane % 16, integrands 4 (lane / 16) .. +3
+// of the slice).  Gaussian rows (approximate mode) go one slice at a time,
+// their estimates through registers.  For every neighbour row oy of the pass and
+// column tile ct, v_mfma_f32_16x16x16_bf16 accumulates
 //     C[b][col] += sum_t d[b][t] * f[row][col][t]
-// and pixel b's window entries are the columns K b + R + ox.  Window rows are
-// split into passes when their accumulators would exceed 40 tiles (160
-// registers); the self term is added by pass 0 only.
+// and pixel b's window entries are the columns K b + R + ox (the columns past
+// RUSED read the next row's words or the slot's tail: their outputs are never
+// read back).  Window rows are split into passes when their accumulators
+// would exceed 40 tiles (160 registers); the self term is added by pass 0
+// only.
 template <int R, int K, int BYC, int OY0, int NOY>
 struct BfGeom {
   static constexpr int BXC = 16;
   static constexpr int RROWS = K * (BYC - 1) + NOY;
   static constexpr int RUSED = K * (BXC - 1) + 2 * R + 1;
-  static constexpr int NT = (RUSED + 15) / 16;
+  static constexpr int NT = (RUSED + 15) / 16;               // column tiles
   static constexpr int RCOLS = 16 * NT;
   static constexpr int NB = BYC * BXC;
-  static constexpr int REG8 = 4 * RROWS * RCOLS;   // region, 8-byte words
-  static constexpr int DC8 = 4 * NB;               // change operands, 8-byte words
-  static constexpr int STAGE_BYTES = 8 * (REG8 + DC8);
-  static constexpr int EXTRACT_BYTES = 16 * NB + BYC * 16 * RCOLS * 4;
+  static constexpr int NTH = 64 * BYC;                       // threads
+  static constexpr int PLANE = RROWS * RUSED;                // region pixels
+  // a plane per tile half, padded to 256 bytes: the four 16-lane groups of a
+  // read then agree modulo 256 bytes
+  static constexpr int PLANE_PAD = (PLANE + 15) / 16 * 16;
+  // region loads per thread and slice: every wave issues the same number
+  // (words past the planes load pixel 0 into the slot's tail), and the reads
+  // of the column tiles past RUSED stay inside the slot
+  static constexpr int ITERD = (2 * PLANE_PAD + RCOLS - RUSED + NTH - 1) / NTH;
+  static constexpr int SLOT = ITERD * NTH;                   // 16-byte words
+  // change-operand words: two slots of 128 16-byte words per wave
+  static constexpr int ARING_BYTES = 2 * BYC * 128 * 16;
+  // three region slots where two workgroups still fit on a CU, else two
+  static constexpr int NBUF = 3 * SLOT * 16 + ARING_BYTES <= 81920 ? 3 : 2;
+  static constexpr int PD = NBUF - 1;
+  static constexpr int STAGE_BYTES = NBUF * SLOT * 16 + ARING_BYTES;
+  static constexpr int EXTRACT_BYTES = BYC * 16 * RCOLS * 4;
   static constexpr int LDS_BYTES = STAGE_BYTES > EXTRACT_BYTES ? STAGE_BYTES : EXTRACT_BYTES;
 };
+
+// s_waitcnt with vmcnt(n) and lgkmcnt(0), expcnt left open (gfx9 encoding)
+template <int N>
+__device__ inline void bf_wait_vm_lgkm0() {
+  static_assert(N < 64, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
 
 template <int R, int K, int BYC, int OY0, int NOY>
 __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa, uint32_t trlen,
@@ -93,12 +123,7 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
   using G = BfGeom<R, K, BYC, OY0, NOY>;
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
-  constexpr int NT = 64 * BYC;
-  constexpr int NITEM = 2 * G::RROWS * G::RUSED;
-  constexpr int ITER = (NITEM + NT - 1) / NT;
-  extern __shared__ uint2 lds8[];
-  uint2* reg = lds8;                 // [4][RROWS][RCOLS]
-  uint2* dcs = lds8 + G::REG8;       // [4][NB]
+  extern __shared__ uint4 lds16[];
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t a0 = blockIdx.y * BYC, b0 = blockIdx.x * G::BXC;
   const uint32_t ky = kappa / K, kx = kappa - ky * K;
@@ -107,39 +132,33 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
   const uint32_t P = v.w * v.h;
   const bool approx = v.mfma == 2;
 
-  // columns past the used ones are never read back; keep them finite
-  for (uint32_t i = threadIdx.x; i < (uint32_t)(4 * G::RROWS * (G::RCOLS - G::RUSED)); i += blockDim.x) {
-    const uint32_t q = i / (G::RCOLS - G::RUSED), c = G::RUSED + i % (G::RCOLS - G::RUSED);
-    reg[q * G::RCOLS + c] = make_uint2(0, 0);
+  // region loads: load it of wave w moves slot words it NTH + 64 w + lane;
+  // word i is (tile half i / PLANE_PAD, region pixel i mod PLANE_PAD), its
+  // source the byte offset below from the slice's first field word
+  uint32_t src[G::ITERD];
+#pragma unroll
+  for (int it = 0; it < G::ITERD; ++it) {
+    const uint32_t i = it * G::NTH + threadIdx.x;
+    const uint32_t half = i / G::PLANE_PAD, pix = i - half * G::PLANE_PAD;
+    src[it] = 0;
+    if (half < 2 && pix < (uint32_t)G::PLANE) {
+      const uint32_t rr = pix / G::RUSED, cc = pix - rr * G::RUSED;
+      uint32_t gy = ys + rr, gx = xs + cc;
+      while (gy >= v.h) gy -= v.h;
+      while (gx >= v.w) gx -= v.w;
+      src[it] = (half * P + gy * v.w + gx) * 16;
+    }
   }
 
-  // change-operand roles: thread i < 2 NB owns (class pixel i >> 1, tile i & 1 of the slice)
-  const uint32_t own_cp = threadIdx.x >> 1, own_half = threadIdx.x & 1;
-  const uint32_t own_a = a0 + own_cp / G::BXC, own_b = b0 + own_cp % G::BXC;
-  const bool own_ok = threadIdx.x < 2u * G::NB && own_a < v.ch && own_b < v.cw;
+  // the lane's class pixel and quarter (four integrands) of the slice
+  const uint32_t quarter = lane >> 4, m = lane & 15;
+  const uint32_t own_a = a0 + w, own_b = b0 + m;
+  const bool own_ok = own_a < v.ch && own_b < v.cw;
   const uint32_t own_p = own_ok ? (ky + K * own_a) * v.w + (kx + K * own_b) : 0;
   const uint32_t own_j = own_ok ? own_a * v.cw + own_b : 0;
   long long z0 = 0;          // exact mode: sum_t dc (c' + c)
   double s0 = 0.0;           // approximate mode: sum_t d (e' + e)
   uint32_t absdc = 0;        // exact mode: sum_t |dc|
-
-  // staging plan: item i = (tile half, region pixel), fixed for the whole range
-  uint32_t item_pix[ITER], item_lds[ITER];
-#pragma unroll
-  for (int it = 0; it < ITER; ++it) {
-    const uint32_t i = threadIdx.x + it * NT;
-    item_pix[it] = 0xFFFFFFFFu;
-    item_lds[it] = 0;
-    if (i < (uint32_t)NITEM) {
-      const uint32_t half = i / (G::RROWS * G::RUSED), pix = i - half * (G::RROWS * G::RUSED);
-      const uint32_t rr = pix / G::RUSED, cc = pix - rr * G::RUSED;
-      uint32_t gy = ys + rr, gx = xs + cc;
-      while (gy >= v.h) gy -= v.h;
-      while (gx >= v.w) gx -= v.w;
-      item_pix[it] = (gy * v.w + gx) | (half << 31);
-      item_lds[it] = ((2 * half) * G::RROWS + rr) * G::RCOLS + cc;
-    }
-  }
 
   f32x4 acc[NOY][G::NT];
 #pragma unroll
@@ -148,111 +167,155 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
     for (int ct = 0; ct < G::NT; ++ct) acc[oy][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const uint32_t t_begin = blockIdx.z * trlen, t_end = min(t_begin + trlen, v.tb);
-  uint4 q[ITER];
-  auto load_region = [&](uint32_t t0) {
+  // Heaviside rows [t_begin, h_end) first, then Gaussian rows [g_begin,
+  // t_end): a slice lies wholly in one kind (both counts are multiples of 16)
+  const uint32_t h_end = min(t_end, v.tp), g_begin = max(t_begin, v.tp);
+  const uint32_t nsh = h_end > t_begin ? (h_end - t_begin) / 16 : 0;
+  const uint32_t nsg = t_end > g_begin ? (t_end - g_begin) / 16 : 0;
+  uint4* aring = lds16 + G::NBUF * G::SLOT;   // [2][BYC][128] change-operand words
+
+  // region loads of the slice at t0 into ring slot buf
+  auto issue = [&](uint32_t t0, uint32_t buf) {
+    const char* fs = (const char*)(v.bf + (size_t)(t0 >> 3) * P * 8);
 #pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      if (item_pix[it] != 0xFFFFFFFFu) {
-        const uint32_t half = item_pix[it] >> 31, pix = item_pix[it] & 0x7FFFFFFFu;
-        q[it] = *(const uint4*)(v.bf + tix(pix, t0 + 8 * half, P));
-      }
-    }
+    for (int it = 0; it < G::ITERD; ++it)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(fs + src[it]),
+                                       (__attribute__((address_space(3))) void*)(lds16 + buf * G::SLOT +
+                                                                                 it * G::NTH + 64 * w),
+                                       16, 0, 0);
   };
-  if (t_begin < t_end) load_region(t_begin);
-  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 16) {
+  // change-operand words of the wave's 16 class pixels for the Heaviside
+  // slice at t0 into its slot: words 0..63 the new (lanes 0..31) and current
+  // (32..63) count words of pixel lane % 16, tile half (lane / 16) % 2;
+  // approximate mode: words 64..67 the slice's 16 exact integrals (four
+  // lanes' worth, repeated by the others)
+  const uint32_t al = lane & 15, ah = (lane >> 4) & 1;
+  const uint32_t a_j = (own_a < v.ch && b0 + al < v.cw) ? own_a * v.cw + b0 + al : 0;
+  const uint32_t a_p = (own_a < v.ch && b0 + al < v.cw) ? (ky + K * own_a) * v.w + (kx + K * (b0 + al)) : 0;
+  auto issue_a = [&](uint32_t t0, uint32_t buf) {
+    uint4* dst = aring + (buf * BYC + w) * 128;
+    const uint16_t* s = lane < 32 ? v.c_new + tix(a_j, t0 + 8 * ah, v.pc) : v.cnt + tix(a_p, t0 + 8 * ah, P);
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)s,
+                                     (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    if (approx)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(v.area + t0 + 4 * (lane & 3)),
+                                       (__attribute__((address_space(3))) void*)(dst + 64), 16, 0, 0);
+  };
+  // the lane's change operand (BF16) of a Heaviside slice and its part of
+  // the self term, from the wave's change-operand words
+  auto operand_h = [&](const uint4* aw) -> bf16x4 {
+    float f[4] = {0.f, 0.f, 0.f, 0.f};
+    if (own_ok) {
+      const u32x2 cn = ((const u32x2*)aw)[2 * ((quarter >> 1) * 16 + m) + (quarter & 1)];
+      const u32x2 co = ((const u32x2*)aw)[2 * (32 + (quarter >> 1) * 16 + m) + (quarter & 1)];
+      const uint32_t nw[2] = {cn.x, cn.y}, ow[2] = {co.x, co.y};
+      const float inv_n = 1.0f / (float)v.n;
 #pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      if (item_pix[it] != 0xFFFFFFFFu) {
-        reg[item_lds[it]] = make_uint2(q[it].x, q[it].y);
-        reg[item_lds[it] + G::RROWS * G::RCOLS] = make_uint2(q[it].z, q[it].w);
-      }
-    }
-    // change operands of the moved pixels (and their self terms)
-    if (threadIdx.x < 2u * G::NB) {
-      uint32_t o[4] = {0u, 0u, 0u, 0u};
-      if (own_ok) {
-        const uint32_t t = t0 + 8 * own_half;
-        if (t < v.tp) {
-          const uint4 cn4 = *(const uint4*)(v.c_new + tix(own_j, t, v.pc));
-          const uint4 co4 = *(const uint4*)(v.cnt + tix(own_p, t, P));
-          const uint32_t nw[4] = {cn4.x, cn4.y, cn4.z, cn4.w}, ow[4] = {co4.x, co4.y, co4.z, co4.w};
-          const float inv_n = 1.0f / (float)v.n;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int n0 = (int)(nw[k] & 0xFFFFu), n1 = (int)(nw[k] >> 16);
-            const int c0 = (int)(ow[k] & 0xFFFFu), c1 = (int)(ow[k] >> 16);
-            const int d0 = n0 - c0, d1 = n1 - c1;
-            if (!approx) {
-              z0 += (long long)(d0 * (n0 + c0) + d1 * (n1 + c1));
-              absdc += (uint32_t)(abs(d0) + abs(d1));
-              o[k] = bf16x2_bits((float)d0, (float)d1);
-            } else {
-              const float f0 = __fmul_rn((float)d0, inv_n), f1 = __fmul_rn((float)d1, inv_n);
-              const double a0d = v.area[t + 2 * k], a1d = v.area[t + 2 * k + 1];
-              s0 = __dadd_rn(s0, __dmul_rn((double)f0, (double)(n0 + c0) / (double)v.n - 2.0 * a0d));
-              s0 = __dadd_rn(s0, __dmul_rn((double)f1, (double)(n1 + c1) / (double)v.n - 2.0 * a1d));
-              o[k] = bf16x2_bits(f0, f1);
-            }
-          }
+      for (int i = 0; i < 4; ++i) {
+        const int n = (int)((nw[i >> 1] >> (16 * (i & 1))) & 0xFFFFu);
+        const int c = (int)((ow[i >> 1] >> (16 * (i & 1))) & 0xFFFFu);
+        const int d = n - c;
+        if (!approx) {
+          z0 += (long long)(d * (n + c));
+          absdc += (uint32_t)abs(d);
+          f[i] = (float)d;
         } else {
-          const uint32_t tg = t - v.tp;
-          const float* gn = v.g_new + (size_t)own_j * v.tgp + tg;
-          const float* go = v.gest + (size_t)own_p * v.tgp + tg;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            float f[2];
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-              const uint32_t i = 2 * k + e;
-              f[e] = 0.0f;
-              if (tg + i < v.tg) {
-                f[e] = __fsub_rn(gn[i], go[i]);
-                s0 = __dadd_rn(s0, __dmul_rn((double)f[e], (double)gn[i] + (double)go[i] - 2.0 * v.gint[tg + i]));
-              }
-            }
-            o[k] = bf16x2_bits(f[0], f[1]);
-          }
+          const double ar = (double)((const float*)(aw + 64))[4 * quarter + i];
+          f[i] = __fmul_rn((float)d, inv_n);
+          s0 = __dadd_rn(s0, __dmul_rn((double)f[i], (double)(n + c) / (double)v.n - 2.0 * ar));
         }
       }
-      dcs[(2 * own_half) * G::NB + own_cp] = make_uint2(o[0], o[1]);
-      dcs[(2 * own_half + 1) * G::NB + own_cp] = make_uint2(o[2], o[3]);
     }
-    __syncthreads();
-    if (t0 + 16 < t_end) load_region(t0 + 16);
-    // lane l: MFMA row (class pixel) l % 16, integrands 4 (l / 16) .. +3 of the slice
-    const uint32_t quarter = lane >> 4, m = lane & 15;
-    const bf16x4 af = __builtin_bit_cast(bf16x4, dcs[quarter * G::NB + w * G::BXC + m]);
+    return __builtin_bit_cast(bf16x4, make_uint2(bf16x2_bits(f[0], f[1]), bf16x2_bits(f[2], f[3])));
+  };
+  auto mfma_slice = [&](uint32_t buf, const bf16x4 af) {
+    const u32x2* fb = (const u32x2*)(lds16 + buf * G::SLOT);
 #pragma unroll
     for (int oy = 0; oy < NOY; ++oy) {
       const uint32_t rr = K * w + oy;
 #pragma unroll
       for (int ct = 0; ct < G::NT; ++ct) {
-        const uint2 b2 = reg[(quarter * G::RROWS + rr) * G::RCOLS + ct * 16 + m];
+        const u32x2 b2 = fb[2 * ((quarter >> 1) * G::PLANE_PAD + rr * G::RUSED + ct * 16 + m) + (quarter & 1)];
         acc[oy][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, __builtin_bit_cast(bf16x4, b2), acc[oy][ct],
                                                                 0, 0, 0);
       }
     }
-    __syncthreads();
+  };
+  // wait until at most N of this wave's loads are in flight and its LDS
+  // accesses are done, then meet the other waves; the empty asm statements
+  // keep the compiler from moving memory accesses across
+  auto sync_vm = [&](auto n) {
+    asm volatile("" ::: "memory");
+    bf_wait_vm_lgkm0<decltype(n)::value>();
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+
+  // Heaviside slices: region words PD slices ahead, change-operand words one
+  // slice ahead, all through LDS, so that no register waits on a load.  Each
+  // step issues one slice of region loads (past the range a repeat of the
+  // first slice, into the slot that is never read again), after that step's
+  // change-operand loads: the loads issued after slice si's are then always
+  // the region loads of the PD - 1 slices that follow it.
+  if (nsh > 0) {
+    issue_a(t_begin, 0);
+#pragma unroll
+    for (int k = 0; k < G::PD; ++k) issue((uint32_t)k < nsh ? t_begin + 16 * k : t_begin, k);
+  }
+  for (uint32_t si = 0; si < nsh; ++si) {
+    const uint32_t t0 = t_begin + 16 * si;
+    sync_vm(std::integral_constant<int, (G::PD - 1) * G::ITERD>{});
+    const bf16x4 af = operand_h(aring + ((si & 1) * BYC + w) * 128);
+    // the slots refilled here were last read by every wave before the barrier
+    issue_a(si + 1 < nsh ? t0 + 16 : t_begin, (si + 1) & 1);
+    issue(si + G::PD < nsh ? t0 + 16 * G::PD : t_begin, (si + G::PD) % G::NBUF);
+    mfma_slice(si % G::NBUF, af);
   }
   __syncthreads();
 
-  // self terms and certificates: the two tile halves of a pixel meet in LDS
-  double* zsh = (double*)lds8;                         // [NB] (exact mode: integer, exact in FP64)
-  uint32_t* ash = (uint32_t*)(zsh + G::NB);            // [NB]
-  if (threadIdx.x < 2u * G::NB && own_half == 0) {
-    zsh[own_cp] = approx ? s0 : (double)z0;
-    ash[own_cp] = absdc;
+  // Gaussian slices (approximate mode only): one slice at a time through
+  // ring slot 0, the change operands from the estimates in registers
+  for (uint32_t si = 0; si < nsg; ++si) {
+    const uint32_t t0 = g_begin + 16 * si;
+    issue(t0, 0);
+    const uint32_t tg = t0 + 4 * quarter - v.tp;
+    float4 gn4 = make_float4(0.f, 0.f, 0.f, 0.f), go4 = gn4;
+    double gi[4] = {0.0, 0.0, 0.0, 0.0};
+    if (own_ok) {
+      gn4 = *(const float4*)(v.g_new + (size_t)own_j * v.tgp + tg);
+      go4 = *(const float4*)(v.gest + (size_t)own_p * v.tgp + tg);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) gi[i] = v.gint[tg + i];
+    }
+    const float gn[4] = {gn4.x, gn4.y, gn4.z, gn4.w}, go[4] = {go4.x, go4.y, go4.z, go4.w};
+    float f[4] = {0.f, 0.f, 0.f, 0.f};
+    if (own_ok) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (tg + i < v.tg) {
+          f[i] = __fsub_rn(gn[i], go[i]);
+          s0 = __dadd_rn(s0, __dmul_rn((double)f[i], (double)gn[i] + (double)go[i] - 2.0 * gi[i]));
+        }
+      }
+    }
+    const bf16x4 af = __builtin_bit_cast(bf16x4, make_uint2(bf16x2_bits(f[0], f[1]), bf16x2_bits(f[2], f[3])));
+    sync_vm(std::integral_constant<int, 0>{});
+    mfma_slice(0, af);
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x < 2u * G::NB && own_half == 1) {
-    zsh[own_cp] = __dadd_rn(zsh[own_cp], approx ? s0 : (double)z0);
-    ash[own_cp] += absdc;
-  }
-  __syncthreads();
+
+  // self terms and certificates: the four quarters of a class pixel meet in
+  // lane m
+  z0 += __shfl_xor(z0, 16);
+  z0 += __shfl_xor(z0, 32);
+  absdc += __shfl_xor(absdc, 16);
+  absdc += __shfl_xor(absdc, 32);
+  s0 = __dadd_rn(s0, __shfl_xor(s0, 16));
+  s0 = __dadd_rn(s0, __shfl_xor(s0, 32));
 
   // window entries: per neighbour row, the wave's tiles go through LDS and
   // lanes 0..15 (one per class pixel) collect their 2R+1 columns
-  float* gsh = (float*)(lds8 + 2 * G::NB) + w * (16 * G::RCOLS);   // [16][RCOLS] per wave
+  float* gsh = (float*)lds16 + w * (16 * G::RCOLS);   // [16][RCOLS] per wave
   const uint32_t b = lane;
   double zd[NCLS];   // exact mode: sums of exact integers below 2^24 each
 #pragma unroll
@@ -283,10 +346,9 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
   }
   const uint32_t a = a0 + w, bb = b0 + b;
   if (lane < 16 && a < v.ch && bb < v.cw) {
-    const uint32_t cp = w * G::BXC + b;
     const uint32_t j = a * v.cw + bb;
-    const double self = OY0 == 0 ? zsh[cp] : 0.0;
-    if (!approx && (unsigned long long)ash[cp] * v.n >= (1ull << 24)) atomicOr(&unsure[j], 1u);
+    const double self = OY0 == 0 ? (approx ? s0 : (double)z0) : 0.0;
+    if (!approx && (unsigned long long)absdc * v.n >= (1ull << 24)) atomicOr(&unsure[j], 1u);
 #pragma unroll
     for (int c = 0; c < NCLS; ++c) {
       long long x;
@@ -473,7 +535,7 @@ constexpr int BF_MAX_TILES = 40;
 template <int R, int K, int OY0, int NOY>
 hipError_t bf_pass(const DevView& v, uint32_t kappa, hipStream_t s) {
   using G = BfGeom<R, K, BF_BYC, OY0, NOY>;
-  static_assert(G::LDS_BYTES <= 65536, "BF16 block exceeds 64 KiB of LDS");
+  static_assert(G::LDS_BYTES <= 163840, "BF16 block exceeds the 160 KiB of LDS of a CU");
   const uint32_t bx = (v.cw + G::BXC - 1) / G::BXC, by = (v.ch + BF_BYC - 1) / BF_BYC;
   uint32_t trlen = 0;
   const uint32_t ns = bf_slices(v, bx * by, &trlen);
@@ -495,6 +557,37 @@ hipError_t bf_passes(const DevView& v, uint32_t kappa, hipStream_t s) {
     hipError_t e = bf_pass<R, K, OY0, NOY>(v, kappa, s);
     if (e != hipSuccess) return e;
     return bf_passes<R, K, OY0 + NOY>(v, kappa, s);
+  }
+}
+
+// Launch limit of the passes' kernels raised to their LDS use where it is
+// above 64 KiB (gfx950 has 160 KiB per CU).
+template <int R, int K, int OY0>
+hipError_t bf_prepare_passes() {
+  if constexpr (OY0 > 2 * R) {
+    return hipSuccess;
+  } else {
+    constexpr int NT = BfGeom<R, K, BF_BYC, 0, 1>::NT;
+    constexpr int LEFT = 2 * R + 1 - OY0;
+    constexpr int FIT = BF_MAX_TILES / NT;
+    constexpr int NOY = LEFT < FIT ? LEFT : FIT;
+    using G = BfGeom<R, K, BF_BYC, OY0, NOY>;
+    if constexpr (G::LDS_BYTES > 65536) {
+      const hipError_t e = hipFuncSetAttribute((const void*)k_delta_bf<R, K, BF_BYC, OY0, NOY>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::LDS_BYTES);
+      if (e != hipSuccess) return e;
+    }
+    return bf_prepare_passes<R, K, OY0 + NOY>();
+  }
+}
+
+template <int R>
+hipError_t bf_prepare(uint32_t k) {
+  switch (k) {
+    case 1: return bf_prepare_passes<R, 1, 0>();
+    case 2: return bf_prepare_passes<R, 2, 0>();
+    case 4: return bf_prepare_passes<R, 4, 0>();
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -529,6 +622,18 @@ hipError_t launch_bf_field(const DevView& v, hipStream_t s) {
   const size_t n = (size_t)v.w * v.h * (v.tb >> 3);
   hipLaunchKernelGGL(k_bf_field, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v);
   return hipGetLastError();
+}
+
+hipError_t prepare_bf_kernels(uint32_t radius, uint32_t k) {
+  switch (radius) {
+    case 1: return bf_prepare<1>(k);
+    case 2: return bf_prepare<2>(k);
+    case 3: return bf_prepare<3>(k);
+    case 4: return bf_prepare<4>(k);
+    case 5: return bf_prepare<5>(k);
+    case 6: return bf_prepare<6>(k);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_delta_bf16(const DevView& v, uint32_t kappa, hipStream_t s) {
