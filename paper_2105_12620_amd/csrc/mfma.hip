@@ -363,78 +363,85 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
 }
 
 // Exact mode: re-check of the accepted moves whose slices could not certify
-// exactness, with the integer class sums (one wave per flagged pixel; a move
-// the exact value rejects is a veto).
+// exactness, with the integer class sums (a move the exact value rejects is a
+// veto).  A wave screens 64 consecutive class pixels, clearing their flags,
+// and re-checks its flagged accepted ones one after another: flagged pixels
+// are rare, and one wave per pixel spent most of the kernel's time launching
+// and retiring waves with nothing to do.
 template <int R>
 __global__ __launch_bounds__(256) void k_delta_refine(DevView v, uint32_t kappa, uint32_t* __restrict__ unsure) {
   __builtin_amdgcn_s_setprio(2);
   constexpr Window<R> W = WinConst<R>::w;
   constexpr int NCLS = WinConst<R>::NCLS;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t j = wave_id();
-  if (j >= v.pc) return;
-  const bool todo = v.accept[j] != 0 && unsure[j] != 0;
-  if (lane == 0) unsure[j] = 0;
-  if (!todo) return;
-  const uint32_t p = class_pixel(v, kappa, j);
-  const uint32_t y = p / v.w, x = p - y * v.w, P = v.w * v.h;
-  long long z0 = 0, zd[NCLS];
-#pragma unroll
-  for (int c = 0; c < NCLS; ++c) zd[c] = 0;
-  for (uint32_t base = 0; base < v.tp; base += 128) {
-    const uint32_t t = base + 2 * lane;
-    const uint32_t cn = *(const uint32_t*)(v.c_new + tix(j, t, v.pc));
-    const uint32_t co = *(const uint32_t*)(v.cnt + tix(p, t, P));
-    const int n0 = (int)(cn & 0xFFFFu), n1 = (int)(cn >> 16);
-    const int o0 = (int)(co & 0xFFFFu), o1 = (int)(co >> 16);
-    const int dc0 = n0 - o0, dc1 = n1 - o1;
-    const uint32_t dcp = ((uint32_t)dc0 & 0xFFFFu) | ((uint32_t)dc1 << 16);
-    z0 += (long long)(dc0 * (n0 + o0) + dc1 * (n1 + o1));
-#pragma unroll
-    for (int mm = 0; mm < W.M; ++mm) {
-      const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
-      zd[W.cls[mm]] += dot2(dcp, *(const uint32_t*)(v.cnt + tix(q, t, P)), 0);
-    }
+  const uint32_t j0 = wave_id() * 64;
+  bool flag = false;
+  if (j0 + lane < v.pc) {
+    flag = v.accept[j0 + lane] != 0 && unsure[j0 + lane] != 0;
+    unsure[j0 + lane] = 0;
   }
-  double acc = 0.0;
+  for (uint64_t todo = __ballot(flag); todo != 0; todo &= todo - 1) {
+    const uint32_t j = j0 + (uint32_t)__builtin_ctzll(todo);
+    const uint32_t p = class_pixel(v, kappa, j);
+    const uint32_t y = p / v.w, x = p - y * v.w, P = v.w * v.h;
+    long long z0 = 0, zd[NCLS];
 #pragma unroll
-  for (int c = 0; c < NCLS; ++c) {
-    long long xv = (long long)W.csize[c] * z0 - 2 * zd[c];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
-    acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)xv));
-  }
-  double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
-  if (v.tgp) {
-    double cs[NCLS];
-#pragma unroll
-    for (int c = 0; c < NCLS; ++c) cs[c] = 0.0;
-    for (uint32_t base = 0; base < v.tgp; base += 64) {
-      const uint32_t t = base + lane;
-      const double gn = v.g_new[(size_t)j * v.tgp + t], go = v.gest[(size_t)p * v.tgp + t];
-      const double d = gn - go, sm = gn + go;
+    for (int c = 0; c < NCLS; ++c) zd[c] = 0;
+    for (uint32_t base = 0; base < v.tp; base += 128) {
+      const uint32_t t = base + 2 * lane;
+      const uint32_t cn = *(const uint32_t*)(v.c_new + tix(j, t, v.pc));
+      const uint32_t co = *(const uint32_t*)(v.cnt + tix(p, t, P));
+      const int n0 = (int)(cn & 0xFFFFu), n1 = (int)(cn >> 16);
+      const int o0 = (int)(co & 0xFFFFu), o1 = (int)(co >> 16);
+      const int dc0 = n0 - o0, dc1 = n1 - o1;
+      const uint32_t dcp = ((uint32_t)dc0 & 0xFFFFu) | ((uint32_t)dc1 << 16);
+      z0 += (long long)(dc0 * (n0 + o0) + dc1 * (n1 + o1));
 #pragma unroll
       for (int mm = 0; mm < W.M; ++mm) {
         const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
-        cs[W.cls[mm]] += d * (sm - 2.0 * (double)v.gest[(size_t)q * v.tgp + t]);
+        zd[W.cls[mm]] += dot2(dcp, *(const uint32_t*)(v.cnt + tix(q, t, P)), 0);
       }
     }
-    double ga = 0.0;
+    double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < NCLS; ++c) {
-      double xv = cs[c];
+      long long xv = (long long)W.csize[c] * z0 - 2 * zd[c];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
-      ga += v.wd[c] * xv;
+      acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)xv));
     }
-    total = __dadd_rn(total, 2.0 * ga);
-  }
-  if (lane == 0) {
-    const bool ok = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
-    v.delta[j] = total;
-    if (!ok) {
-      v.accept[j] = 0;
-      atomicAdd(&v.ctr[2], 1ull);
+    double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+    if (v.tgp) {
+      double cs[NCLS];
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) cs[c] = 0.0;
+      for (uint32_t base = 0; base < v.tgp; base += 64) {
+        const uint32_t t = base + lane;
+        const double gn = v.g_new[(size_t)j * v.tgp + t], go = v.gest[(size_t)p * v.tgp + t];
+        const double d = gn - go, sm = gn + go;
+#pragma unroll
+        for (int mm = 0; mm < W.M; ++mm) {
+          const uint32_t q = ((y + v.h + W.oy[mm]) % v.h) * v.w + (x + v.w + W.ox[mm]) % v.w;
+          cs[W.cls[mm]] += d * (sm - 2.0 * (double)v.gest[(size_t)q * v.tgp + t]);
+        }
+      }
+      double ga = 0.0;
+#pragma unroll
+      for (int c = 0; c < NCLS; ++c) {
+        double xv = cs[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) xv += __shfl_xor(xv, off);
+        ga += v.wd[c] * xv;
+      }
+      total = __dadd_rn(total, 2.0 * ga);
+    }
+    if (lane == 0) {
+      const bool ok = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
+      v.delta[j] = total;
+      if (!ok) {
+        v.accept[j] = 0;
+        atomicAdd(&v.ctr[2], 1ull);
+      }
     }
   }
 }
@@ -604,7 +611,7 @@ hipError_t bf_launch(const DevView& v, uint32_t kappa, hipStream_t s) {
   e = launch_finish(v, s);
   if (e != hipSuccess) return e;
   if (v.mfma == 1) {
-    hipLaunchKernelGGL((k_delta_refine<R>), dim3((v.pc + 3) / 4), dim3(256), 0, s, v, kappa, v.unsure);
+    hipLaunchKernelGGL((k_delta_refine<R>), dim3((v.pc + 255) / 256), dim3(256), 0, s, v, kappa, v.unsure);
     return hipGetLastError();
   }
   if ((e = launch_stage_exact(v, kappa, s)) != hipSuccess) return e;

@@ -93,6 +93,52 @@ def test_bf16_full_size_first_phase_sampled():
         assert bool(ph["accept"][j]) == bool(d[0] < 0)
 
 
+
+def test_bf16_uncertified_slices_are_rechecked():
+    """Generator (1, 1) puts a pixel's 256 samples on one line, so its counts
+    change a lot between offsets; one colour class and a 64 x 512 tile give
+    512 workgroups, each over all 8192 integrands, so N * sum|dc| passes 2^24
+    for every class pixel and its accepted move goes through the exact
+    integer re-check.  Eight Heavisides repeated 1024 times make the Gram
+    sums grow steadily past 2^24, where FP32 rounds them, so the re-check
+    changes values.  Decisions and accepted energy changes equal the FP32
+    form's (and, for sampled pixels, the oracle's exact value)."""
+    w = workload(n=256, g=(1, 1), t_heaviside=8192, width=64, height=512, radius=1, colour_k=1)
+    inp = synthgen.problem_inputs(w)
+    inp["heaviside"] = {k: np.ascontiguousarray(v[np.arange(8192) % 8]) for k, v in inp["heaviside"].items()}
+    with gpu_problem(w, inp) as p32, gpu_problem(bf16(w), inp) as pbf:
+        for p in (p32, pbf):
+            p.phase_propose(0)
+            p.phase_evaluate(0)
+        a, b = p32.get_phase(), pbf.get_phase()
+        raw = pbf.get_phase_bf16()
+    np.testing.assert_array_equal(a["u_new"], b["u_new"])
+    exact, acc = a["delta"], b["accept"]
+    # the matrix-core values were rounded where slices went uncertified, and
+    # the re-check replaced them for the accepted moves
+    assert np.any(raw[acc] != b["delta"][acc]), "no accepted move was re-checked"
+    np.testing.assert_allclose(b["delta"][acc], exact[acc], rtol=1e-12, atol=0)
+    clear = np.abs(exact) > 1e-6 * np.abs(exact).max()
+    np.testing.assert_array_equal(acc[clear], a["accept"][clear])
+    # sampled pixels against the oracle's exact energy change
+    W, H, T, r = w["width"], w["height"], w["t_heaviside"], w["radius"]
+    u0 = inp["offsets"].reshape(-1, 2).astype(np.int64)
+    ref = oracle_problem(w, inp)
+    local = np.zeros((H, W, T), dtype=np.int16)
+    for j in synthgen.pixel_sample(W * H, 4, seed=9):
+        y, x = int(j) // W, int(j) % W
+        win = [((y + oy) % H, (x + ox) % W) for oy in range(-r, r + 1) for ox in range(-r, r + 1)]
+        ids = np.array([yy * W + xx for yy, xx in win])
+        local[tuple(np.array(win).T)] = estimator.hit_counts(w["n"], w["g"], u0[ids], inp["heaviside"])
+        u_new = osw.proposals(ref, np.array([y]), np.array([x]), 0).astype(np.int64)
+        c_new = estimator.hit_counts(w["n"], w["g"], u_new, inp["heaviside"])
+        d = energy.delta_exact(local, [y], [x], c_new, w["n"], r, w["sigma"])
+        assert exact[j] == pytest.approx(d[0], rel=1e-12)
+        if acc[j]:
+            assert b["delta"][j] == pytest.approx(d[0], rel=1e-12)
+        local[tuple(np.array(win).T)] = 0
+
+
 def test_bf16_energy_of_counts_is_exact():
     w = bf16(EDGE["n256_r4"])
     inp = synthgen.problem_inputs(w)
