@@ -87,7 +87,6 @@ struct BfGeom {
   static constexpr int RUSED = K * (BXC - 1) + 2 * R + 1;
   static constexpr int NT = (RUSED + 15) / 16;               // column tiles
   static constexpr int RCOLS = 16 * NT;
-  static constexpr int NB = BYC * BXC;
   static constexpr int NTH = 64 * BYC;                       // threads
   static constexpr int PLANE = RROWS * RUSED;                // region pixels
   // a plane per tile half, padded to 256 bytes: the four 16-lane groups of a
