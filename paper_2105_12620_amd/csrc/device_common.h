@@ -67,6 +67,23 @@ __device__ inline uint32_t wave_id() {
   return __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
 }
 
+// Workgroup barrier of the kernels that fill LDS with global_load_lds: waits
+// until at most N of this wave's vector-memory loads are in flight (they
+// complete in order, so every earlier one has landed) and its LDS accesses
+// are done, then meets the other waves (a __syncthreads would also wait for
+// the loads still meant to be in flight).  The empty asm statements keep the
+// compiler from moving memory accesses across.  s_waitcnt immediate in the
+// gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt (bits 6:4) left open,
+// lgkmcnt (bits 11:8) zero.
+template <int N>
+__device__ inline void barrier_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8), each
 // with its own L2.  This renumbers them so that every XCD's workgroups form one
 // contiguous range of logical indices: neighbouring work then shares an L2.

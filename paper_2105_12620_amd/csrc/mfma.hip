@@ -107,13 +107,6 @@ struct BfGeom {
   static constexpr int LDS_BYTES = STAGE_BYTES > EXTRACT_BYTES ? STAGE_BYTES : EXTRACT_BYTES;
 };
 
-// s_waitcnt with vmcnt(n) and lgkmcnt(0), expcnt left open (gfx9 encoding)
-template <int N>
-__device__ inline void bf_wait_vm_lgkm0() {
-  static_assert(N < 64, "vmcnt");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
-}
-
 template <int R, int K, int BYC, int OY0, int NOY>
 __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa, uint32_t trlen,
                                                       long long* __restrict__ xsum, uint32_t* __restrict__ unsure) {
@@ -240,15 +233,6 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
       }
     }
   };
-  // wait until at most N of this wave's loads are in flight and its LDS
-  // accesses are done, then meet the other waves; the empty asm statements
-  // keep the compiler from moving memory accesses across
-  auto sync_vm = [&](auto n) {
-    asm volatile("" ::: "memory");
-    bf_wait_vm_lgkm0<decltype(n)::value>();
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-  };
 
   // Heaviside slices: region words PD slices ahead, change-operand words one
   // slice ahead, all through LDS, so that no register waits on a load.  Each
@@ -263,7 +247,7 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
   }
   for (uint32_t si = 0; si < nsh; ++si) {
     const uint32_t t0 = t_begin + 16 * si;
-    sync_vm(std::integral_constant<int, (G::PD - 1) * G::ITERD>{});
+    barrier_vm<(G::PD - 1) * G::ITERD>();
     const bf16x4 af = operand_h(aring + ((si & 1) * BYC + w) * 128);
     // the slots refilled here were last read by every wave before the barrier
     issue_a(si + 1 < nsh ? t0 + 16 : t_begin, (si + 1) & 1);
@@ -298,7 +282,7 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
       }
     }
     const bf16x4 af = __builtin_bit_cast(bf16x4, make_uint2(bf16x2_bits(f[0], f[1]), bf16x2_bits(f[2], f[3])));
-    sync_vm(std::integral_constant<int, 0>{});
+    barrier_vm<0>();
     mfma_slice(0, af);
     __syncthreads();
   }

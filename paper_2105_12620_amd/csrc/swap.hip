@@ -119,13 +119,6 @@ __device__ inline bool swap_step_offset(int st, int i, int& ox, int& oy) {
   return oy <= R;
 }
 
-// s_waitcnt with vmcnt(n) and lgkmcnt(0), expcnt left open (gfx9 encoding)
-template <int N>
-__device__ inline void wait_vm_lgkm0() {
-  static_assert(N < 64, "vmcnt");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
-}
-
 template <int R>
 __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stage(DevView v, SwapView sv, uint32_t kappa,
                                                                     uint32_t slen, uint32_t gx, uint32_t gy) {
@@ -215,15 +208,6 @@ __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stag
                                        16, 0, 0);
     }
   };
-  // wait until at most N of this wave's loads are in flight and its LDS
-  // accesses are done, then meet the other waves; the empty asm statements
-  // keep the compiler from moving memory accesses across
-  auto sync_vm = [&](auto n) {
-    asm volatile("" ::: "memory");
-    wait_vm_lgkm0<decltype(n)::value>();
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-  };
 
   const uint32_t grp = tid / G::GL, li = tid & 7, lp = (tid >> 3) & 1;
   // word of the lane's slot relative to the member's own word of plane lp:
@@ -264,7 +248,7 @@ __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stag
       for (int st = 0; st < G::STEPS; ++st) acc[s][st] = 0;
     }
     // the previous round's reads of the ring are done
-    sync_vm(std::integral_constant<int, 0>{});
+    barrier_vm<0>();
 #pragma unroll
     for (int k = 0; k < G::PD; ++k)
       if ((uint32_t)k < nst) issue(t_begin + 16 * k, k);
@@ -272,9 +256,9 @@ __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stag
       // stage si has landed once at most the loads of the stages issued
       // after it (up to PD - 1 of them) are in flight
       const uint32_t ahead = min((uint32_t)G::PD - 1, nst - 1 - si);
-      if (G::PD >= 3 && ahead == 2) sync_vm(std::integral_constant<int, 2 * G::D>{});
-      else if (G::PD >= 2 && ahead == 1) sync_vm(std::integral_constant<int, G::D>{});
-      else sync_vm(std::integral_constant<int, 0>{});
+      if (G::PD >= 3 && ahead == 2) barrier_vm<2 * G::D>();
+      else if (G::PD >= 2 && ahead == 1) barrier_vm<G::D>();
+      else barrier_vm<0>();
       if (si + G::PD < nst) issue(t_begin + 16 * (si + G::PD), (si + G::PD) % G::NBUF);
       const u32x4* bf = lds4 + (si % G::NBUF) * G::SBUF;
 #pragma unroll
