@@ -511,8 +511,11 @@ struct ProfMark {
   bn_status s = BN_OK;
   ProfMark(bn_problem p_, std::vector<hipEvent_t>* v_, hipStream_t st_) : p(p_), vec(v_), st(st_) {
     if (!p->profiling) return;
+    // timing-only events: no system-scope fence (cache write-back) when they
+    // are recorded, so they disturb the work around them less
     hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess || hipEventRecord(a, st) != hipSuccess) {
+    if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess || hipEventRecord(a, st) != hipSuccess) {
       s = fail(BN_EHIP, "profiling events");
       return;
     }
