@@ -491,10 +491,10 @@ def main() -> int:
                            "passes": swap["kernels_ms"]["phases"]},
             "evaluate_hbm_gbs": swap_bytes / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9,
             "roofline": roof("hbm", swap_bytes / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e9, "GB/s",
-                             "k_swap_stage + k_swap_finish (one swap pass)",
+                             "k_swap_stage (class sums of one swap pass)",
                              f"tile counts once + {M} partner rows ({T} integrands x 2 B)"),
             "roofline_alu": roof("alu", stencil_lane_ops / (swap["kernels_ms"]["evaluate_per_phase"] * 1e-3) / 1e12,
-                                 "TOP/s", "k_swap_stage + k_swap_finish (one swap pass)",
+                                 "TOP/s", "k_swap_stage (class sums of one swap pass)",
                                  f"{M} members x {win} offsets x {T} integrands / 2 per v_dot2")},
         "batched": None if batch is None else dict(batch, roofline=roof(
             "alu", batch["count_lane_ops_per_sweep"] / (batch["ms_per_sweep"] * 1e-3) / 1e12, "TOP/s",

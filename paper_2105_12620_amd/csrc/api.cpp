@@ -690,14 +690,16 @@ bn_status swap_commit(bn_problem p) {
   return BN_OK;
 }
 
+// A sweep's passes: the class sums of the couples (timed as the evaluation),
+// then their decisions and exchanges in one launch (timed as the commit).
 bn_status record_swap_sweep(bn_problem p) {
   bn_status s;
   for (uint32_t kappa = 0; kappa < p->v.k * p->v.k; ++kappa) {
     ProfMark me(p, &p->prof_eval, p->stream);
-    if ((s = swap_evaluate(p, kappa)) != BN_OK) return s;
+    HIPCHK(launch_swap_evaluate(p->v, p->sv, kappa, p->stream, false));
     if ((s = me.end()) != BN_OK) return s;
     ProfMark mc(p, &p->prof_commit, p->stream);
-    if ((s = swap_commit(p)) != BN_OK) return s;
+    HIPCHK(launch_swap_decide_exchange(p->v, p->sv, kappa, p->stream));
     if ((s = mc.end()) != BN_OK) return s;
   }
   HIPCHK(launch_advance(p->v, p->stream));

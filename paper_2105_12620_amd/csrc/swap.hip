@@ -336,19 +336,19 @@ __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stag
   }
 }
 
-// One thread per couple: add the two members' class sums and the pair
+// Decision of couple i: add the two members' class sums and the pair
 // correction, take the FP64 weighted sum in increasing d and decide; the sums
-// are cleared for the next pass.  All of a couple's sums are loaded before
-// any is cleared, so the loads are in flight together.
+// are cleared for the next pass (all of a couple's sums are loaded before any
+// is cleared, so the loads are in flight together).  Writes delta, accept and
+// the couple's pixels (u_new); returns the decision and the pixels.
 template <int R>
-__global__ __launch_bounds__(128) void k_swap_finish(DevView v, SwapView sv, uint32_t kappa) {
+__device__ __forceinline__ bool swap_decide(const DevView& v, const SwapView& sv, uint32_t kappa, uint32_t i,
+                                            uint32_t& a, uint32_t& b) {
   constexpr int NCLS = WinConst<R>::NCLS;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t half = sv.m >> 1;
-  if (i >= half) return;
   const uint32_t mask = swap_mask(v, kappa);
   const uint32_t L = kappa * sv.m + 2 * i;
-  const uint32_t a = sv.perm[L] ^ mask, b = sv.perm[L + 1] ^ mask;
+  a = sv.perm[L] ^ mask;
+  b = sv.perm[L + 1] ^ mask;
   long long* xp = sv.xs + (size_t)2 * i * NCLS;
   long long x[NCLS];
 #pragma unroll
@@ -379,26 +379,25 @@ __global__ __launch_bounds__(128) void k_swap_finish(DevView v, SwapView sv, uin
 #pragma unroll
   for (int c = 0; c < NCLS; ++c) acc = __dadd_rn(acc, __dmul_rn(v.wd[c], (double)x[c]));
   const double total = __dmul_rn(acc, 2.0 / ((double)v.n * (double)v.n));
+  const bool ok = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
   v.delta[i] = total;
-  v.accept[i] = (v.objective > 0) ? (total < 0.0) : (total > 0.0);
+  v.accept[i] = ok;
   v.u_new[2 * i] = a;
   v.u_new[2 * i + 1] = b;
+  return ok;
 }
 
-// One wave per accepted couple: exchange offsets and count tiles.
-__global__ __launch_bounds__(256) void k_swap_commit(DevView v, SwapView sv) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t i = wave_id();
-  if (i >= (sv.m >> 1) || !v.accept[i]) return;
-  const uint32_t a = v.u_new[2 * i], b = v.u_new[2 * i + 1];
+// Exchange of an accepted couple's offsets and count tiles by one wave: the
+// counts are read from the pixel-major copy (whole lines), written to both
+// layouts.
+__device__ __forceinline__ void swap_exchange(const DevView& v, const SwapView& sv, uint32_t a, uint32_t b,
+                                              uint32_t lane) {
   if (lane == 0) {
     const uint32_t ua = v.U[a], ub = v.U[b];
     v.U[a] = ub;
     v.U[b] = ua;
     atomicAdd(&v.ctr[1], 1ull);
   }
-  // the counts are read from the pixel-major copy (whole lines), written to
-  // both layouts
   const uint32_t P = v.w * v.h;
   uint4* wa = (uint4*)(sv.row + (size_t)a * v.tp);
   uint4* wb = (uint4*)(sv.row + (size_t)b * v.tp);
@@ -409,6 +408,40 @@ __global__ __launch_bounds__(256) void k_swap_commit(DevView v, SwapView sv) {
     *(uint4*)(v.cnt + ((size_t)tt * P + a) * 8) = qb;
     *(uint4*)(v.cnt + ((size_t)tt * P + b) * 8) = qa;
   }
+}
+
+// One thread per couple: the decision alone (the phase-stepping calls).
+template <int R>
+__global__ __launch_bounds__(128) void k_swap_finish(DevView v, SwapView sv, uint32_t kappa) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (sv.m >> 1)) return;
+  uint32_t a, b;
+  (void)swap_decide<R>(v, sv, kappa, i, a, b);
+}
+
+// One wave per couple: decision and, if accepted, the exchange (the sweeps:
+// one launch less per pass, and no round trip of the decision through HBM).
+// Lane 0 decides; the wave then exchanges the couple.
+template <int R>
+__global__ __launch_bounds__(256) void k_swap_decide_exchange(DevView v, SwapView sv, uint32_t kappa) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t i = wave_id();
+  if (i >= (sv.m >> 1)) return;
+  uint32_t a = 0, b = 0, ok = 0;
+  if (lane == 0) ok = swap_decide<R>(v, sv, kappa, i, a, b) ? 1u : 0u;
+  ok = __builtin_amdgcn_readfirstlane(ok);
+  if (!ok) return;
+  a = __builtin_amdgcn_readfirstlane(a);
+  b = __builtin_amdgcn_readfirstlane(b);
+  swap_exchange(v, sv, a, b, lane);
+}
+
+// One wave per accepted couple: exchange offsets and count tiles.
+__global__ __launch_bounds__(256) void k_swap_commit(DevView v, SwapView sv) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t i = wave_id();
+  if (i >= (sv.m >> 1) || !v.accept[i]) return;
+  swap_exchange(v, sv, v.u_new[2 * i], v.u_new[2 * i + 1], lane);
 }
 
 // Pixel-major copy of the tiled counts: thread per (pixel, 8-integrand tile),
@@ -448,7 +481,7 @@ hipError_t prepare_swap_kernels() {
 // 256 CUs, and few enough stages per slice that every per-lane int32 step sum
 // stays below 2^31.
 template <int R>
-hipError_t swap_stage_launch(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
+hipError_t swap_stage_launch(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s, bool decide) {
   using G = SwapGeom<R>;
   const uint32_t gx = (v.w + G::BW - 1) / G::BW, gy = (v.h + G::BH - 1) / G::BH, chunks = v.tp / 16;
   const double n2 = (double)v.n * v.n;
@@ -462,24 +495,36 @@ hipError_t swap_stage_launch(const DevView& v, const SwapView& sv, uint32_t kapp
   hipLaunchKernelGGL(k_swap_stage<R>, dim3(gx * gy * nz), dim3(G::NT), (size_t)G::LDS_BYTES, s, v, sv, kappa,
                      per * 16, gx, gy);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !decide) return e;
   const uint32_t half = sv.m >> 1;
   hipLaunchKernelGGL(k_swap_finish<R>, dim3((half + 127) / 128), dim3(128), 0, s, v, sv, kappa);
   return hipGetLastError();
 }
 
-hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
-  hipError_t e;
+hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s, bool decide) {
   switch (v.radius) {
-    case 1: e = swap_stage_launch<1>(v, sv, kappa, s); break;
-    case 2: e = swap_stage_launch<2>(v, sv, kappa, s); break;
-    case 3: e = swap_stage_launch<3>(v, sv, kappa, s); break;
-    case 4: e = swap_stage_launch<4>(v, sv, kappa, s); break;
-    case 5: e = swap_stage_launch<5>(v, sv, kappa, s); break;
-    case 6: e = swap_stage_launch<6>(v, sv, kappa, s); break;
+    case 1: return swap_stage_launch<1>(v, sv, kappa, s, decide);
+    case 2: return swap_stage_launch<2>(v, sv, kappa, s, decide);
+    case 3: return swap_stage_launch<3>(v, sv, kappa, s, decide);
+    case 4: return swap_stage_launch<4>(v, sv, kappa, s, decide);
+    case 5: return swap_stage_launch<5>(v, sv, kappa, s, decide);
+    case 6: return swap_stage_launch<6>(v, sv, kappa, s, decide);
     default: return hipErrorInvalidValue;
   }
-  return e;
+}
+
+hipError_t launch_swap_decide_exchange(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s) {
+  const dim3 g(((sv.m >> 1) + 3) / 4), b(256);
+  switch (v.radius) {
+    case 1: hipLaunchKernelGGL(k_swap_decide_exchange<1>, g, b, 0, s, v, sv, kappa); break;
+    case 2: hipLaunchKernelGGL(k_swap_decide_exchange<2>, g, b, 0, s, v, sv, kappa); break;
+    case 3: hipLaunchKernelGGL(k_swap_decide_exchange<3>, g, b, 0, s, v, sv, kappa); break;
+    case 4: hipLaunchKernelGGL(k_swap_decide_exchange<4>, g, b, 0, s, v, sv, kappa); break;
+    case 5: hipLaunchKernelGGL(k_swap_decide_exchange<5>, g, b, 0, s, v, sv, kappa); break;
+    case 6: hipLaunchKernelGGL(k_swap_decide_exchange<6>, g, b, 0, s, v, sv, kappa); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_swap_rows(const DevView& v, const SwapView& sv, hipStream_t s) {

@@ -31,7 +31,11 @@ struct SwapView {
 // exchange the accepted couples' offsets and count tiles.
 // Once per process, before the first swap launch (not under stream capture).
 hipError_t prepare_swap_kernels();
-hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s);
+// class sums of the pass's couples (and, with decide, their decisions)
+hipError_t launch_swap_evaluate(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s,
+                                bool decide = true);
+// decisions of the pass's couples and the exchange of the accepted ones
+hipError_t launch_swap_decide_exchange(const DevView& v, const SwapView& sv, uint32_t kappa, hipStream_t s);
 hipError_t launch_swap_commit(const DevView& v, const SwapView& sv, hipStream_t s);
 // Rebuild the pixel-major copy from the tiled counts (after every recount).
 hipError_t launch_swap_rows(const DevView& v, const SwapView& sv, hipStream_t s);
