@@ -15,7 +15,6 @@
 #include <stdint.h>
 
 #include <algorithm>
-#include <type_traits>
 
 #include "bnlat_dev.h"
 #include "device_common.h"
