@@ -181,12 +181,11 @@ __global__ __launch_bounds__(64 * BYC) void k_delta_bf(DevView v, uint32_t kappa
   // (32..63) count words of pixel lane % 16, tile half (lane / 16) % 2;
   // approximate mode: words 64..67 the slice's 16 exact integrals (four
   // lanes' worth, repeated by the others)
-  const uint32_t al = lane & 15, ah = (lane >> 4) & 1;
-  const uint32_t a_j = (own_a < v.ch && b0 + al < v.cw) ? own_a * v.cw + b0 + al : 0;
-  const uint32_t a_p = (own_a < v.ch && b0 + al < v.cw) ? (ky + K * own_a) * v.w + (kx + K * (b0 + al)) : 0;
+  // (the lane's pixel is its own class pixel; lanes without one read row 0)
+  const uint32_t ah = (lane >> 4) & 1;
   auto issue_a = [&](uint32_t t0, uint32_t buf) {
     uint4* dst = aring + (buf * BYC + w) * 128;
-    const uint16_t* s = lane < 32 ? v.c_new + tix(a_j, t0 + 8 * ah, v.pc) : v.cnt + tix(a_p, t0 + 8 * ah, P);
+    const uint16_t* s = lane < 32 ? v.c_new + tix(own_j, t0 + 8 * ah, v.pc) : v.cnt + tix(own_p, t0 + 8 * ah, P);
     __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)s,
                                      (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
     if (approx)
