@@ -172,7 +172,9 @@ def test_full_size_tile256_sweeps_sampled():
     graph-replayed overlapped sweeps with the capped sweep-wide recount):
     every sampled pixel's offset is its initial one or the oracle's proposal
     for one of the two sweeps, its counts are the oracle's estimator at that
-    offset, and the energy fell."""
+    offset, the energy fell, and the energy equals the oracle's exact energy
+    of the exported counts (Eq. (1) in exact integers per distance class,
+    summed over 128-integrand slices, about a minute of CPU)."""
     w = workload("tile256_n256_t1024")
     inp = synthgen.problem_inputs(w)
     W = w["width"]
@@ -194,6 +196,10 @@ def test_full_size_tile256_sweeps_sampled():
         assert (np.array_equal(u[q], u0[q]) or np.array_equal(u[q], props[0][i])
                 or np.array_equal(u[q], props[1][i])), q
     np.testing.assert_array_equal(c[sample], estimator.hit_counts(w["n"], w["g"], u[sample], inp["heaviside"]))
+    c3 = c.reshape(w["height"], W, -1)
+    xd = sum(energy.energy_class_sums(c3[:, :, t:t + 128], w["radius"]) for t in range(0, c3.shape[2], 128))
+    e_ref = float(energy.weighted_class_sum(xd, w["radius"], w["sigma"])) / (w["n"] * w["n"])
+    assert e2 == pytest.approx(e_ref, rel=1e-12)
 
 
 def test_rerun_and_resume_are_bit_identical():
