@@ -172,9 +172,9 @@ def test_full_size_tile256_sweeps_sampled():
     graph-replayed overlapped sweeps with the capped sweep-wide recount):
     every sampled pixel's offset is its initial one or the oracle's proposal
     for one of the two sweeps, its counts are the oracle's estimator at that
-    offset, the energy fell, and the energy equals the oracle's exact energy
-    of the exported counts (Eq. (1) in exact integers per distance class,
-    summed over 128-integrand slices, about a minute of CPU)."""
+    offset, the energy fell, and the energy and the blur criterion equal the
+    oracle's from all exported counts (Eq. (1) in exact integers per distance
+    class, summed over 128-integrand slices; Q at sigma_b = 4)."""
     w = workload("tile256_n256_t1024")
     inp = synthgen.problem_inputs(w)
     W = w["width"]
@@ -186,6 +186,7 @@ def test_full_size_tile256_sweeps_sampled():
         u = p.get_offsets().reshape(-1, 2).astype(np.int64)
         c = p.get_counts()
         e2 = p.energy()
+        q2 = p.quality_metric([4.0])
     assert e2 < e0
     moved = np.any(u != u0, axis=1)
     assert 0.01 < moved.mean() < 0.99
@@ -200,6 +201,9 @@ def test_full_size_tile256_sweeps_sampled():
     xd = sum(energy.energy_class_sums(c3[:, :, t:t + 128], w["radius"]) for t in range(0, c3.shape[2], 128))
     e_ref = float(energy.weighted_class_sum(xd, w["radius"], w["sigma"])) / (w["n"] * w["n"])
     assert e2 == pytest.approx(e_ref, rel=1e-12)
+    # the blur criterion at sigma_b = 4 from the same counts
+    np.testing.assert_allclose(q2, quality.quality(estimator.errors_from_counts(c3, w["n"], ref.areas), [4.0]),
+                               rtol=1e-5)
 
 
 def test_rerun_and_resume_are_bit_identical():
