@@ -139,6 +139,35 @@ def test_full_size_tile256_swap_sampled():
         assert bool(got["accept"][i]) == bool(d > 0)
 
 
+
+def test_full_size_tile256_swap_sweeps():
+    """256x256 tile, N=256, T=1024, 9x9 window, two graph-replayed swap
+    sweeps (ascent): the offsets are a permutation of the initial ones, the
+    counts of sampled pixels are the oracle's estimator at their offsets, and
+    the energy rose and equals the oracle's exact energy of all exported
+    counts."""
+    w = workload("tile256_n256_t1024", move=1, objective=-1)
+    inp = synthgen.problem_inputs(w)
+    W, H = w["width"], w["height"]
+    u0 = inp["offsets"].reshape(-1, 2).astype(np.int64)
+    with gpu_problem(w, inp) as p:
+        e0 = p.energy()
+        stats = p.sweep(2, stats=True)
+        u = p.get_offsets().reshape(-1, 2).astype(np.int64)
+        c = p.get_counts()
+        e2 = p.energy()
+    assert stats["accepts"] > 0 and e2 > e0
+    key = lambda v: np.sort(v[:, 0] * 65536 + v[:, 1])
+    np.testing.assert_array_equal(key(u), key(u0))
+    assert np.any(u != u0)
+    sample = synthgen.pixel_sample(W * H, 64, seed=6)
+    np.testing.assert_array_equal(c[sample], estimator.hit_counts(w["n"], w["g"], u[sample], inp["heaviside"]))
+    c3 = c.reshape(H, W, -1)
+    xd = sum(energy.energy_class_sums(c3[:, :, t:t + 128], w["radius"]) for t in range(0, c3.shape[2], 128))
+    e_ref = float(energy.weighted_class_sum(xd, w["radius"], w["sigma"])) / (w["n"] * w["n"])
+    assert e2 == pytest.approx(e_ref, rel=1e-12)
+
+
 def test_swap_call_order():
     w = SWAP["n16"]
     inp = synthgen.problem_inputs(w)
