@@ -94,6 +94,30 @@ def test_bf16_full_size_first_phase_sampled():
 
 
 
+
+def test_bf16_full_size_sweeps_equal_fp32():
+    """256x256, N=256, T=1024, 9x9: two graph-replayed sweeps of the exact
+    BF16 form, with the matrix-core pass beside the capped sweep-wide recount,
+    reach the FP32 form's offsets and counts bit for bit, and the energy is
+    the oracle's exact energy of all exported counts."""
+    w = workload("tile256_n256_t1024")
+    inp = synthgen.problem_inputs(w)
+    out = []
+    for form in (w, bf16(w)):
+        with gpu_problem(form, inp) as p:
+            st = p.sweep(2, stats=True)
+            out.append((p.get_offsets(), p.get_counts(), p.energy(), st))
+    (u32, c32, e32, s32), (ubf, cbf, ebf, sbf) = out
+    assert sbf["bf16_vetoes"] == 0 and sbf["accepts"] == s32["accepts"] > 0
+    np.testing.assert_array_equal(ubf, u32)
+    np.testing.assert_array_equal(cbf, c32)
+    assert ebf == e32
+    c3 = cbf.reshape(w["height"], w["width"], -1)
+    xd = sum(energy.energy_class_sums(c3[:, :, t:t + 128], w["radius"]) for t in range(0, c3.shape[2], 128))
+    e_ref = float(energy.weighted_class_sum(xd, w["radius"], w["sigma"])) / (w["n"] * w["n"])
+    assert ebf == pytest.approx(e_ref, rel=1e-12)
+
+
 def test_bf16_uncertified_slices_are_rechecked():
     """Generator (1, 1) puts a pixel's 256 samples on one line, so its counts
     change a lot between offsets; one colour class and a 64 x 512 tile give
