@@ -214,6 +214,10 @@ __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stag
   // repeat its last offset)
   const uint32_t lr = min(li, (uint32_t)G::RC - 1), lc = li * G::RWP,
                  lcl = min(li, (uint32_t)G::LASTROWS - 1) * G::RWP;
+  // the same shifted so that every step reads at a non-negative constant
+  // offset, and the partner word of the group's first slot
+  const uint32_t rof = lr - (R * G::RWP + R), cof = lc - (R * G::RWP + R - G::RC),
+                 clof = lcl - (R * G::RWP + R - G::RC), pe0 = 2 * G::PLANE + 2 * grp + lp;
   const uint32_t t_begin = bz * slen, t_end = min(t_begin + slen, v.tp);
   const uint32_t nst = t_end > t_begin ? (t_end - t_begin) / 16 : 0;
   __syncthreads();
@@ -228,20 +232,16 @@ __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stag
     }
     int acc[G::SLOTS][G::STEPS];
     int dd[G::SLOTS];
-    // per slot: the member's own word of plane lp, its partner word, and the
-    // bases of the row steps, the column steps and a column's last step,
-    // shifted so that every step reads at a non-negative constant offset
-    uint32_t sp[G::SLOTS], pe[G::SLOTS], rb[G::SLOTS], cb[G::SLOTS], cbl[G::SLOTS];
+    // per slot: the member's own word of plane lp; the lane's reads are at
+    // fixed offsets from it (one register per slot rather than one per step
+    // kind: fewer spills at radius 4)
+    uint32_t sp[G::SLOTS];
     bool ok[G::SLOTS];
 #pragma unroll
     for (int s = 0; s < G::SLOTS; ++s) {
       const uint32_t mi = grp + G::GROUPS * s;
       ok[s] = base + mi < nm;
       sp[s] = lp * G::PLANE + (ok[s] ? mpos[base + mi] : (uint32_t)(R * G::RWP + R));
-      pe[s] = 2 * G::PLANE + 2 * mi + lp;
-      rb[s] = sp[s] + lr - (R * G::RWP + R);
-      cb[s] = sp[s] + lc - (R * G::RWP + R - G::RC);
-      cbl[s] = sp[s] + lcl - (R * G::RWP + R - G::RC);
       dd[s] = 0;
 #pragma unroll
       for (int st = 0; st < G::STEPS; ++st) acc[s][st] = 0;
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stag
 #pragma unroll
       for (int s = 0; s < G::SLOTS; ++s) {
         if (ok[s]) {
-          const u32x4 own = bf[sp[s]], pc = bf[pe[s]];
+          const u32x4 own = bf[sp[s]], pc = bf[pe0 + 2 * G::GROUPS * s];
           uint32_t dl[4];
 #pragma unroll
           for (int h = 0; h < 4; ++h) {
@@ -275,9 +275,9 @@ __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stag
                                                          __builtin_bit_cast(v2i16, ow_h)));
             dd[s] = dot2(dl[h], dl[h], dd[s]);
           }
-          const u32x4* rp = bf + rb[s];
-          const u32x4* cp = bf + cb[s];
-          const u32x4* clp = bf + cbl[s];
+          const u32x4* rp = bf + (sp[s] + rof);
+          const u32x4* cp = bf + (sp[s] + cof);
+          const u32x4* clp = bf + (sp[s] + clof);
 #pragma unroll
           for (int st = 0; st < G::STEPS; ++st) {
             u32x4 c;
