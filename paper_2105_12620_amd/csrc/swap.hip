@@ -226,8 +226,12 @@ __global__ __launch_bounds__(SwapGeom<R>::NT, (R <= 4) ? 4 : 2) void k_swap_stag
 #pragma unroll
     for (int k = 0; k < G::D; ++k) {
       if (ldst[k] >= 2u * G::PLANE) {
-        const uint32_t e = ldst[k] - 2 * G::PLANE + lane, m = base + (e >> 1);
-        lsrc[k] = (m < nm ? mb[m] : 0) * 2 + (e & 1);
+        // partner word 2 base + e of the round (its member and plane), with
+        // the wave-uniform part summed first: kept per load across rounds,
+        // the lane parts spilled at radius 4
+        const uint32_t e2 = __builtin_amdgcn_readfirstlane(2 * base + ldst[k] - 2 * G::PLANE) + lane,
+                       m = e2 >> 1;
+        lsrc[k] = (m < nm ? mb[m] : 0) * 2 + (e2 & 1);
       }
     }
     int acc[G::SLOTS][G::STEPS];
