@@ -231,7 +231,7 @@ struct bn_problem_s {
   bool sets_ready = false;
   uint64_t prefetched = ~0ull;
   hipStream_t aux = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   hipGraph_t pair_graph = nullptr;
   hipGraphExec_t pair_exec = nullptr;
   bool pair_failed = false;
@@ -485,6 +485,16 @@ DevView sweep_view(bn_problem p, int b) {
   return v;
 }
 
+// The recount of the single-problem overlapped schedule reads its own sweep
+// index, counter word 3, kept one past the sweep counter by the schedule:
+// it then waits on the main stream only for the phases that last read its
+// proposal set, not for the advance of the sweep counter.
+DevView recount_view(bn_problem p, int b) {
+  DevView v = sweep_view(p, b);
+  v.ctr = p->v.ctr + 3;
+  return v;
+}
+
 bn_status ensure_sweep_sets(bn_problem p) {
   if (p->sets_ready) return BN_OK;
   const size_t P = (size_t)p->v.w * p->v.h;
@@ -529,8 +539,8 @@ struct ProfMark {
   }
 };
 
-bn_status record_proposals(bn_problem p, int b, uint32_t ahead, hipStream_t st) {
-  const DevView v = sweep_view(p, b);
+bn_status record_proposals(bn_problem p, int b, uint32_t ahead, hipStream_t st, bool own_index = false) {
+  const DevView v = own_index ? recount_view(p, b) : sweep_view(p, b);
   const uint32_t P = v.w * v.h;
   ProfMark m(p, &p->prof_recount, st);
   HIPCHK(launch_count(v, MODE_SWEEP, ahead, P, st));
@@ -560,7 +570,8 @@ bn_status record_phases(bn_problem p, int b) {
 // the current one: [recount(s+1) -> set 1 || phases(s) from set 0], join,
 // advance, [recount(s+2) -> set 0 || phases(s+1) from set 1], join, advance.
 // The sweep counter only moves after a join, so every recount reads a stable
-// index.  Set 0 holds the current sweep's proposals before and after.
+// index.  Set 0 holds the current sweep's proposals before and after.  (The
+// batch's ungrouped members; a single problem chains its recounts, below.)
 bn_status record_pair(bn_problem p) {
   bn_status s;
   for (int half = 0; half < 2; ++half) {
@@ -576,10 +587,41 @@ bn_status record_pair(bn_problem p) {
   return BN_OK;
 }
 
+// The single problem's two sweeps, chained: the same halves, but each
+// recount reads the recount index (advanced on the auxiliary stream after
+// it) and waits only for the phases that last read its set: those of the
+// first half for the second recount; for the first, those of the previous
+// pair's second half, or, at the start of a captured pair or of a call
+// (`fork`), everything before on the main stream.  The phases of a sweep are
+// done long before the recount beside them, so the auxiliary stream counts
+// back to back; the main stream still joins each recount before its advance.
+bn_status record_pair_chained(bn_problem p, bool fork) {
+  bn_status s;
+  for (int half = 0; half < 2; ++half) {
+    const int cur = half, nxt = 1 - half;
+    if (half == 1) {
+      HIPCHK(hipStreamWaitEvent(p->aux, p->ev[2], 0));
+    } else if (fork) {
+      HIPCHK(hipEventRecord(p->ev[0], p->stream));
+      HIPCHK(hipStreamWaitEvent(p->aux, p->ev[0], 0));
+    } else {
+      HIPCHK(hipStreamWaitEvent(p->aux, p->ev[4], 0));
+    }
+    if ((s = record_proposals(p, nxt, 0, p->aux, true)) != BN_OK) return s;
+    HIPCHK(launch_advance(recount_view(p, nxt), p->aux));
+    HIPCHK(hipEventRecord(p->ev[2 * half + 1], p->aux));
+    if ((s = record_phases(p, cur)) != BN_OK) return s;
+    HIPCHK(hipEventRecord(p->ev[half == 0 ? 2 : 4], p->stream));
+    HIPCHK(hipStreamWaitEvent(p->stream, p->ev[2 * half + 1], 0));
+    HIPCHK(launch_advance(p->v, p->stream));
+  }
+  return BN_OK;
+}
+
 bn_status build_pair_graph(bn_problem p) {
   if (p->pair_exec || p->pair_failed) return BN_OK;
   HIPCHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-  bn_status s = record_pair(p);
+  bn_status s = record_pair_chained(p, true);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(p->stream, &g);
   if (s != BN_OK) {
@@ -612,11 +654,14 @@ bn_status overlapped_sweeps(bn_problem p, uint32_t k) {
     p->prefetched = p->sweep;
   }
   if (k >= 2 && !p->profiling && (s = build_pair_graph(p)) != BN_OK) return s;
+  // the recount index one past the sweep counter, which other calls may have
+  // moved
+  if (k >= 2) HIPCHK(launch_recount_index(p->v, p->stream));
   uint32_t done = 0;
   while (k - done >= 2) {
     if (p->pair_exec && !p->profiling) {
       HIPCHK(hipGraphLaunch(p->pair_exec, p->stream));
-    } else if ((s = record_pair(p)) != BN_OK) {
+    } else if ((s = record_pair_chained(p, done == 0)) != BN_OK) {
       return s;
     }
     done += 2;

@@ -42,7 +42,8 @@ struct DevView {
   double* delta;             // [M] energy change
   uint8_t* accept;           // [M] decision
   const uint32_t* pix_list;  // [M] pixels (list mode)
-  unsigned long long* ctr;   // [0] sweep index, [1] accepted total, [2] BF16 vetoes
+  unsigned long long* ctr;   // [0] sweep index, [1] accepted total, [2] BF16 vetoes,
+                             // [3] the overlapped schedule's recount index
   long long* xpart;          // [ncls][pc] integer class sums of the staged evaluation (kept zero between phases)
   uint32_t* unsure;          // [pc] matrix-core results not certified exact (kept zero between phases)
   uint32_t mfma;             // colour phases' evaluation: 0 FP32 form (exact integer stencil), 1 BF16 matrix
@@ -73,6 +74,7 @@ hipError_t launch_commit(const DevView& v, uint32_t kappa, hipStream_t s);
 uint32_t commit_blocks(const DevView& v);
 hipError_t launch_errors(const DevView& v, hipStream_t s);
 hipError_t launch_advance(const DevView& v, hipStream_t s);
+hipError_t launch_recount_index(const DevView& v, hipStream_t s);
 hipError_t launch_points(const DevView& v, uint32_t pixel, uint32_t* out, hipStream_t s);
 hipError_t launch_energy(const DevView& v, unsigned long long* y, hipStream_t s);
 hipError_t launch_blur(const DevView& v, const float* field, uint32_t pitch, uint32_t valid, const float* kx,

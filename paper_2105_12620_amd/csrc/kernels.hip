@@ -418,6 +418,12 @@ __global__ void k_advance(unsigned long long* ctr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&ctr[0], 1ull);
 }
 
+// The overlapped schedule's recount index (counter word 3) one past the sweep
+// counter.
+__global__ void k_recount_index(unsigned long long* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctr[3] = ctr[0] + 1ull;
+}
+
 __global__ void k_advance_batch(const DevView* __restrict__ views, uint32_t nmem) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nmem) atomicAdd(&views[i].ctr[0], 1ull);
@@ -938,6 +944,11 @@ hipError_t launch_errors(const DevView& v, hipStream_t s) {
 
 hipError_t launch_advance(const DevView& v, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, v.ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_recount_index(const DevView& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_recount_index, dim3(1), dim3(64), 0, s, v.ctr);
   return hipGetLastError();
 }
 
