@@ -272,6 +272,35 @@ def test_profiled_and_mixed_schedules_agree():
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_profiled_pairs_chain_recounts(precision):
+    """Three eager overlapped pairs in one call (kernel profiling on): every
+    recount reads the recount index, and the first recount of the second and
+    third pairs waits only for the previous pair's last phases.  The offsets
+    and counts equal the oracle's after the six sweeps, and a graph-replayed
+    call (the index set again from the sweep counter) continues the oracle's
+    trajectory."""
+    w = dict(EDGE["n256_r4"], precision=precision)
+    inp = synthgen.problem_inputs(w)
+    ref = oracle_problem(w, inp)
+    st = osw.initial_state(ref, inp["offsets"])
+    osw.run(ref, st, 6)
+    u6, c6 = st.u.copy(), st.c.reshape(-1, w["t_heaviside"]).copy()
+    osw.run(ref, st, 4)
+    with gpu_problem(w, inp) as p:
+        p.set_profiling(True)
+        p.sweep(6)
+        prof = p.get_profile()
+        assert prof["recount_launches"] >= 6 and prof["phases"] == 24
+        p.set_profiling(False)
+        np.testing.assert_array_equal(p.get_offsets(), u6)
+        np.testing.assert_array_equal(p.get_counts(), c6)
+        p.sweep(4)
+        np.testing.assert_array_equal(p.get_offsets(), st.u)
+        np.testing.assert_array_equal(p.get_counts(), st.c.reshape(-1, w["t_heaviside"]))
+        assert p.get_sweep_index() == 10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_recount_cap_does_not_change_results(precision):
     """The sweep-wide recount with a workgroup cap (workgroups striding over
     the work) gives the oracle's trajectory for any cap, before and after the
