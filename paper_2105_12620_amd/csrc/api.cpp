@@ -593,8 +593,9 @@ bn_status record_pair(bn_problem p) {
 // first half for the second recount; for the first, those of the previous
 // pair's second half, or, at the start of a captured pair or of a call
 // (`fork`), everything before on the main stream.  The phases of a sweep are
-// done long before the recount beside them, so the auxiliary stream counts
-// back to back; the main stream still joins each recount before its advance.
+// done long before the recount beside them, so a recount does not wait for
+// the join and advance after the previous one; the main stream still joins
+// each recount before its advance.
 bn_status record_pair_chained(bn_problem p, bool fork) {
   bn_status s;
   for (int half = 0; half < 2; ++half) {
