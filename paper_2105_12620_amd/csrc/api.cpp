@@ -587,9 +587,10 @@ bn_status record_pair(bn_problem p) {
   return BN_OK;
 }
 
-// The single problem's two sweeps, chained: the same halves, but each
-// recount reads the recount index (advanced on the auxiliary stream after
-// it) and waits only for the phases that last read its set: those of the
+// The single problem's two sweeps, chained: the same halves, but the
+// recounts read the recount index, the second half's one past it (the index
+// advances by two on the auxiliary stream after the pair's second recount),
+// and each waits only for the phases that last read its set: those of the
 // first half for the second recount; for the first, those of the previous
 // pair's second half, or, at the start of a captured pair or of a call
 // (`fork`), everything before on the main stream.  The phases of a sweep are
@@ -608,8 +609,8 @@ bn_status record_pair_chained(bn_problem p, bool fork) {
     } else {
       HIPCHK(hipStreamWaitEvent(p->aux, p->ev[4], 0));
     }
-    if ((s = record_proposals(p, nxt, 0, p->aux, true)) != BN_OK) return s;
-    HIPCHK(launch_advance(recount_view(p, nxt), p->aux));
+    if ((s = record_proposals(p, nxt, (uint32_t)half, p->aux, true)) != BN_OK) return s;
+    if (half == 1) HIPCHK(launch_recount_advance_pair(p->v, p->aux));
     HIPCHK(hipEventRecord(p->ev[2 * half + 1], p->aux));
     if ((s = record_phases(p, cur)) != BN_OK) return s;
     HIPCHK(hipEventRecord(p->ev[half == 0 ? 2 : 4], p->stream));

@@ -75,6 +75,7 @@ uint32_t commit_blocks(const DevView& v);
 hipError_t launch_errors(const DevView& v, hipStream_t s);
 hipError_t launch_advance(const DevView& v, hipStream_t s);
 hipError_t launch_recount_index(const DevView& v, hipStream_t s);
+hipError_t launch_recount_advance_pair(const DevView& v, hipStream_t s);
 hipError_t launch_points(const DevView& v, uint32_t pixel, uint32_t* out, hipStream_t s);
 hipError_t launch_energy(const DevView& v, unsigned long long* y, hipStream_t s);
 hipError_t launch_blur(const DevView& v, const float* field, uint32_t pitch, uint32_t valid, const float* kx,

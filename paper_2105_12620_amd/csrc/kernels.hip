@@ -419,9 +419,13 @@ __global__ void k_advance(unsigned long long* ctr) {
 }
 
 // The overlapped schedule's recount index (counter word 3) one past the sweep
-// counter.
+// counter, and its advance by a pair of sweeps.
 __global__ void k_recount_index(unsigned long long* ctr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ctr[3] = ctr[0] + 1ull;
+}
+
+__global__ void k_recount_advance_pair(unsigned long long* ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctr[3] += 2ull;
 }
 
 __global__ void k_advance_batch(const DevView* __restrict__ views, uint32_t nmem) {
@@ -949,6 +953,11 @@ hipError_t launch_advance(const DevView& v, hipStream_t s) {
 
 hipError_t launch_recount_index(const DevView& v, hipStream_t s) {
   hipLaunchKernelGGL(k_recount_index, dim3(1), dim3(64), 0, s, v.ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_recount_advance_pair(const DevView& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_recount_advance_pair, dim3(1), dim3(64), 0, s, v.ctr);
   return hipGetLastError();
 }
 
